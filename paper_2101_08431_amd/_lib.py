@@ -1,0 +1,249 @@
+"""ctypes binding of the C ABI in include/nmf.h (argument marshalling only).
+
+Every step of the factorisation runs in the HIP library libnmf_hip.so; this
+module only passes pointers and sizes.  PyTorch provides the device workspace
+and the stream.  Importing works without a GPU; using a context needs one.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnmf_hip.so")
+
+NMF_OK, NMF_CONVERGED = 0, 1
+NMF_EINVAL, NMF_ENOMEM, NMF_EDEVICE, NMF_ENOTCONV = -1, -2, -3, -4
+NMF_ESINGULAR, NMF_ESTATE, NMF_ECAPACITY = -5, -6, -7
+GRAM_FP64, GRAM_FP32, GRAM_BF16X2 = 0, 1, 2
+
+# Every symbol include/nmf.h declares.
+EXPORTS = [
+    "nmf_default_options", "nmf_workspace_bytes", "nmf_create", "nmf_anls_step", "nmf_ipm_step",
+    "nmf_solve", "nmf_append_columns", "nmf_get_factors", "nmf_get_masks", "nmf_get_report",
+    "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
+]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("eps_tol", ctypes.c_double), ("eps_stol", ctypes.c_double), ("tau", ctypes.c_double),
+        ("eta", ctypes.c_double), ("sigma_c", ctypes.c_double), ("rho0_factor", ctypes.c_double),
+        ("rho", ctypes.c_double),
+        ("inner_cap", ctypes.c_int32), ("exact_hessian_switch", ctypes.c_int32),
+        ("max_anls_sweeps", ctypes.c_int32), ("max_ipm_iters", ctypes.c_int32),
+        ("max_backtracks", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("gram_precision", ctypes.c_int32), ("with_ipm", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("f", ctypes.c_double), ("E0", ctypes.c_double), ("Emu", ctypes.c_double),
+        ("mu", ctypes.c_double), ("sigma", ctypes.c_double), ("step_rel", ctypes.c_double),
+        ("stage", ctypes.c_int32), ("flag", ctypes.c_int32),
+        ("sweeps", ctypes.c_int64), ("ipm_iters", ctypes.c_int64), ("ipm_outer", ctypes.c_int64),
+        ("backtracks", ctypes.c_int64), ("nnls_solves", ctypes.c_int64), ("nnls_failed", ctypes.c_int64),
+        ("mask_changes", ctypes.c_int64), ("exact_steps", ctypes.c_int64), ("fallbacks", ctypes.c_int64),
+        ("ms_stage1", ctypes.c_double), ("ms_stage2", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libnmf_hip.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH} (run paper_2101_08431_amd.build.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.nmf_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.nmf_default_options.restype = None
+    L.nmf_workspace_bytes.argtypes = [i64, i64, i32, ctypes.POINTER(Options)]
+    L.nmf_workspace_bytes.restype = ctypes.c_size_t
+    L.nmf_create.argtypes = [vp, i64, i64, i64, i32, i64, vp, vp, ctypes.POINTER(Options), vp,
+                             ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.nmf_create.restype = ctypes.c_int
+    for name in ("nmf_anls_step", "nmf_ipm_step"):
+        getattr(L, name).argtypes = [vp, i32, ctypes.POINTER(Report)]
+        getattr(L, name).restype = ctypes.c_int
+    L.nmf_solve.argtypes = [vp, ctypes.POINTER(Report)]
+    L.nmf_solve.restype = ctypes.c_int
+    L.nmf_append_columns.argtypes = [vp, vp, i64, i64]
+    L.nmf_append_columns.restype = ctypes.c_int
+    L.nmf_get_factors.argtypes = [vp, vp, vp]
+    L.nmf_get_factors.restype = ctypes.c_int
+    L.nmf_get_masks.argtypes = [vp, vp, vp]
+    L.nmf_get_masks.restype = ctypes.c_int
+    L.nmf_get_report.argtypes = [vp, ctypes.POINTER(Report)]
+    L.nmf_get_report.restype = ctypes.c_int
+    L.nmf_anls_profile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.nmf_anls_profile.restype = ctypes.c_int
+    L.nmf_get_shape.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.nmf_get_shape.restype = ctypes.c_int
+    L.nmf_destroy.argtypes = [vp]
+    L.nmf_destroy.restype = ctypes.c_int
+    L.nmf_last_error.argtypes = [vp]
+    L.nmf_last_error.restype = ctypes.c_char_p
+    L.nmf_status_string.argtypes = [ctypes.c_int]
+    L.nmf_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def default_options(**kw):
+    o = Options()
+    load().nmf_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def workspace_bytes(n, m_capacity, k, opts=None):
+    o = opts if opts is not None else default_options()
+    return int(load().nmf_workspace_bytes(int(n), int(m_capacity), int(k), ctypes.byref(o)))
+
+
+class NMFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{load().nmf_status_string(status).decode()}: {msg}")
+        self.status = status
+
+
+def _ptr(a):
+    """Device or host address of a torch tensor or numpy array (contiguous)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr())
+    if not a.flags["C_CONTIGUOUS"] and not a.flags["F_CONTIGUOUS"]:
+        raise ValueError("array must be contiguous")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class NMF:
+    """One streaming factorisation living in a device workspace.
+
+    M: (n, m) float64, column-major host array (numpy, Fortran order) or a
+    torch tensor of shape (m, n) on the GPU (its rows are the columns of M).
+    X0: (n, k) row-major; Y0: (k, m) row-major; numpy or torch (host or GPU).
+    """
+
+    def __init__(self, M, k, X0=None, Y0=None, m_capacity=None, options=None, stream=None, device=None):
+        import torch
+        L = load()
+        self._torch = torch
+        if hasattr(M, "data_ptr"):
+            m, n = M.shape
+            Mptr, ldm = _ptr(M), n
+        else:
+            n, m = M.shape
+            if not M.flags["F_CONTIGUOUS"]:
+                raise ValueError("host M must be column-major (numpy Fortran order)")
+            Mptr, ldm = _ptr(M), n
+        self._keep = [M, X0, Y0]
+        self.options = options if options is not None else default_options()
+        cap = int(m_capacity) if m_capacity is not None else int(m)
+        nbytes = workspace_bytes(n, cap, k, self.options)
+        if nbytes == 0:
+            raise NMFError(NMF_EINVAL, "invalid sizes")
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        out = ctypes.c_void_p()
+        st = L.nmf_create(Mptr, n, m, ldm, int(k), cap, _ptr(X0), _ptr(Y0), ctypes.byref(self.options),
+                          ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(out))
+        if st != NMF_OK:
+            raise NMFError(st, L.nmf_last_error(None).decode())
+        self._ctx = out
+        self.n, self.k = int(n), int(k)
+
+    # -- helpers
+    def _check(self, st, ok=(NMF_OK, NMF_CONVERGED, NMF_ENOTCONV)):
+        if st not in ok:
+            raise NMFError(st, load().nmf_last_error(self._ctx).decode())
+        return st
+
+    @property
+    def m(self):
+        n, m, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        load().nmf_get_shape(self._ctx, ctypes.byref(n), ctypes.byref(m), ctypes.byref(k))
+        return int(m.value)
+
+    def anls_step(self, sweeps, report=True):
+        r = Report() if report else None
+        st = self._check(load().nmf_anls_step(self._ctx, int(sweeps), ctypes.byref(r) if r else None))
+        return (st, r.as_dict()) if r is not None else st
+
+    def ipm_step(self, iters, report=True):
+        r = Report() if report else None
+        st = self._check(load().nmf_ipm_step(self._ctx, int(iters), ctypes.byref(r) if r else None))
+        return (st, r.as_dict()) if r is not None else st
+
+    def anls_profile(self, sweeps):
+        """Mean device ms of the X-half and Y-half kernels over `sweeps` sweeps."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(load().nmf_anls_profile(self._ctx, int(sweeps), ctypes.byref(a), ctypes.byref(b)),
+                    ok=(NMF_OK,))
+        return a.value, b.value
+
+    def solve(self):
+        r = Report()
+        st = self._check(load().nmf_solve(self._ctx, ctypes.byref(r)))
+        return st, r.as_dict()
+
+    def report(self):
+        r = Report()
+        self._check(load().nmf_get_report(self._ctx, ctypes.byref(r)))
+        return r.as_dict()
+
+    def append_columns(self, Mnew):
+        if hasattr(Mnew, "data_ptr"):
+            mnew, n = Mnew.shape
+        else:
+            n, mnew = Mnew.shape
+            if not Mnew.flags["F_CONTIGUOUS"]:
+                raise ValueError("host columns must be column-major")
+        if n != self.n:
+            raise ValueError("row count differs")
+        self._keep.append(Mnew)
+        self._check(load().nmf_append_columns(self._ctx, _ptr(Mnew), int(mnew), int(n)), ok=(NMF_OK,))
+
+    def factors(self):
+        """(X (n, k), Y (k, m)) as host numpy float64 arrays."""
+        import numpy as np
+        X = np.empty((self.n, self.k))
+        Y = np.empty((self.k, self.m))
+        self._check(load().nmf_get_factors(self._ctx, _ptr(X), _ptr(Y)), ok=(NMF_OK,))
+        return X, Y
+
+    def masks(self):
+        import numpy as np
+        xm = np.empty(self.n, dtype=np.uint32)
+        ym = np.empty(self.m, dtype=np.uint32)
+        self._check(load().nmf_get_masks(self._ctx, _ptr(xm), _ptr(ym)), ok=(NMF_OK,))
+        return xm, ym
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().nmf_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,622 @@
+// Stage 1 of the two-stage NMF: one ANLS sweep (Alg. 1) is two kernels.
+//
+//   k_xhalf  X-half.  Grid (Tn row tiles of 64) x (Sx column chunks).  Each
+//            block streams its 64 x xcols slab of M once (coalesced 512-byte
+//            wave loads), forms its share of B_X = M Y^T, and writes it to a
+//            partial buffer.  The last block of a row tile to finish (device
+//            counter, release/acquire fences) sums the Sx partials in a fixed
+//            order, reduces G_Y = Y Y^T from the Y-half tile partials, measures
+//            the KKT parts of E(.;0) at the old point (r = max(graX, 0),
+//            Sec. V-A), and runs one warm-started NNLS per row (eq. (2) with
+//            C = Y^T).  It leaves tile partials of G_X = X^T X for the Y-half.
+//   k_yhalf  Y-half, the same pattern for B_Y = X^T M over row splits, with
+//            the NNLS of eq. (2) for C = X per column.  The last tile of the
+//            sweep reduces the tile statistics and applies the stop rule of
+//            Sec. IV on the device; later enqueued sweeps then return at once.
+//
+// Every reduction runs in a fixed order, so results are bitwise reproducible
+// from run to run and independent of block scheduling.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "nmf_internal.h"
+#include "nnls_lh.h"
+
+namespace nmfk {
+
+__device__ __forceinline__ void release_fence() { __threadfence(); }
+
+// Increments a tile counter; returns true in the block that arrives last
+// (and resets the counter for the next launch).  All threads of the block
+// call it; the returned value is block-uniform.
+__device__ __forceinline__ bool last_arrival(unsigned *cnt, unsigned expected, unsigned *flag_lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned old = atomicAdd(cnt, 1u);
+        const bool last = (old == expected - 1u);
+        if (last) {
+            atomicExch(cnt, 0u);
+            __threadfence();
+        }
+        *flag_lds = last ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool last = (*flag_lds != 0u);
+    if (last) __threadfence();
+    return last;
+}
+
+// One butterfly step: lanes that differ in bit H swap halves of v[0..2H) and
+// keep the sum of the half named by their bit.
+template <int H>
+__device__ __forceinline__ void transpose_step(double (&v)[YVALS], int lane) {
+    const bool up = (lane & H) != 0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        const double send = up ? v[q] : v[q + H];
+        const double keep = up ? v[q + H] : v[q];
+        v[q] = keep + __shfl_xor(send, H, 64);
+    }
+}
+
+// Lane l of the wave ends up with the sum over the 64 lanes of v[l].
+__device__ __forceinline__ double wave_transpose_reduce(double (&v)[YVALS], int lane) {
+    transpose_step<32>(v, lane);
+    transpose_step<16>(v, lane);
+    transpose_step<8>(v, lane);
+    transpose_step<4>(v, lane);
+    transpose_step<2>(v, lane);
+    transpose_step<1>(v, lane);
+    return v[0];
+}
+
+// Fixed-order sum of `cnt` records of `len` doubles (stride `len`) into out[0..len).
+__device__ __forceinline__ void reduce_records(const double *src, int cnt, int len, double *out) {
+    for (int q = threadIdx.x; q < len; q += blockDim.x) {
+        double acc = 0.0;
+        int t = 0;
+        for (; t + 4 <= cnt; t += 4) {
+            const double a0 = src[(size_t)(t + 0) * len + q];
+            const double a1 = src[(size_t)(t + 1) * len + q];
+            const double a2 = src[(size_t)(t + 2) * len + q];
+            const double a3 = src[(size_t)(t + 3) * len + q];
+            acc += a0;
+            acc += a1;
+            acc += a2;
+            acc += a3;
+        }
+        for (; t < cnt; ++t) acc += src[(size_t)t * len + q];
+        out[q] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- X-half
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_xhalf(AnlsParams p) {
+    if (p.mode == 0 && p.st->converged) return;
+    __shared__ double ys[XCHUNK * K];
+    __shared__ double red[4 * K * XTILE];
+    __shared__ double G[K * K];
+    __shared__ double xs[XTILE * K];
+    __shared__ double stl[NST * XTILE];
+    __shared__ unsigned flag;
+
+    const int tile = blockIdx.x, split = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)tile * XTILE + lane;
+    const int64_t j0 = (int64_t)split * p.xcols;
+    const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
+
+    double acc[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) acc[a] = 0.0;
+
+    for (int64_t c0 = j0; c0 < j1; c0 += XCHUNK) {
+        const int nc = (int)min((int64_t)XCHUNK, j1 - c0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nc * K; q += NTHR) {
+            const int jj = q / K, a = q - jj * K;
+            ys[q] = p.Y[(int64_t)a * p.ldY + c0 + jj];
+        }
+        __syncthreads();
+        if (i < p.n) {
+            const double *mp = p.M + c0 * p.ldM + i;
+            int jj = w;
+            for (; jj + 12 < nc; jj += 16) {
+                const double m0 = mp[(int64_t)(jj + 0) * p.ldM];
+                const double m1 = mp[(int64_t)(jj + 4) * p.ldM];
+                const double m2 = mp[(int64_t)(jj + 8) * p.ldM];
+                const double m3 = mp[(int64_t)(jj + 12) * p.ldM];
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    acc[a] = fma(m0, ys[(jj + 0) * K + a], acc[a]);
+                    acc[a] = fma(m1, ys[(jj + 4) * K + a], acc[a]);
+                    acc[a] = fma(m2, ys[(jj + 8) * K + a], acc[a]);
+                    acc[a] = fma(m3, ys[(jj + 12) * K + a], acc[a]);
+                }
+            }
+            for (; jj < nc; jj += 4) {
+                const double m0 = mp[(int64_t)jj * p.ldM];
+#pragma unroll
+                for (int a = 0; a < K; ++a) acc[a] = fma(m0, ys[jj * K + a], acc[a]);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < K; ++a) red[(w * K + a) * XTILE + lane] = acc[a];
+    __syncthreads();
+    if (w == 0 && i < p.n) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            double v = red[(0 * K + a) * XTILE + lane];
+            v += red[(1 * K + a) * XTILE + lane];
+            v += red[(2 * K + a) * XTILE + lane];
+            v += red[(3 * K + a) * XTILE + lane];
+            p.bx_part[((int64_t)split * K + a) * p.ldX + i] = v;
+        }
+    }
+    if (!last_arrival(p.cnt_x + tile, (unsigned)p.Sx, &flag)) return;
+
+    // ---- last block of this row tile: G_Y, E parts, NNLS per row
+    reduce_records(p.gy_part, p.Tm, K * K, G);
+    __syncthreads();
+    if (w == 0) {
+        double gmax = 0.0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
+        double st[NST];
+#pragma unroll
+        for (int q = 0; q < NST; ++q) st[q] = 0.0;
+        double xn[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) xn[a] = 0.0;
+        if (i < p.n) {
+            double b[K], x[K];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                double v = 0.0;
+                for (int s = 0; s < p.Sx; ++s) v += p.bx_part[((int64_t)s * K + a) * p.ldX + i];
+                b[a] = v;
+                x[a] = p.X[(int64_t)a * p.ldX + i];
+            }
+            // graX at the old point: (X Y Y^T - M Y^T)_i
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                double g = -b[a];
+#pragma unroll
+                for (int c = 0; c < K; ++c) g = fma(G[a * K + c], x[c], g);
+                if (g < 0.0) st[ST_EG2] += g * g;
+                else st[ST_EC2] += (g * x[a]) * (g * x[a]);
+            }
+            if (p.mode == 0) {
+                const uint32_t old_mask = p.xmask[i];
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    xn[a] = x[a];
+                    st[ST_NORM2] += x[a] * x[a];
+                }
+                const LhResult r = lh_warm<K>(G, gmax, b, xn);
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    const double d = xn[a] - x[a];
+                    st[ST_STEP2] += d * d;
+                    p.X[(int64_t)a * p.ldX + i] = xn[a];
+                }
+                p.xmask[i] = r.P;
+                st[ST_SOLVES] = r.solves;
+                st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
+                st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
+            } else {
+#pragma unroll
+                for (int a = 0; a < K; ++a) xn[a] = x[a];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NST; ++q) stl[q * XTILE + lane] = st[q];
+#pragma unroll
+        for (int a = 0; a < K; ++a) xs[lane * K + a] = xn[a];
+    }
+    __syncthreads();
+    if (threadIdx.x < NST) {
+        double v = 0.0;
+        for (int l = 0; l < XTILE; ++l) v += stl[threadIdx.x * XTILE + l];
+        p.xstat[(int64_t)tile * NST + threadIdx.x] = v;
+    }
+    if (p.mode == 0) {
+        for (int q = threadIdx.x; q < K * K; q += NTHR) {
+            const int a = q / K, c = q - a * K;
+            double v = 0.0;
+            for (int l = 0; l < XTILE; ++l) v = fma(xs[l * K + a], xs[l * K + c], v);
+            p.gx_part[(int64_t)tile * K * K + q] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Y-half
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_yhalf(AnlsParams p) {
+    if (p.mode == 0 && p.st->converged) return;
+    constexpr int J = YVALS / K;
+    __shared__ double red[4 * YVALS];
+    __shared__ double G[K * K];
+    __shared__ double bsum[YVALS];
+    __shared__ double ysn[J * K];
+    __shared__ double stl[NST * J];
+    __shared__ unsigned flag;
+
+    const int ct = blockIdx.x, split = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t jb = (int64_t)ct * J;
+    const int nj = (int)min((int64_t)J, p.m - jb);
+    const int64_t r0 = (int64_t)split * p.yrows;
+    const int64_t r1 = min(r0 + (int64_t)p.yrows, p.n);
+
+    double v[YVALS];
+#pragma unroll
+    for (int q = 0; q < YVALS; ++q) v[q] = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += NTHR) {
+        double x[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) x[a] = p.X[(int64_t)a * p.ldX + i];
+        const double *mp = p.M + jb * p.ldM + i;
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) {
+            if (jj < nj) {
+                const double mv = mp[(int64_t)jj * p.ldM];
+#pragma unroll
+                for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv, x[a], v[jj * K + a]);
+            }
+        }
+    }
+    const double mine = wave_transpose_reduce(v, lane);
+    red[w * YVALS + lane] = mine;
+    __syncthreads();
+    if (threadIdx.x < YVALS) {
+        double s = red[0 * YVALS + threadIdx.x];
+        s += red[1 * YVALS + threadIdx.x];
+        s += red[2 * YVALS + threadIdx.x];
+        s += red[3 * YVALS + threadIdx.x];
+        p.by_part[((int64_t)ct * p.Sy + split) * YVALS + threadIdx.x] = s;
+    }
+    if (!last_arrival(p.cnt_y + ct, (unsigned)p.Sy, &flag)) return;
+
+    // ---- last block of this column tile: G_X, NNLS per column
+    reduce_records(p.gx_part, p.Tn, K * K, G);
+    if (threadIdx.x < YVALS) {
+        double s = 0.0;
+        for (int sp = 0; sp < p.Sy; ++sp) s += p.by_part[((int64_t)ct * p.Sy + sp) * YVALS + threadIdx.x];
+        bsum[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < J) {
+        const int jj = threadIdx.x;
+        double st[NST];
+#pragma unroll
+        for (int q = 0; q < NST; ++q) st[q] = 0.0;
+        double yn[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) yn[a] = 0.0;
+        if (jj < nj) {
+            const int64_t j = jb + jj;
+            double gmax = 0.0;
+#pragma unroll
+            for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
+            double b[K], y[K];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                b[a] = bsum[jj * K + a];
+                y[a] = p.Y[(int64_t)a * p.ldY + j];
+                yn[a] = y[a];
+                st[ST_NORM2] += y[a] * y[a];
+            }
+            const uint32_t old_mask = p.ymask[j];
+            const LhResult r = lh_warm<K>(G, gmax, b, yn);
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const double d = yn[a] - y[a];
+                st[ST_STEP2] += d * d;
+                p.Y[(int64_t)a * p.ldY + j] = yn[a];
+            }
+            p.ymask[j] = r.P;
+            // graY at the new point: (X^T X Y - X^T M)_j, the Y part of E(.;0)
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                double g = -b[a];
+#pragma unroll
+                for (int c = 0; c < K; ++c) g = fma(G[a * K + c], yn[c], g);
+                if (g < 0.0) st[ST_EG2] += g * g;
+                else st[ST_EC2] += (g * yn[a]) * (g * yn[a]);
+            }
+            st[ST_SOLVES] = r.solves;
+            st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
+            st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NST; ++q) stl[q * J + jj] = st[q];
+#pragma unroll
+        for (int a = 0; a < K; ++a) ysn[jj * K + a] = yn[a];
+    }
+    __syncthreads();
+    if (threadIdx.x < NST) {
+        double s = 0.0;
+        for (int l = 0; l < J; ++l) s += stl[threadIdx.x * J + l];
+        p.ystat[(int64_t)ct * NST + threadIdx.x] = s;
+    }
+    for (int q = threadIdx.x; q < K * K; q += NTHR) {
+        const int a = q / K, c = q - a * K;
+        double s = 0.0;
+        for (int l = 0; l < J; ++l) s = fma(ysn[l * K + a], ysn[l * K + c], s);
+        p.gy_part[(int64_t)ct * K * K + q] = s;
+    }
+    if (!last_arrival(p.cnt_fin, (unsigned)p.Tm, &flag)) return;
+
+    // ---- last tile of the sweep: statistics and the Sec. IV stop rule
+    __shared__ double sx[NST], sy[NST];
+    reduce_records(p.xstat, p.Tn, NST, sx);
+    reduce_records(p.ystat, p.Tm, NST, sy);
+    __syncthreads();
+    if (threadIdx.x == 0 && p.mode == 2) {
+        // appended columns solved: Y part of E, counters; no sweep, no stop test
+        DevStatus *st = p.st;
+        st->ey_g2 = sy[ST_EG2];
+        st->ey_c2 = sy[ST_EC2];
+        st->E_cur = -1.0;
+        st->solves += sy[ST_SOLVES];
+        st->fails += sy[ST_FAILS];
+        st->changes += sy[ST_CHANGES];
+    } else if (threadIdx.x == 0) {
+        DevStatus *st = p.st;
+        const double step2 = sx[ST_STEP2] + sy[ST_STEP2];
+        const double norm2 = sx[ST_NORM2] + sy[ST_NORM2];
+        st->step2 = step2;
+        st->norm2 = norm2;
+        st->ex_g2 = sx[ST_EG2];
+        st->ex_c2 = sx[ST_EC2];
+        if (st->ey_g2 >= 0.0) {
+            const double eg = sqrt(sx[ST_EG2] + st->ey_g2);
+            const double ec = sqrt(sx[ST_EC2] + st->ey_c2);
+            st->E_prev = eg > ec ? eg : ec;
+        }
+        st->ey_g2_prev = st->ey_g2;
+        st->ey_c2_prev = st->ey_c2;
+        st->ey_g2 = sy[ST_EG2];
+        st->ey_c2 = sy[ST_EC2];
+        st->E_cur = -1.0;
+        st->solves += sx[ST_SOLVES] + sy[ST_SOLVES];
+        st->fails += sx[ST_FAILS] + sy[ST_FAILS];
+        st->changes += sx[ST_CHANGES] + sy[ST_CHANGES];
+        st->sweeps += 1;
+        if (sqrt(step2) <= st->eps_stol * (1.0 + sqrt(norm2)) || st->sweeps >= st->max_sweeps)
+            st->converged = 1;
+    }
+}
+
+// E(.;0) at the current iterate after a measure-mode X-half: X part from the
+// tile records, Y part from the last Y-half.
+template <int K>
+__global__ void k_measure_finish(AnlsParams p) {
+    __shared__ double sx[NST];
+    reduce_records(p.xstat, p.Tn, NST, sx);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DevStatus *st = p.st;
+        const double yg = st->ey_g2 >= 0.0 ? st->ey_g2 : 0.0;
+        const double yc = st->ey_c2 >= 0.0 ? st->ey_c2 : 0.0;
+        const double eg = sqrt(sx[ST_EG2] + yg);
+        const double ec = sqrt(sx[ST_EC2] + yc);
+        st->E_cur = eg > ec ? eg : ec;
+    }
+}
+
+// G_Y partials from the current Y, in the Y-half tile layout.
+template <int K>
+__global__ void k_gram_y_init(AnlsParams p) {
+    constexpr int J = YVALS / K;
+    const int ct = blockIdx.x;
+    const int64_t jb = (int64_t)ct * J;
+    const int nj = (int)min((int64_t)J, p.m - jb);
+    for (int q = threadIdx.x; q < K * K; q += blockDim.x) {
+        const int a = q / K, c = q - a * K;
+        double s = 0.0;
+        for (int l = 0; l < nj; ++l)
+            s = fma(p.Y[(int64_t)a * p.ldY + jb + l], p.Y[(int64_t)c * p.ldY + jb + l], s);
+        p.gy_part[(int64_t)ct * K * K + q] = s;
+    }
+}
+
+// Direct objective 1/2 ||XY - M||^2: per-block partials, fixed order.
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_objective(AnlsParams p, double *part) {
+    __shared__ double red[NTHR];
+    double acc = 0.0;
+    const int64_t total = p.n * p.m;
+    for (int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x; e < total; e += (int64_t)gridDim.x * NTHR) {
+        const int64_t j = e / p.n, i = e - j * p.n;
+        double r = -p.M[j * p.ldM + i];
+#pragma unroll
+        for (int a = 0; a < K; ++a) r = fma(p.X[(int64_t)a * p.ldX + i], p.Y[(int64_t)a * p.ldY + j], r);
+        acc = fma(r, r, acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = NTHR / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    __shared__ unsigned flag;
+    if (!last_arrival(p.cnt_fin + 1, gridDim.x, &flag)) return;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (unsigned b = 0; b < gridDim.x; ++b) s += part[b];
+        p.st->f_direct = 0.5 * s;
+    }
+}
+
+// part[0..nblk): ||M||^2 partials; part[nblk..2 nblk): count of non-finite entries.
+__global__ __launch_bounds__(NTHR) void k_check_finite(const double *M, int64_t n, int64_t m, int64_t ldM,
+                                                       double *part) {
+    __shared__ double red[NTHR], bad[NTHR];
+    double acc = 0.0, nb = 0.0;
+    const int64_t total = n * m;
+    for (int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x; e < total; e += (int64_t)gridDim.x * NTHR) {
+        const int64_t j = e / n, i = e - j * n;
+        const double v = M[j * ldM + i];
+        if (isfinite(v)) acc = fma(v, v, acc);
+        else nb += 1.0;
+    }
+    red[threadIdx.x] = acc;
+    bad[threadIdx.x] = nb;
+    __syncthreads();
+    for (int h = NTHR / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red[threadIdx.x] += red[threadIdx.x + h];
+            bad[threadIdx.x] += bad[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = red[0];
+        part[gridDim.x + blockIdx.x] = bad[0];
+    }
+}
+
+// Row-major X (n x K) and Y (K x m) into the component-major device layout;
+// masks from the signs.  Either source may be NULL (left untouched).
+// Negative or non-finite entries are counted in *bad.
+template <int K>
+__global__ void k_factor_in(const double *sx, const double *sy, AnlsParams p, unsigned *bad) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned nb = 0;
+    if (sx && e < p.n) {
+        uint32_t P = 0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const double v = sx[e * K + a];
+            p.X[(int64_t)a * p.ldX + e] = v;
+            if (v > 0.0) P |= 1u << a;
+            if (!(v >= 0.0) || !isfinite(v)) ++nb;
+        }
+        p.xmask[e] = P;
+    }
+    if (sy && e < p.m) {
+        uint32_t P = 0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const double v = sy[(int64_t)a * p.m + e];
+            p.Y[(int64_t)a * p.ldY + e] = v;
+            if (v > 0.0) P |= 1u << a;
+            if (!(v >= 0.0) || !isfinite(v)) ++nb;
+        }
+        p.ymask[e] = P;
+    }
+    if (nb) atomicAdd(bad, nb);
+}
+
+template <int K>
+__global__ void k_factor_out(AnlsParams p, double *dx, double *dy) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (dx && e < p.n) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) dx[e * K + a] = p.X[(int64_t)a * p.ldX + e];
+    }
+    if (dy && e < p.m) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) dy[(int64_t)a * p.m + e] = p.Y[(int64_t)a * p.ldY + e];
+    }
+}
+
+// Columns [j0, j1) of Y start from column j_from and its passive set (the
+// neighbouring-column warm start for appended time instants).
+template <int K>
+__global__ void k_copy_columns_warm(AnlsParams p, int64_t j_from, int64_t j0, int64_t j1) {
+    const int64_t j = j0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= j1) return;
+#pragma unroll
+    for (int a = 0; a < K; ++a) p.Y[(int64_t)a * p.ldY + j] = p.Y[(int64_t)a * p.ldY + j_from];
+    p.ymask[j] = p.ymask[j_from];
+}
+
+// ---------------------------------------------------------------- launchers
+#define NMF_K_SWITCH(K, CALL)                                                        \
+    switch (K) {                                                                     \
+        case 1: { constexpr int KK = 1; CALL; } break;                               \
+        case 2: { constexpr int KK = 2; CALL; } break;                               \
+        case 3: { constexpr int KK = 3; CALL; } break;                               \
+        case 4: { constexpr int KK = 4; CALL; } break;                               \
+        case 5: { constexpr int KK = 5; CALL; } break;                               \
+        case 6: { constexpr int KK = 6; CALL; } break;                               \
+        case 7: { constexpr int KK = 7; CALL; } break;                               \
+        case 8: { constexpr int KK = 8; CALL; } break;                               \
+        case 9: { constexpr int KK = 9; CALL; } break;                               \
+        case 10: { constexpr int KK = 10; CALL; } break;                             \
+        case 11: { constexpr int KK = 11; CALL; } break;                             \
+        case 12: { constexpr int KK = 12; CALL; } break;                             \
+        case 13: { constexpr int KK = 13; CALL; } break;                             \
+        case 14: { constexpr int KK = 14; CALL; } break;                             \
+        case 15: { constexpr int KK = 15; CALL; } break;                             \
+        case 16: { constexpr int KK = 16; CALL; } break;                             \
+        default: return hipErrorInvalidValue;                                        \
+    }
+
+int yhalf_cols(int K) { return K >= 1 && K <= KMAX ? YVALS / K : 0; }
+
+hipError_t launch_xhalf(int K, const AnlsParams &p, hipStream_t s) {
+    dim3 grid(p.Tn, p.Sx);
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_xhalf<KK>, grid, dim3(NTHR), 0, s, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s) {
+    dim3 grid(p.Tm, p.Sy);
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_yhalf<KK>, grid, dim3(NTHR), 0, s, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_measure_finish<KK>, dim3(1), dim3(NTHR), 0, s, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_y_init(int K, const AnlsParams &p, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_y_init<KK>, dim3(p.Tm), dim3(NTHR), 0, s, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_objective(int K, const AnlsParams &p, double *part, int nblk, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_objective<KK>, dim3(nblk), dim3(NTHR), 0, s, p, part));
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double *M, int64_t n, int64_t m, int64_t ldM, double *part, int nblk,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_check_finite, dim3(nblk), dim3(NTHR), 0, s, M, n, m, ldM, part);
+    return hipGetLastError();
+}
+
+static dim3 grid_rows(const AnlsParams &p) {
+    const int64_t e = p.n > p.m ? p.n : p.m;
+    return dim3((unsigned)((e + NTHR - 1) / NTHR));
+}
+
+hipError_t launch_factor_in(int K, const double *sx, const double *sy, const AnlsParams &p, unsigned *bad,
+                            hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_factor_in<KK>, grid_rows(p), dim3(NTHR), 0, s, sx, sy, p, bad));
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_out(int K, const AnlsParams &p, double *dx, double *dy, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_factor_out<KK>, grid_rows(p), dim3(NTHR), 0, s, p, dx, dy));
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_columns_warm(int K, const AnlsParams &p, int64_t j_from, int64_t j0, int64_t j1,
+                                    hipStream_t s) {
+    if (j1 <= j0) return hipSuccess;
+    const unsigned nb = (unsigned)((j1 - j0 + NTHR - 1) / NTHR);
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_copy_columns_warm<KK>, dim3(nb), dim3(NTHR), 0, s, p, j_from, j0, j1));
+    return hipGetLastError();
+}
+
+}  // namespace nmfk

@@ -1,0 +1,609 @@
+// Host runtime behind include/nmf.h: workspace layout, launch planning, the
+// stage machine of Alg. 3 and the C entry points.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nmf.h"
+#include "ipm.h"
+#include "nmf_internal.h"
+
+using nmfk::AnlsParams;
+using nmfk::DevStatus;
+
+namespace {
+
+constexpr int kRedBlocks = 512;   // blocks of the fixed-order reduction kernels
+constexpr int kSxMax = 64;        // column splits of the X-half
+constexpr int kSyMax = 64;        // row splits of the Y-half
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Plan {
+    int64_t ldM, ldX, ldY;
+    int Tn, Sx, xcols, Sy, yrows, Tm, J;
+};
+
+// Stage-1 launch shape.  X-half: one tile per 64 rows, column splits so that
+// the grid holds ~2048 blocks and a block streams >= 16 columns.  Y-half: J =
+// 64/K columns per tile, row splits of >= 2048 rows (8 rows per thread).
+Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K) {
+    Plan P;
+    P.ldM = align_up((size_t)n, 32);
+    P.ldX = align_up((size_t)n, 64);
+    P.ldY = align_up((size_t)m_cap, 64);
+    P.Tn = (int)ceil_div(n, nmfk::XTILE);
+    int64_t sx = ceil_div(2048, P.Tn);
+    sx = std::min<int64_t>(sx, std::max<int64_t>(1, ceil_div(m, 16)));
+    sx = std::max<int64_t>(1, std::min<int64_t>(sx, kSxMax));
+    P.xcols = (int)ceil_div(m, sx);
+    P.Sx = (int)ceil_div(m, P.xcols);
+    int64_t sy = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 2048), kSyMax));
+    P.yrows = (int)ceil_div(n, sy);
+    P.Sy = (int)ceil_div(n, P.yrows);
+    P.J = nmfk::yhalf_cols(K);
+    P.Tm = (int)ceil_div(m, P.J);
+    return P;
+}
+
+struct Carve {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t count) {
+        const size_t at = align_up(off, 256);
+        off = at + count * sizeof(T);
+        return at;
+    }
+};
+
+struct Offsets {
+    size_t M, X, Y, xmask, ymask, bx, by, gx, gy, xst, yst, cntx, cnty, cntf, status, red, io, bad;
+    size_t ipm_base, total;
+};
+
+Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
+    const Plan P = plan_shape(n, m_cap, m_cap, K);
+    const int64_t TmMax = ceil_div(m_cap, P.J);
+    Offsets L;
+    Carve c;
+    L.M = c.take<double>((size_t)P.ldM * m_cap);
+    L.X = c.take<double>((size_t)K * P.ldX);
+    L.Y = c.take<double>((size_t)K * P.ldY);
+    L.xmask = c.take<uint32_t>(P.ldX);
+    L.ymask = c.take<uint32_t>(P.ldY);
+    L.bx = c.take<double>((size_t)kSxMax * K * P.ldX);
+    L.by = c.take<double>((size_t)TmMax * P.Sy * nmfk::YVALS);
+    L.gx = c.take<double>((size_t)P.Tn * K * K);
+    L.gy = c.take<double>((size_t)TmMax * K * K);
+    L.xst = c.take<double>((size_t)P.Tn * nmfk::NST);
+    L.yst = c.take<double>((size_t)TmMax * nmfk::NST);
+    L.cntx = c.take<unsigned>(P.Tn);
+    L.cnty = c.take<unsigned>(TmMax);
+    L.cntf = c.take<unsigned>(4);
+    L.status = c.take<DevStatus>(1);
+    L.red = c.take<double>(2 * kRedBlocks);
+    L.io = c.take<double>((size_t)K * (n + m_cap));
+    L.bad = c.take<unsigned>(4);
+    L.ipm_base = align_up(c.off, 256);
+    size_t ipm = o.with_ipm ? nmfk::ipm_workspace_bytes(n, m_cap, K) : 0;
+    L.total = L.ipm_base + ipm;
+    return L;
+}
+
+}  // namespace
+
+struct nmf_ctx {
+    int64_t n = 0, m = 0, m_cap = 0;
+    int K = 0;
+    nmf_options opt;
+    hipStream_t stream = nullptr;
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0;
+    Offsets off;
+    Plan plan;
+    AnlsParams p;
+    double *red = nullptr, *io = nullptr;
+    unsigned *bad = nullptr;
+    int stage = 1;
+    double mnorm2 = 0.0;
+    double ms1 = 0.0, ms2 = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    nmfk::IpmState ipm;
+    std::string err;
+};
+
+static nmf_status fail(nmf_ctx *c, nmf_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+static nmf_status hip_fail(nmf_ctx *c, hipError_t e, const char *what) {
+    return fail(c, NMF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, call)                                   \
+    do {                                                  \
+        hipError_t _e = (call);                           \
+        if (_e != hipSuccess) return hip_fail(c, _e, #call); \
+    } while (0)
+
+static void refresh_shape(nmf_ctx *c) {
+    c->plan = plan_shape(c->n, c->m, c->m_cap, c->K);
+    AnlsParams &p = c->p;
+    p.n = c->n;
+    p.m = c->m;
+    p.Sx = c->plan.Sx;
+    p.Tn = c->plan.Tn;
+    p.xcols = c->plan.xcols;
+    p.Sy = c->plan.Sy;
+    p.Tm = c->plan.Tm;
+    p.yrows = c->plan.yrows;
+}
+
+extern "C" {
+
+void nmf_default_options(nmf_options *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->eps_tol = 1e-6;
+    o->eps_stol = 1e-6;
+    o->tau = 0.9;
+    o->eta = 0.5;
+    o->sigma_c = 0.01;
+    o->rho0_factor = 1e-6;
+    o->rho = 1e-6;
+    o->inner_cap = 3;
+    o->exact_hessian_switch = 1;
+    o->max_anls_sweeps = 5000;
+    o->max_ipm_iters = 1000;
+    o->max_backtracks = 60;
+    o->check_every = 32;
+    o->gram_precision = NMF_GRAM_FP64;
+    o->with_ipm = 1;
+    o->seed = 0;
+}
+
+size_t nmf_workspace_bytes(int64_t n, int64_t m_capacity, int32_t k, const nmf_options *opts) {
+    if (n < 1 || m_capacity < 1 || k < 1 || k > nmfk::KMAX) return 0;
+    nmf_options o;
+    if (opts) o = *opts;
+    else nmf_default_options(&o);
+    return layout(n, m_capacity, k, o).total;
+}
+
+const char *nmf_status_string(nmf_status s) {
+    switch (s) {
+        case NMF_OK: return "NMF_OK";
+        case NMF_CONVERGED: return "NMF_CONVERGED";
+        case NMF_EINVAL: return "NMF_EINVAL";
+        case NMF_ENOMEM: return "NMF_ENOMEM";
+        case NMF_EDEVICE: return "NMF_EDEVICE";
+        case NMF_ENOTCONV: return "NMF_ENOTCONV";
+        case NMF_ESINGULAR: return "NMF_ESINGULAR";
+        case NMF_ESTATE: return "NMF_ESTATE";
+        case NMF_ECAPACITY: return "NMF_ECAPACITY";
+    }
+    return "unknown";
+}
+
+const char *nmf_last_error(const nmf_ctx *c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+nmf_status nmf_get_shape(const nmf_ctx *c, int64_t *n, int64_t *m, int32_t *k) {
+    if (!c) return NMF_EINVAL;
+    if (n) *n = c->n;
+    if (m) *m = c->m;
+    if (k) *k = c->K;
+    return NMF_OK;
+}
+
+// Host draw of the seeded start (splitmix64 -> U(0,1)), scaled so that
+// ||X0 Y0||_F = ||M||_F.
+static double host_u01(uint64_t seed, uint64_t idx) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (idx + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_t k, int64_t m_capacity,
+                      const double *X0, const double *Y0, const nmf_options *opts, void *device_workspace,
+                      size_t ws_bytes, void *hip_stream, nmf_ctx **out) {
+    if (!out) return fail(nullptr, NMF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!M) return fail(nullptr, NMF_EINVAL, "M is NULL");
+    if (n < 1 || m < 1 || k < 1 || k > nmfk::KMAX)
+        return fail(nullptr, NMF_EINVAL, "need n >= 1, m >= 1, 1 <= k <= 16");
+    if (m_capacity < m) return fail(nullptr, NMF_EINVAL, "m_capacity < m");
+    if (ldm < n) return fail(nullptr, NMF_EINVAL, "ldm < n");
+    if ((X0 == nullptr) != (Y0 == nullptr)) return fail(nullptr, NMF_EINVAL, "give both X0 and Y0 or neither");
+    nmf_options o;
+    if (opts) o = *opts;
+    else nmf_default_options(&o);
+    if (o.inner_cap < 1 || o.check_every < 1 || !(o.tau > 0 && o.tau < 1) || !(o.eta > 0 && o.eta < 1))
+        return fail(nullptr, NMF_EINVAL, "invalid options");
+    if (o.gram_precision != NMF_GRAM_FP64)
+        return fail(nullptr, NMF_EINVAL, "only NMF_GRAM_FP64 is available in this build");
+    const Offsets L = layout(n, m_capacity, k, o);
+    if (!device_workspace || ws_bytes < L.total)
+        return fail(nullptr, NMF_ENOMEM, "workspace smaller than nmf_workspace_bytes()");
+    if (((uintptr_t)device_workspace) % 256 != 0) return fail(nullptr, NMF_EINVAL, "workspace not 256-byte aligned");
+
+    nmf_ctx *c = new (std::nothrow) nmf_ctx();
+    if (!c) return fail(nullptr, NMF_ENOMEM, "host allocation failed");
+    c->n = n;
+    c->m = m;
+    c->m_cap = m_capacity;
+    c->K = k;
+    c->opt = o;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (uint8_t *)device_workspace;
+    c->ws_bytes = ws_bytes;
+    c->off = L;
+    AnlsParams &p = c->p;
+    memset(&p, 0, sizeof(p));
+    uint8_t *w = c->ws;
+    p.M = (const double *)(w + L.M);
+    p.X = (double *)(w + L.X);
+    p.Y = (double *)(w + L.Y);
+    p.xmask = (uint32_t *)(w + L.xmask);
+    p.ymask = (uint32_t *)(w + L.ymask);
+    p.bx_part = (double *)(w + L.bx);
+    p.by_part = (double *)(w + L.by);
+    p.gx_part = (double *)(w + L.gx);
+    p.gy_part = (double *)(w + L.gy);
+    p.xstat = (double *)(w + L.xst);
+    p.ystat = (double *)(w + L.yst);
+    p.cnt_x = (unsigned *)(w + L.cntx);
+    p.cnt_y = (unsigned *)(w + L.cnty);
+    p.cnt_fin = (unsigned *)(w + L.cntf);
+    p.st = (DevStatus *)(w + L.status);
+    c->red = (double *)(w + L.red);
+    c->io = (double *)(w + L.io);
+    c->bad = (unsigned *)(w + L.bad);
+    refresh_shape(c);
+    p.ldM = c->plan.ldM;
+    p.ldX = c->plan.ldX;
+    p.ldY = c->plan.ldY;
+
+    nmf_status st = NMF_OK;
+    auto bail = [&](nmf_status s) {
+        g_create_error = c->err;
+        if (c->ev0) (void)hipEventDestroy(c->ev0);
+        if (c->ev1) (void)hipEventDestroy(c->ev1);
+        delete c;
+        return s;
+    };
+#define CHK(call)                                                  \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return bail(hip_fail(c, _e, #call)); \
+    } while (0)
+
+    hipStream_t s = c->stream;
+    CHK(hipEventCreate(&c->ev0));
+    CHK(hipEventCreate(&c->ev1));
+    // small regions start at zero (counters must be zero before the first sweep)
+    CHK(hipMemsetAsync(w + L.bx, 0, L.io - L.bx, s));
+    CHK(hipMemsetAsync(w + L.X, 0, L.bx - L.X, s));
+    CHK(hipMemcpy2DAsync((void *)p.M, (size_t)p.ldM * 8, M, (size_t)ldm * 8, (size_t)n * 8, (size_t)m,
+                         hipMemcpyDefault, s));
+    CHK(nmfk::launch_check_finite(p.M, n, m, p.ldM, c->red, kRedBlocks, s));
+    std::vector<double> red(2 * kRedBlocks);
+    CHK(hipMemcpyAsync(red.data(), c->red, red.size() * 8, hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+    double mn2 = 0.0, nbad = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) {
+        mn2 += red[b];
+        nbad += red[kRedBlocks + b];
+    }
+    if (nbad > 0) {
+        c->err = "M has NaN or Inf entries";
+        return bail(NMF_EINVAL);
+    }
+    c->mnorm2 = mn2;
+
+    const double *sx = X0, *sy = Y0;
+    std::vector<double> hx, hy;
+    if (!X0) {
+        hx.resize((size_t)n * k);
+        hy.resize((size_t)k * m);
+        for (size_t q = 0; q < hx.size(); ++q) hx[q] = host_u01(o.seed, q);
+        for (size_t q = 0; q < hy.size(); ++q) hy[q] = host_u01(o.seed ^ 0x5851F42D4C957F2Dull, q);
+        double p2 = 0.0;
+        std::vector<double> row(m);
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t j = 0; j < m; ++j) {
+                double v = 0.0;
+                for (int a = 0; a < k; ++a) v += hx[i * k + a] * hy[(size_t)a * m + j];
+                p2 += v * v;
+            }
+        }
+        const double scale = (p2 > 0 && mn2 > 0) ? sqrt(sqrt(mn2 / p2)) : 1.0;
+        for (auto &v : hx) v *= scale;
+        for (auto &v : hy) v *= scale;
+        sx = hx.data();
+        sy = hy.data();
+    }
+    // stage through io: [X0 n*k][Y0 k*m]
+    CHK(hipMemcpyAsync(c->io, sx, (size_t)n * k * 8, hipMemcpyDefault, s));
+    CHK(hipMemcpyAsync(c->io + (size_t)n * k, sy, (size_t)k * m * 8, hipMemcpyDefault, s));
+    CHK(hipMemsetAsync(c->bad, 0, 16, s));
+    CHK(nmfk::launch_factor_in(k, c->io, c->io + (size_t)n * k, p, c->bad, s));
+    unsigned hbad = 0;
+    CHK(hipMemcpyAsync(&hbad, c->bad, 4, hipMemcpyDeviceToHost, s));
+    CHK(nmfk::launch_gram_y_init(k, p, s));
+    DevStatus ds;
+    memset(&ds, 0, sizeof(ds));
+    ds.eps_stol = o.eps_stol;
+    ds.max_sweeps = o.max_anls_sweeps;
+    ds.ey_g2 = ds.ey_c2 = -1.0;
+    ds.ey_g2_prev = ds.ey_c2_prev = -1.0;
+    ds.E_prev = ds.E_cur = -1.0;
+    ds.f_direct = -1.0;
+    CHK(hipMemcpyAsync(p.st, &ds, sizeof(ds), hipMemcpyHostToDevice, s));
+    CHK(hipStreamSynchronize(s));
+    if (hbad) {
+        c->err = "X0/Y0 have negative, NaN or Inf entries";
+        return bail(NMF_EINVAL);
+    }
+    if (o.with_ipm) {
+        st = nmfk::ipm_bind(c->ipm, w + L.ipm_base, n, m_capacity, k);
+        if (st != NMF_OK) {
+            c->err = "stage-2 workspace binding failed";
+            return bail(st);
+        }
+    }
+#undef CHK
+    *out = c;
+    return NMF_OK;
+}
+
+nmf_status nmf_destroy(nmf_ctx *c) {
+    if (!c) return NMF_OK;
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+    return NMF_OK;
+}
+
+static nmf_status read_status(nmf_ctx *c, DevStatus &ds) {
+    HIPCHK(c, hipMemcpyAsync(&ds, c->p.st, sizeof(ds), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NMF_OK;
+}
+
+static void fill_stage1(nmf_ctx *c, const DevStatus &ds, nmf_report *r) {
+    r->stage = c->stage;
+    r->sweeps = ds.sweeps;
+    r->step_rel = sqrt(ds.step2) / (1.0 + sqrt(ds.norm2));
+    r->E0 = ds.E_cur >= 0 ? ds.E_cur : ds.E_prev;
+    r->nnls_solves = (int64_t)ds.solves;
+    r->nnls_failed = (int64_t)ds.fails;
+    r->mask_changes = (int64_t)ds.changes;
+    r->f = ds.f_direct;
+    r->ms_stage1 = c->ms1;
+    r->ms_stage2 = c->ms2;
+}
+
+static nmf_status enqueue_sweeps(nmf_ctx *c, int sweeps) {
+    AnlsParams p = c->p;
+    p.mode = 0;
+    for (int t = 0; t < sweeps; ++t) {
+        HIPCHK(c, nmfk::launch_xhalf(c->K, p, c->stream));
+        HIPCHK(c, nmfk::launch_yhalf(c->K, p, c->stream));
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_anls_step(nmf_ctx *c, int32_t sweeps, nmf_report *r) {
+    if (!c) return NMF_EINVAL;
+    if (sweeps < 0) return fail(c, NMF_EINVAL, "sweeps < 0");
+    if (c->stage != 1) return fail(c, NMF_ESTATE, "stage 2 has started");
+    if (r) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    nmf_status st = enqueue_sweeps(c, sweeps);
+    if (st != NMF_OK) return st;
+    if (!r) return NMF_OK;
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    DevStatus ds;
+    st = read_status(c, ds);
+    if (st != NMF_OK) return st;
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->ms1 += ms;
+    memset(r, 0, sizeof(*r));
+    fill_stage1(c, ds, r);
+    return ds.converged ? NMF_CONVERGED : NMF_OK;
+}
+
+nmf_status nmf_anls_profile(nmf_ctx *c, int32_t sweeps, double *ms_x, double *ms_y) {
+    if (!c) return NMF_EINVAL;
+    if (sweeps < 1) return fail(c, NMF_EINVAL, "sweeps < 1");
+    if (c->stage != 1) return fail(c, NMF_ESTATE, "stage 2 has started");
+    std::vector<hipEvent_t> ev(4 * (size_t)sweeps, nullptr);
+    nmf_status st = NMF_OK;
+    for (auto &e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) { st = fail(c, NMF_EDEVICE, "hipEventCreate failed"); break; }
+    }
+    AnlsParams p = c->p;
+    p.mode = 0;
+    for (int t = 0; st == NMF_OK && t < sweeps; ++t) {
+        if (hipEventRecord(ev[4 * t + 0], c->stream) != hipSuccess ||
+            nmfk::launch_xhalf(c->K, p, c->stream) != hipSuccess ||
+            hipEventRecord(ev[4 * t + 1], c->stream) != hipSuccess ||
+            hipEventRecord(ev[4 * t + 2], c->stream) != hipSuccess ||
+            nmfk::launch_yhalf(c->K, p, c->stream) != hipSuccess ||
+            hipEventRecord(ev[4 * t + 3], c->stream) != hipSuccess)
+            st = fail(c, NMF_EDEVICE, "launch failed");
+    }
+    double sx = 0.0, sy = 0.0;
+    if (st == NMF_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, NMF_EDEVICE, "sync failed");
+    for (int t = 0; st == NMF_OK && t < sweeps; ++t) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, ev[4 * t + 0], ev[4 * t + 1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[4 * t + 2], ev[4 * t + 3]) != hipSuccess)
+            st = fail(c, NMF_EDEVICE, "hipEventElapsedTime failed");
+        sx += a;
+        sy += b;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st != NMF_OK) return st;
+    if (ms_x) *ms_x = sx / sweeps;
+    if (ms_y) *ms_y = sy / sweeps;
+    return NMF_OK;
+}
+
+// E(.;0) of the current stage-1 iterate (measure-mode X-half) and the direct
+// objective; results land in the device status.
+static nmf_status measure_stage1(nmf_ctx *c) {
+    AnlsParams p = c->p;
+    p.mode = 1;
+    HIPCHK(c, nmfk::launch_xhalf(c->K, p, c->stream));
+    HIPCHK(c, nmfk::launch_measure_finish(c->K, p, c->stream));
+    HIPCHK(c, nmfk::launch_objective(c->K, p, c->red, kRedBlocks, c->stream));
+    return NMF_OK;
+}
+
+nmf_status nmf_get_report(nmf_ctx *c, nmf_report *r) {
+    if (!c || !r) return NMF_EINVAL;
+    memset(r, 0, sizeof(*r));
+    if (c->stage == 2) return nmfk::ipm_report(c->ipm, r, c->ms1, c->ms2);
+    nmf_status st = measure_stage1(c);
+    if (st != NMF_OK) return st;
+    DevStatus ds;
+    st = read_status(c, ds);
+    if (st != NMF_OK) return st;
+    fill_stage1(c, ds, r);
+    return NMF_OK;
+}
+
+nmf_status nmf_get_factors(nmf_ctx *c, double *X, double *Y) {
+    if (!c) return NMF_EINVAL;
+    if (c->stage == 2) {
+        nmf_status st = nmfk::ipm_export(c->ipm, c->p, c->stream);
+        if (st != NMF_OK) return fail(c, st, "stage-2 export failed");
+    }
+    HIPCHK(c, nmfk::launch_factor_out(c->K, c->p, c->io, c->io + (size_t)c->n * c->K, c->stream));
+    if (X) HIPCHK(c, hipMemcpyAsync(X, c->io, (size_t)c->n * c->K * 8, hipMemcpyDefault, c->stream));
+    if (Y)
+        HIPCHK(c, hipMemcpyAsync(Y, c->io + (size_t)c->n * c->K, (size_t)c->K * c->m * 8, hipMemcpyDefault,
+                                 c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NMF_OK;
+}
+
+nmf_status nmf_get_masks(nmf_ctx *c, uint32_t *xm, uint32_t *ym) {
+    if (!c) return NMF_EINVAL;
+    if (xm) HIPCHK(c, hipMemcpyAsync(xm, c->p.xmask, (size_t)c->n * 4, hipMemcpyDefault, c->stream));
+    if (ym) HIPCHK(c, hipMemcpyAsync(ym, c->p.ymask, (size_t)c->m * 4, hipMemcpyDefault, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NMF_OK;
+}
+
+nmf_status nmf_append_columns(nmf_ctx *c, const double *Mnew, int64_t mnew, int64_t ldm) {
+    if (!c) return NMF_EINVAL;
+    if (mnew < 0 || (mnew > 0 && !Mnew)) return fail(c, NMF_EINVAL, "bad new columns");
+    if (mnew == 0) return NMF_OK;
+    if (ldm < c->n) return fail(c, NMF_EINVAL, "ldm < n");
+    if (c->m + mnew > c->m_cap) return fail(c, NMF_ECAPACITY, "m_capacity exceeded");
+    hipStream_t s = c->stream;
+    double *dst = (double *)c->p.M + (size_t)c->p.ldM * c->m;
+    HIPCHK(c, hipMemcpy2DAsync(dst, (size_t)c->p.ldM * 8, Mnew, (size_t)ldm * 8, (size_t)c->n * 8,
+                               (size_t)mnew, hipMemcpyDefault, s));
+    HIPCHK(c, nmfk::launch_check_finite(dst, c->n, mnew, c->p.ldM, c->red, kRedBlocks, s));
+    std::vector<double> red(2 * kRedBlocks);
+    HIPCHK(c, hipMemcpyAsync(red.data(), c->red, red.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double add = 0.0, nbad = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) {
+        add += red[b];
+        nbad += red[kRedBlocks + b];
+    }
+    if (nbad > 0) return fail(c, NMF_EINVAL, "new columns have NaN or Inf entries");
+    if (c->stage == 2) {
+        nmf_status st = nmfk::ipm_export(c->ipm, c->p, s);
+        if (st != NMF_OK) return fail(c, st, "stage-2 export failed");
+        c->stage = 1;
+    }
+    const int64_t m_old = c->m;
+    c->mnorm2 += add;
+    HIPCHK(c, nmfk::launch_copy_columns_warm(c->K, c->p, m_old - 1, m_old, m_old + mnew, s));
+    c->m = m_old + mnew;
+    refresh_shape(c);
+    // the Y-half over all columns: the new ones start from their neighbour
+    AnlsParams p = c->p;
+    p.mode = 2;
+    HIPCHK(c, nmfk::launch_yhalf(c->K, p, s));
+    // the stop rule must be re-earned on the grown problem
+    const int zero = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->p.st->converged, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return NMF_OK;
+}
+
+nmf_status nmf_ipm_step(nmf_ctx *c, int32_t iters, nmf_report *r) {
+    if (!c) return NMF_EINVAL;
+    if (!c->opt.with_ipm) return fail(c, NMF_ESTATE, "context created without stage-2 workspace");
+    if (iters < 0) return fail(c, NMF_EINVAL, "iters < 0");
+    if (c->stage == 1) {
+        nmf_status st = nmfk::ipm_transition(c->ipm, c->p, c->opt, c->stream);
+        if (st != NMF_OK) return fail(c, st, nmfk::ipm_last_error(c->ipm));
+        c->stage = 2;
+    }
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    nmf_status st = nmfk::ipm_iterate(c->ipm, c->p, c->opt, iters, c->stream);
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCHK(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->ms2 += ms;
+    if (st != NMF_OK && st != NMF_CONVERGED && st != NMF_ENOTCONV)
+        return fail(c, st, nmfk::ipm_last_error(c->ipm));
+    if (r) {
+        memset(r, 0, sizeof(*r));
+        nmf_status rs = nmfk::ipm_report(c->ipm, r, c->ms1, c->ms2);
+        if (rs != NMF_OK) return fail(c, rs, "report failed");
+    }
+    return st;
+}
+
+nmf_status nmf_solve(nmf_ctx *c, nmf_report *r) {
+    if (!c) return NMF_EINVAL;
+    nmf_status st = NMF_OK;
+    if (c->stage == 1) {
+        DevStatus ds;
+        HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+        for (;;) {
+            st = enqueue_sweeps(c, c->opt.check_every);
+            if (st != NMF_OK) return st;
+            st = read_status(c, ds);
+            if (st != NMF_OK) return st;
+            if (ds.converged) break;
+        }
+        HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+        HIPCHK(c, hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        c->ms1 += ms;
+        if (!c->opt.with_ipm) {
+            if (r) return nmf_get_report(c, r);
+            return NMF_OK;
+        }
+    }
+    st = nmf_ipm_step(c, c->opt.max_ipm_iters, r);
+    return st;
+}
+
+}  // extern "C"
