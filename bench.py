@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the full two-stage solve")
+    ap.add_argument("--workload", default=WORKLOAD, help="named synthetic workload (default: the metric's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -89,7 +90,7 @@ def main():
     import torch
     from paper_2101_08431_amd import NMF, default_options, synth
 
-    M, X0, Y0 = synth.make(WORKLOAD, 0)
+    M, X0, Y0 = synth.make(args.workload, 0)
     n, m = M.shape
     k = X0.shape[1]
     Md = torch.from_numpy(np.ascontiguousarray(M.T)).cuda()   # resident in HBM
@@ -128,7 +129,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": n, "m": m, "k": k,
+        "config": {"workload": args.workload, "n": n, "m": m, "k": k,
                    "step": "one ANLS sweep (X-half + Y-half kernels), n + m NNLS solves",
                    "wall_ms_timed": wall_ms},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -84,6 +84,8 @@ typedef struct {
     int32_t check_every;          /* stage-1 sweeps enqueued between host reads of the stop rule (32) */
     int32_t gram_precision;       /* nmf_gram_precision (NMF_GRAM_FP64) */
     int32_t with_ipm;             /* 1: reserve workspace for stage 2 (mk x mk Schur matrix) */
+    int32_t x_splits;             /* stage-1 launch shape: column splits of the X-half (0 = automatic, <= 64) */
+    int32_t y_splits;             /* stage-1 launch shape: row splits of the Y-half (0 = automatic, <= 64) */
     uint64_t seed;                /* initial point when X0/Y0 are NULL */
 } nmf_options;
 

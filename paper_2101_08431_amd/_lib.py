@@ -34,6 +34,7 @@ class Options(ctypes.Structure):
         ("max_anls_sweeps", ctypes.c_int32), ("max_ipm_iters", ctypes.c_int32),
         ("max_backtracks", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("gram_precision", ctypes.c_int32), ("with_ipm", ctypes.c_int32),
+        ("x_splits", ctypes.c_int32), ("y_splits", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

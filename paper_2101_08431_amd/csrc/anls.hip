@@ -1,21 +1,24 @@
-// Stage 1 of the two-stage NMF: one ANLS sweep (Alg. 1) is two kernels.
+// Stage 1 of the two-stage NMF: one ANLS sweep (Alg. 1) is four kernels.
 //
-//   k_xhalf  X-half.  Grid (Tn row tiles of 64) x (Sx column chunks).  Each
-//            block streams its 64 x xcols slab of M once (coalesced 512-byte
-//            wave loads), forms its share of B_X = M Y^T, and writes it to a
-//            partial buffer.  The last block of a row tile to finish (device
-//            counter, release/acquire fences) sums the Sx partials in a fixed
-//            order, reduces G_Y = Y Y^T from the Y-half tile partials, measures
-//            the KKT parts of E(.;0) at the old point (r = max(graX, 0),
-//            Sec. V-A), and runs one warm-started NNLS per row (eq. (2) with
-//            C = Y^T).  It leaves tile partials of G_X = X^T X for the Y-half.
-//   k_yhalf  Y-half, the same pattern for B_Y = X^T M over row splits, with
-//            the NNLS of eq. (2) for C = X per column.  The last tile of the
-//            sweep reduces the tile statistics and applies the stop rule of
-//            Sec. IV on the device; later enqueued sweeps then return at once.
+//   k_xstream  B_X = M Y^T in split partials.  Grid (Tn tiles of 64 rows) x
+//              (Sx column splits); 8 waves per block, each wave a slice of
+//              the split's columns, eight 512-byte loads of M in flight per
+//              wave; Y for the split is staged in LDS.
+//   k_xnnls    one thread per row: sums the Sx partials in order, reduces
+//              G_Y = Y Y^T from the block partials of the last Y-half,
+//              measures the KKT parts of E(.;0) at the old point (r =
+//              max(graX, 0), Sec. V-A) and solves eq. (2) with C = Y^T by the
+//              warm-started active-set method.  Leaves block partials of the
+//              new G_X = X^T X.
+//   k_ystream  B_Y = X^T M in split partials.  Grid (Tm tiles of J = 64/K
+//              columns) x (Sy row splits); every lane accumulates J*K dot
+//              products and a wave transpose-reduce leaves one sum per lane.
+//   k_ynnls    one thread per column: eq. (2) with C = X; block partials of
+//              the new G_Y; the last block applies the stop rule of Sec. IV.
 //
-// Every reduction runs in a fixed order, so results are bitwise reproducible
-// from run to run and independent of block scheduling.
+// All hand-overs between blocks cross a kernel boundary, except the sweep
+// summary in k_ynnls (ceil(m/256) blocks).  Every sum runs in a fixed order,
+// so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -24,11 +27,8 @@
 
 namespace nmfk {
 
-__device__ __forceinline__ void release_fence() { __threadfence(); }
-
-// Increments a tile counter; returns true in the block that arrives last
-// (and resets the counter for the next launch).  All threads of the block
-// call it; the returned value is block-uniform.
+// Increments a counter; returns true in the block that arrives last (and
+// resets the counter).  All threads of the block call it.
 __device__ __forceinline__ bool last_arrival(unsigned *cnt, unsigned expected, unsigned *flag_lds) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -71,180 +71,203 @@ __device__ __forceinline__ double wave_transpose_reduce(double (&v)[YVALS], int 
     return v[0];
 }
 
-// Fixed-order sum of `cnt` records of `len` doubles (stride `len`) into out[0..len).
-__device__ __forceinline__ void reduce_records(const double *src, int cnt, int len, double *out) {
-    for (int q = threadIdx.x; q < len; q += blockDim.x) {
+// Fixed-order sum of `cnt` records of `len` doubles (stride `len`) into
+// out[0..len) (LDS), using the whole block: thread (q, g) sums the records
+// g, g + G, g + 2G, ... of entry q (G = blockDim / len groups), then the G
+// group sums are added in order.  `scratch` holds blockDim doubles of LDS.
+// Ends with a barrier.  len <= blockDim.
+__device__ __forceinline__ void reduce_records(const double *src, int cnt, int len, double *out,
+                                               double *scratch) {
+    const int G = (int)blockDim.x / len;
+    const int q = threadIdx.x % len, g = threadIdx.x / len;
+    if (g < G) {
         double acc = 0.0;
-        int t = 0;
-        for (; t + 4 <= cnt; t += 4) {
-            const double a0 = src[(size_t)(t + 0) * len + q];
-            const double a1 = src[(size_t)(t + 1) * len + q];
-            const double a2 = src[(size_t)(t + 2) * len + q];
-            const double a3 = src[(size_t)(t + 3) * len + q];
+        int t = g;
+        for (; t + 3 * G < cnt; t += 4 * G) {
+            const double a0 = src[(size_t)t * len + q];
+            const double a1 = src[(size_t)(t + G) * len + q];
+            const double a2 = src[(size_t)(t + 2 * G) * len + q];
+            const double a3 = src[(size_t)(t + 3 * G) * len + q];
             acc += a0;
             acc += a1;
             acc += a2;
             acc += a3;
         }
-        for (; t < cnt; ++t) acc += src[(size_t)t * len + q];
-        out[q] = acc;
+        for (; t < cnt; t += G) acc += src[(size_t)t * len + q];
+        scratch[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < len) {
+        double acc = 0.0;
+        for (int gg = 0; gg < G; ++gg) acc += scratch[gg * len + threadIdx.x];
+        out[threadIdx.x] = acc;
+    }
+    __syncthreads();
+}
+
+// Fixed-order tree sum of v over the block (blockDim = NTHR); lds holds NTHR.
+// The result is valid in thread 0.  Ends with a barrier.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int h = NTHR / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// Per-block statistics and the Gram partial of the new rows (columns).
+template <int K>
+__device__ __forceinline__ void block_stats_and_gram(const double (&st)[NST], const double (&xn)[K],
+                                                     double *stat_out, double *gram_out, double *lds,
+                                                     double *xs) {
+#pragma unroll
+    for (int q = 0; q < NST; ++q) {
+        const double v = block_sum(st[q], lds);
+        if (threadIdx.x == 0) stat_out[q] = v;
+    }
+    if (gram_out) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) xs[threadIdx.x * K + a] = xn[a];
+        __syncthreads();
+        for (int q = threadIdx.x; q < K * K; q += NTHR) {
+            const int a = q / K, c = q - a * K;
+            double v = 0.0;
+            for (int l = 0; l < NTHR; ++l) v = fma(xs[l * K + a], xs[l * K + c], v);
+            gram_out[q] = v;
+        }
     }
 }
 
 // ---------------------------------------------------------------- X-half
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_xhalf(AnlsParams p) {
+__global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) {
     if (p.mode == 0 && p.st->converged) return;
-    __shared__ double ys[XCHUNK * K];
-    __shared__ double red[4 * K * XTILE];
-    __shared__ double G[K * K];
-    __shared__ double xs[XTILE * K];
-    __shared__ double stl[NST * XTILE];
-    __shared__ unsigned flag;
-
+    constexpr int RED = SWAVES * K * XTILE;
+    constexpr int LDSN = (XCHUNK * K > RED) ? XCHUNK * K : RED;
+    __shared__ double lds[LDSN];   // Y chunk while streaming, then the wave sums
     const int tile = blockIdx.x, split = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = (int64_t)tile * XTILE + lane;
     const int64_t j0 = (int64_t)split * p.xcols;
     const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
+    const bool row_ok = i < p.n;
 
     double acc[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) acc[a] = 0.0;
-
     for (int64_t c0 = j0; c0 < j1; c0 += XCHUNK) {
         const int nc = (int)min((int64_t)XCHUNK, j1 - c0);
         __syncthreads();
-        for (int q = threadIdx.x; q < nc * K; q += NTHR) {
+        for (int q = threadIdx.x; q < nc * K; q += STHR) {
             const int jj = q / K, a = q - jj * K;
-            ys[q] = p.Y[(int64_t)a * p.ldY + c0 + jj];
+            lds[q] = p.Y[(int64_t)a * p.ldY + c0 + jj];
         }
         __syncthreads();
-        if (i < p.n) {
-            const double *mp = p.M + c0 * p.ldM + i;
-            int jj = w;
-            for (; jj + 12 < nc; jj += 16) {
-                const double m0 = mp[(int64_t)(jj + 0) * p.ldM];
-                const double m1 = mp[(int64_t)(jj + 4) * p.ldM];
-                const double m2 = mp[(int64_t)(jj + 8) * p.ldM];
-                const double m3 = mp[(int64_t)(jj + 12) * p.ldM];
+        const double *mp = p.M + c0 * p.ldM + (row_ok ? i : 0);
+        for (int jb = w; jb < nc; jb += 8 * SWAVES) {
+            double mv[8];
 #pragma unroll
-                for (int a = 0; a < K; ++a) {
-                    acc[a] = fma(m0, ys[(jj + 0) * K + a], acc[a]);
-                    acc[a] = fma(m1, ys[(jj + 4) * K + a], acc[a]);
-                    acc[a] = fma(m2, ys[(jj + 8) * K + a], acc[a]);
-                    acc[a] = fma(m3, ys[(jj + 12) * K + a], acc[a]);
-                }
+            for (int t = 0; t < 8; ++t) {
+                const int jj = jb + t * SWAVES;
+                mv[t] = (jj < nc && row_ok) ? mp[(int64_t)jj * p.ldM] : 0.0;
             }
-            for (; jj < nc; jj += 4) {
-                const double m0 = mp[(int64_t)jj * p.ldM];
 #pragma unroll
-                for (int a = 0; a < K; ++a) acc[a] = fma(m0, ys[jj * K + a], acc[a]);
+            for (int t = 0; t < 8; ++t) {
+                const int jj = jb + t * SWAVES;
+                if (jj < nc) {
+#pragma unroll
+                    for (int a = 0; a < K; ++a) acc[a] = fma(mv[t], lds[jj * K + a], acc[a]);
+                }
             }
         }
     }
-#pragma unroll
-    for (int a = 0; a < K; ++a) red[(w * K + a) * XTILE + lane] = acc[a];
     __syncthreads();
-    if (w == 0 && i < p.n) {
+#pragma unroll
+    for (int a = 0; a < K; ++a) lds[(w * K + a) * XTILE + lane] = acc[a];
+    __syncthreads();
+    if (w == 0 && row_ok) {
 #pragma unroll
         for (int a = 0; a < K; ++a) {
-            double v = red[(0 * K + a) * XTILE + lane];
-            v += red[(1 * K + a) * XTILE + lane];
-            v += red[(2 * K + a) * XTILE + lane];
-            v += red[(3 * K + a) * XTILE + lane];
+            double v = lds[(0 * K + a) * XTILE + lane];
+#pragma unroll
+            for (int ww = 1; ww < SWAVES; ++ww) v += lds[(ww * K + a) * XTILE + lane];
             p.bx_part[((int64_t)split * K + a) * p.ldX + i] = v;
-        }
-    }
-    if (!last_arrival(p.cnt_x + tile, (unsigned)p.Sx, &flag)) return;
-
-    // ---- last block of this row tile: G_Y, E parts, NNLS per row
-    reduce_records(p.gy_part, p.Tm, K * K, G);
-    __syncthreads();
-    if (w == 0) {
-        double gmax = 0.0;
-#pragma unroll
-        for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
-        double st[NST];
-#pragma unroll
-        for (int q = 0; q < NST; ++q) st[q] = 0.0;
-        double xn[K];
-#pragma unroll
-        for (int a = 0; a < K; ++a) xn[a] = 0.0;
-        if (i < p.n) {
-            double b[K], x[K];
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                double v = 0.0;
-                for (int s = 0; s < p.Sx; ++s) v += p.bx_part[((int64_t)s * K + a) * p.ldX + i];
-                b[a] = v;
-                x[a] = p.X[(int64_t)a * p.ldX + i];
-            }
-            // graX at the old point: (X Y Y^T - M Y^T)_i
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                double g = -b[a];
-#pragma unroll
-                for (int c = 0; c < K; ++c) g = fma(G[a * K + c], x[c], g);
-                if (g < 0.0) st[ST_EG2] += g * g;
-                else st[ST_EC2] += (g * x[a]) * (g * x[a]);
-            }
-            if (p.mode == 0) {
-                const uint32_t old_mask = p.xmask[i];
-#pragma unroll
-                for (int a = 0; a < K; ++a) {
-                    xn[a] = x[a];
-                    st[ST_NORM2] += x[a] * x[a];
-                }
-                const LhResult r = lh_warm<K>(G, gmax, b, xn);
-#pragma unroll
-                for (int a = 0; a < K; ++a) {
-                    const double d = xn[a] - x[a];
-                    st[ST_STEP2] += d * d;
-                    p.X[(int64_t)a * p.ldX + i] = xn[a];
-                }
-                p.xmask[i] = r.P;
-                st[ST_SOLVES] = r.solves;
-                st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
-                st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
-            } else {
-#pragma unroll
-                for (int a = 0; a < K; ++a) xn[a] = x[a];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < NST; ++q) stl[q * XTILE + lane] = st[q];
-#pragma unroll
-        for (int a = 0; a < K; ++a) xs[lane * K + a] = xn[a];
-    }
-    __syncthreads();
-    if (threadIdx.x < NST) {
-        double v = 0.0;
-        for (int l = 0; l < XTILE; ++l) v += stl[threadIdx.x * XTILE + l];
-        p.xstat[(int64_t)tile * NST + threadIdx.x] = v;
-    }
-    if (p.mode == 0) {
-        for (int q = threadIdx.x; q < K * K; q += NTHR) {
-            const int a = q / K, c = q - a * K;
-            double v = 0.0;
-            for (int l = 0; l < XTILE; ++l) v = fma(xs[l * K + a], xs[l * K + c], v);
-            p.gx_part[(int64_t)tile * K * K + q] = v;
         }
     }
 }
 
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) {
+    if (p.mode == 0 && p.st->converged) return;
+    __shared__ double G[K * K];
+    __shared__ double lds[NTHR];
+    __shared__ double xs[NTHR * K];
+    reduce_records(p.gy_part, p.By, K * K, G, lds);
+    const int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    double st[NST];
+#pragma unroll
+    for (int q = 0; q < NST; ++q) st[q] = 0.0;
+    double xn[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) xn[a] = 0.0;
+    if (i < p.n) {
+        double gmax = 0.0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
+        double b[K], x[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            b[a] = 0.0;
+            x[a] = p.X[(int64_t)a * p.ldX + i];
+        }
+        for (int s = 0; s < p.Sx; ++s) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) b[a] += p.bx_part[((int64_t)s * K + a) * p.ldX + i];
+        }
+        // graX at the old point: (X Y Y^T - M Y^T)_i
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            double g = -b[a];
+#pragma unroll
+            for (int c = 0; c < K; ++c) g = fma(G[a * K + c], x[c], g);
+            if (g < 0.0) st[ST_EG2] += g * g;
+            else st[ST_EC2] += (g * x[a]) * (g * x[a]);
+        }
+        if (p.mode == 0) {
+            const uint32_t old_mask = p.xmask[i];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                xn[a] = x[a];
+                st[ST_NORM2] += x[a] * x[a];
+            }
+            const LhResult r = lh_warm<K>(G, gmax, b, xn);
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const double d = xn[a] - x[a];
+                st[ST_STEP2] += d * d;
+                p.X[(int64_t)a * p.ldX + i] = xn[a];
+            }
+            p.xmask[i] = r.P;
+            st[ST_SOLVES] = r.solves;
+            st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
+            st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
+        }
+    }
+    block_stats_and_gram<K>(st, xn, p.xstat + (int64_t)blockIdx.x * NST,
+                            p.mode == 0 ? p.gx_part + (int64_t)blockIdx.x * K * K : nullptr, lds, xs);
+}
+
 // ---------------------------------------------------------------- Y-half
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_yhalf(AnlsParams p) {
+__global__ __launch_bounds__(STHR) void k_ystream(AnlsParams p) {
     if (p.mode == 0 && p.st->converged) return;
     constexpr int J = YVALS / K;
-    __shared__ double red[4 * YVALS];
-    __shared__ double G[K * K];
-    __shared__ double bsum[YVALS];
-    __shared__ double ysn[J * K];
-    __shared__ double stl[NST * J];
-    __shared__ unsigned flag;
-
+    __shared__ double red[SWAVES * YVALS];
     const int ct = blockIdx.x, split = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t jb = (int64_t)ct * J;
@@ -255,150 +278,133 @@ __global__ __launch_bounds__(NTHR) void k_yhalf(AnlsParams p) {
     double v[YVALS];
 #pragma unroll
     for (int q = 0; q < YVALS; ++q) v[q] = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += NTHR) {
-        double x[K];
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += STHR) {
+        double x[K], mv[J];
 #pragma unroll
         for (int a = 0; a < K; ++a) x[a] = p.X[(int64_t)a * p.ldX + i];
         const double *mp = p.M + jb * p.ldM + i;
 #pragma unroll
+        for (int jj = 0; jj < J; ++jj) mv[jj] = (jj < nj) ? mp[(int64_t)jj * p.ldM] : 0.0;
+#pragma unroll
         for (int jj = 0; jj < J; ++jj) {
-            if (jj < nj) {
-                const double mv = mp[(int64_t)jj * p.ldM];
 #pragma unroll
-                for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv, x[a], v[jj * K + a]);
-            }
+            for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
         }
     }
-    const double mine = wave_transpose_reduce(v, lane);
-    red[w * YVALS + lane] = mine;
+    red[w * YVALS + lane] = wave_transpose_reduce(v, lane);
     __syncthreads();
-    if (threadIdx.x < YVALS) {
-        double s = red[0 * YVALS + threadIdx.x];
-        s += red[1 * YVALS + threadIdx.x];
-        s += red[2 * YVALS + threadIdx.x];
-        s += red[3 * YVALS + threadIdx.x];
-        p.by_part[((int64_t)ct * p.Sy + split) * YVALS + threadIdx.x] = s;
-    }
-    if (!last_arrival(p.cnt_y + ct, (unsigned)p.Sy, &flag)) return;
-
-    // ---- last block of this column tile: G_X, NNLS per column
-    reduce_records(p.gx_part, p.Tn, K * K, G);
-    if (threadIdx.x < YVALS) {
-        double s = 0.0;
-        for (int sp = 0; sp < p.Sy; ++sp) s += p.by_part[((int64_t)ct * p.Sy + sp) * YVALS + threadIdx.x];
-        bsum[threadIdx.x] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < J) {
-        const int jj = threadIdx.x;
-        double st[NST];
+    if ((int)threadIdx.x < nj * K) {
+        double s = red[threadIdx.x];
 #pragma unroll
-        for (int q = 0; q < NST; ++q) st[q] = 0.0;
-        double yn[K];
-#pragma unroll
-        for (int a = 0; a < K; ++a) yn[a] = 0.0;
-        if (jj < nj) {
-            const int64_t j = jb + jj;
-            double gmax = 0.0;
-#pragma unroll
-            for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
-            double b[K], y[K];
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                b[a] = bsum[jj * K + a];
-                y[a] = p.Y[(int64_t)a * p.ldY + j];
-                yn[a] = y[a];
-                st[ST_NORM2] += y[a] * y[a];
-            }
-            const uint32_t old_mask = p.ymask[j];
-            const LhResult r = lh_warm<K>(G, gmax, b, yn);
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                const double d = yn[a] - y[a];
-                st[ST_STEP2] += d * d;
-                p.Y[(int64_t)a * p.ldY + j] = yn[a];
-            }
-            p.ymask[j] = r.P;
-            // graY at the new point: (X^T X Y - X^T M)_j, the Y part of E(.;0)
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                double g = -b[a];
-#pragma unroll
-                for (int c = 0; c < K; ++c) g = fma(G[a * K + c], yn[c], g);
-                if (g < 0.0) st[ST_EG2] += g * g;
-                else st[ST_EC2] += (g * yn[a]) * (g * yn[a]);
-            }
-            st[ST_SOLVES] = r.solves;
-            st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
-            st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < NST; ++q) stl[q * J + jj] = st[q];
-#pragma unroll
-        for (int a = 0; a < K; ++a) ysn[jj * K + a] = yn[a];
-    }
-    __syncthreads();
-    if (threadIdx.x < NST) {
-        double s = 0.0;
-        for (int l = 0; l < J; ++l) s += stl[threadIdx.x * J + l];
-        p.ystat[(int64_t)ct * NST + threadIdx.x] = s;
-    }
-    for (int q = threadIdx.x; q < K * K; q += NTHR) {
-        const int a = q / K, c = q - a * K;
-        double s = 0.0;
-        for (int l = 0; l < J; ++l) s = fma(ysn[l * K + a], ysn[l * K + c], s);
-        p.gy_part[(int64_t)ct * K * K + q] = s;
-    }
-    if (!last_arrival(p.cnt_fin, (unsigned)p.Tm, &flag)) return;
-
-    // ---- last tile of the sweep: statistics and the Sec. IV stop rule
-    __shared__ double sx[NST], sy[NST];
-    reduce_records(p.xstat, p.Tn, NST, sx);
-    reduce_records(p.ystat, p.Tm, NST, sy);
-    __syncthreads();
-    if (threadIdx.x == 0 && p.mode == 2) {
-        // appended columns solved: Y part of E, counters; no sweep, no stop test
-        DevStatus *st = p.st;
-        st->ey_g2 = sy[ST_EG2];
-        st->ey_c2 = sy[ST_EC2];
-        st->E_cur = -1.0;
-        st->solves += sy[ST_SOLVES];
-        st->fails += sy[ST_FAILS];
-        st->changes += sy[ST_CHANGES];
-    } else if (threadIdx.x == 0) {
-        DevStatus *st = p.st;
-        const double step2 = sx[ST_STEP2] + sy[ST_STEP2];
-        const double norm2 = sx[ST_NORM2] + sy[ST_NORM2];
-        st->step2 = step2;
-        st->norm2 = norm2;
-        st->ex_g2 = sx[ST_EG2];
-        st->ex_c2 = sx[ST_EC2];
-        if (st->ey_g2 >= 0.0) {
-            const double eg = sqrt(sx[ST_EG2] + st->ey_g2);
-            const double ec = sqrt(sx[ST_EC2] + st->ey_c2);
-            st->E_prev = eg > ec ? eg : ec;
-        }
-        st->ey_g2_prev = st->ey_g2;
-        st->ey_c2_prev = st->ey_c2;
-        st->ey_g2 = sy[ST_EG2];
-        st->ey_c2 = sy[ST_EC2];
-        st->E_cur = -1.0;
-        st->solves += sx[ST_SOLVES] + sy[ST_SOLVES];
-        st->fails += sx[ST_FAILS] + sy[ST_FAILS];
-        st->changes += sx[ST_CHANGES] + sy[ST_CHANGES];
-        st->sweeps += 1;
-        if (sqrt(step2) <= st->eps_stol * (1.0 + sqrt(norm2)) || st->sweeps >= st->max_sweeps)
-            st->converged = 1;
+        for (int ww = 1; ww < SWAVES; ++ww) s += red[ww * YVALS + threadIdx.x];
+        const int jj = threadIdx.x / K, a = threadIdx.x - jj * K;
+        p.by_part[((int64_t)split * K + a) * p.ldY + jb + jj] = s;
     }
 }
 
-// E(.;0) at the current iterate after a measure-mode X-half: X part from the
-// tile records, Y part from the last Y-half.
 template <int K>
-__global__ void k_measure_finish(AnlsParams p) {
+__global__ __launch_bounds__(NTHR) void k_ynnls(AnlsParams p) {
+    if (p.mode == 0 && p.st->converged) return;
+    __shared__ double G[K * K];
+    __shared__ double lds[NTHR];
+    __shared__ double xs[NTHR * K];
+    __shared__ unsigned flag;
+    reduce_records(p.gx_part, p.Bx, K * K, G, lds);
+    const int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    double st[NST];
+#pragma unroll
+    for (int q = 0; q < NST; ++q) st[q] = 0.0;
+    double yn[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) yn[a] = 0.0;
+    if (j < p.m) {
+        double gmax = 0.0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
+        double b[K], y[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            b[a] = 0.0;
+            y[a] = p.Y[(int64_t)a * p.ldY + j];
+            yn[a] = y[a];
+            st[ST_NORM2] += y[a] * y[a];
+        }
+        for (int s = 0; s < p.Sy; ++s) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) b[a] += p.by_part[((int64_t)s * K + a) * p.ldY + j];
+        }
+        const uint32_t old_mask = p.ymask[j];
+        const LhResult r = lh_warm<K>(G, gmax, b, yn);
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const double d = yn[a] - y[a];
+            st[ST_STEP2] += d * d;
+            p.Y[(int64_t)a * p.ldY + j] = yn[a];
+        }
+        p.ymask[j] = r.P;
+        // graY at the new point: (X^T X Y - X^T M)_j, the Y part of E(.;0)
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            double g = -b[a];
+#pragma unroll
+            for (int c = 0; c < K; ++c) g = fma(G[a * K + c], yn[c], g);
+            if (g < 0.0) st[ST_EG2] += g * g;
+            else st[ST_EC2] += (g * yn[a]) * (g * yn[a]);
+        }
+        st[ST_SOLVES] = r.solves;
+        st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
+        st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
+    }
+    block_stats_and_gram<K>(st, yn, p.ystat + (int64_t)blockIdx.x * NST, p.gy_part + (int64_t)blockIdx.x * K * K,
+                            lds, xs);
+    if (!last_arrival(p.cnt_fin, (unsigned)p.By, &flag)) return;
+
+    // ---- last block of the sweep: statistics and the Sec. IV stop rule
+    __shared__ double sx[NST], sy[NST];
+    reduce_records(p.xstat, p.Bx, NST, sx, lds);
+    reduce_records(p.ystat, p.By, NST, sy, lds);
+    if (threadIdx.x == 0 && p.mode == 2) {
+        // appended columns solved: Y part of E, counters; no sweep, no stop test
+        DevStatus *s = p.st;
+        s->ey_g2 = sy[ST_EG2];
+        s->ey_c2 = sy[ST_EC2];
+        s->E_cur = -1.0;
+        s->solves += sy[ST_SOLVES];
+        s->fails += sy[ST_FAILS];
+        s->changes += sy[ST_CHANGES];
+    } else if (threadIdx.x == 0) {
+        DevStatus *s = p.st;
+        const double step2 = sx[ST_STEP2] + sy[ST_STEP2];
+        const double norm2 = sx[ST_NORM2] + sy[ST_NORM2];
+        s->step2 = step2;
+        s->norm2 = norm2;
+        s->ex_g2 = sx[ST_EG2];
+        s->ex_c2 = sx[ST_EC2];
+        if (s->ey_g2 >= 0.0) {
+            const double eg = sqrt(sx[ST_EG2] + s->ey_g2);
+            const double ec = sqrt(sx[ST_EC2] + s->ey_c2);
+            s->E_prev = eg > ec ? eg : ec;
+        }
+        s->ey_g2_prev = s->ey_g2;
+        s->ey_c2_prev = s->ey_c2;
+        s->ey_g2 = sy[ST_EG2];
+        s->ey_c2 = sy[ST_EC2];
+        s->E_cur = -1.0;
+        s->solves += sx[ST_SOLVES] + sy[ST_SOLVES];
+        s->fails += sx[ST_FAILS] + sy[ST_FAILS];
+        s->changes += sx[ST_CHANGES] + sy[ST_CHANGES];
+        s->sweeps += 1;
+        if (sqrt(step2) <= s->eps_stol * (1.0 + sqrt(norm2)) || s->sweeps >= s->max_sweeps) s->converged = 1;
+    }
+}
+
+// E(.;0) at the current iterate after a measure-mode k_xnnls: X part from the
+// block records, Y part from the last Y-half.
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_measure_finish(AnlsParams p) {
     __shared__ double sx[NST];
-    reduce_records(p.xstat, p.Tn, NST, sx);
-    __syncthreads();
+    __shared__ double scr[NTHR];
+    reduce_records(p.xstat, p.Bx, NST, sx, scr);
     if (threadIdx.x == 0) {
         DevStatus *st = p.st;
         const double yg = st->ey_g2 >= 0.0 ? st->ey_g2 : 0.0;
@@ -409,19 +415,19 @@ __global__ void k_measure_finish(AnlsParams p) {
     }
 }
 
-// G_Y partials from the current Y, in the Y-half tile layout.
+// G_Y block partials from the current Y, in the k_ynnls block layout.
 template <int K>
-__global__ void k_gram_y_init(AnlsParams p) {
-    constexpr int J = YVALS / K;
-    const int ct = blockIdx.x;
-    const int64_t jb = (int64_t)ct * J;
-    const int nj = (int)min((int64_t)J, p.m - jb);
-    for (int q = threadIdx.x; q < K * K; q += blockDim.x) {
+__global__ __launch_bounds__(NTHR) void k_gram_y_init(AnlsParams p) {
+    __shared__ double ys[NTHR * K];
+    const int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < K; ++a) ys[threadIdx.x * K + a] = j < p.m ? p.Y[(int64_t)a * p.ldY + j] : 0.0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < K * K; q += NTHR) {
         const int a = q / K, c = q - a * K;
-        double s = 0.0;
-        for (int l = 0; l < nj; ++l)
-            s = fma(p.Y[(int64_t)a * p.ldY + jb + l], p.Y[(int64_t)c * p.ldY + jb + l], s);
-        p.gy_part[(int64_t)ct * K * K + q] = s;
+        double v = 0.0;
+        for (int l = 0; l < NTHR; ++l) v = fma(ys[l * K + a], ys[l * K + c], v);
+        p.gy_part[(int64_t)blockIdx.x * K * K + q] = v;
     }
 }
 
@@ -562,16 +568,34 @@ __global__ void k_copy_columns_warm(AnlsParams p, int64_t j_from, int64_t j0, in
 
 int yhalf_cols(int K) { return K >= 1 && K <= KMAX ? YVALS / K : 0; }
 
-hipError_t launch_xhalf(int K, const AnlsParams &p, hipStream_t s) {
-    dim3 grid(p.Tn, p.Sx);
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_xhalf<KK>, grid, dim3(NTHR), 0, s, p));
+hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_xstream<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, s, p));
     return hipGetLastError();
 }
 
-hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s) {
-    dim3 grid(p.Tm, p.Sy);
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_yhalf<KK>, grid, dim3(NTHR), 0, s, p));
+hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_xnnls<KK>, dim3(p.Bx), dim3(NTHR), 0, s, p));
     return hipGetLastError();
+}
+
+hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_ystream<KK>, dim3(p.Tm, p.Sy), dim3(STHR), 0, s, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_ynnls<KK>, dim3(p.By), dim3(NTHR), 0, s, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_xhalf(int K, const AnlsParams &p, hipStream_t s) {
+    hipError_t e = launch_xstream(K, p, s);
+    return e != hipSuccess ? e : launch_xnnls(K, p, s);
+}
+
+hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s) {
+    hipError_t e = launch_ystream(K, p, s);
+    return e != hipSuccess ? e : launch_ynnls(K, p, s);
 }
 
 hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s) {
@@ -580,7 +604,7 @@ hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s) {
 }
 
 hipError_t launch_gram_y_init(int K, const AnlsParams &p, hipStream_t s) {
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_y_init<KK>, dim3(p.Tm), dim3(NTHR), 0, s, p));
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_y_init<KK>, dim3(p.By), dim3(NTHR), 0, s, p));
     return hipGetLastError();
 }
 

@@ -29,28 +29,33 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Plan {
     int64_t ldM, ldX, ldY;
-    int Tn, Sx, xcols, Sy, yrows, Tm, J;
+    int Tn, Sx, xcols, Sy, yrows, Tm, J, Bx, By;
 };
 
-// Stage-1 launch shape.  X-half: one tile per 64 rows, column splits so that
-// the grid holds ~2048 blocks and a block streams >= 16 columns.  Y-half: J =
-// 64/K columns per tile, row splits of >= 2048 rows (8 rows per thread).
-Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K) {
+// Stage-1 launch shape.  X stream: 64-row tiles, column splits so that about
+// 4096 waves stream M (8 per block).  Y stream: J = 64/K columns per tile, row
+// splits while every thread still covers >= 4 rows and the grid is short of
+// ~4096 waves.  NNLS kernels: 256 problems per block.
+Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, int y_splits = 0) {
     Plan P;
     P.ldM = align_up((size_t)n, 32);
     P.ldX = align_up((size_t)n, 64);
     P.ldY = align_up((size_t)m_cap, 64);
     P.Tn = (int)ceil_div(n, nmfk::XTILE);
-    int64_t sx = ceil_div(2048, P.Tn);
-    sx = std::min<int64_t>(sx, std::max<int64_t>(1, ceil_div(m, 16)));
-    sx = std::max<int64_t>(1, std::min<int64_t>(sx, kSxMax));
+    int64_t sx = ceil_div(4096, (int64_t)P.Tn * nmfk::SWAVES);
+    if (x_splits > 0) sx = x_splits;
+    sx = std::max<int64_t>(1, std::min<int64_t>(sx, std::min<int64_t>(kSxMax, m)));
     P.xcols = (int)ceil_div(m, sx);
     P.Sx = (int)ceil_div(m, P.xcols);
-    int64_t sy = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 2048), kSyMax));
-    P.yrows = (int)ceil_div(n, sy);
-    P.Sy = (int)ceil_div(n, P.yrows);
     P.J = nmfk::yhalf_cols(K);
     P.Tm = (int)ceil_div(m, P.J);
+    int64_t sy = std::min<int64_t>(ceil_div(4096, (int64_t)P.Tm * nmfk::SWAVES), n / (4 * nmfk::STHR));
+    if (y_splits > 0) sy = y_splits;
+    sy = std::max<int64_t>(1, std::min<int64_t>(sy, std::min<int64_t>(kSyMax, n)));
+    P.yrows = (int)ceil_div(n, sy);
+    P.Sy = (int)ceil_div(n, P.yrows);
+    P.Bx = (int)ceil_div(n, nmfk::NTHR);
+    P.By = (int)ceil_div(m, nmfk::NTHR);
     return P;
 }
 
@@ -65,13 +70,13 @@ struct Carve {
 };
 
 struct Offsets {
-    size_t M, X, Y, xmask, ymask, bx, by, gx, gy, xst, yst, cntx, cnty, cntf, status, red, io, bad;
+    size_t M, X, Y, xmask, ymask, bx, by, gx, gy, xst, yst, cntf, status, red, io, bad;
     size_t ipm_base, total;
 };
 
 Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
-    const Plan P = plan_shape(n, m_cap, m_cap, K);
-    const int64_t TmMax = ceil_div(m_cap, P.J);
+    const Plan P = plan_shape(n, m_cap, m_cap, K, o.x_splits, o.y_splits);
+    const int64_t ByMax = ceil_div(m_cap, nmfk::NTHR);
     Offsets L;
     Carve c;
     L.M = c.take<double>((size_t)P.ldM * m_cap);
@@ -80,13 +85,11 @@ Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
     L.xmask = c.take<uint32_t>(P.ldX);
     L.ymask = c.take<uint32_t>(P.ldY);
     L.bx = c.take<double>((size_t)kSxMax * K * P.ldX);
-    L.by = c.take<double>((size_t)TmMax * P.Sy * nmfk::YVALS);
-    L.gx = c.take<double>((size_t)P.Tn * K * K);
-    L.gy = c.take<double>((size_t)TmMax * K * K);
-    L.xst = c.take<double>((size_t)P.Tn * nmfk::NST);
-    L.yst = c.take<double>((size_t)TmMax * nmfk::NST);
-    L.cntx = c.take<unsigned>(P.Tn);
-    L.cnty = c.take<unsigned>(TmMax);
+    L.by = c.take<double>((size_t)kSyMax * K * P.ldY);   // Sy varies with m; <= kSyMax
+    L.gx = c.take<double>((size_t)P.Bx * K * K);
+    L.gy = c.take<double>((size_t)ByMax * K * K);
+    L.xst = c.take<double>((size_t)P.Bx * nmfk::NST);
+    L.yst = c.take<double>((size_t)ByMax * nmfk::NST);
     L.cntf = c.take<unsigned>(4);
     L.status = c.take<DevStatus>(1);
     L.red = c.take<double>(2 * kRedBlocks);
@@ -137,7 +140,7 @@ static nmf_status hip_fail(nmf_ctx *c, hipError_t e, const char *what) {
     } while (0)
 
 static void refresh_shape(nmf_ctx *c) {
-    c->plan = plan_shape(c->n, c->m, c->m_cap, c->K);
+    c->plan = plan_shape(c->n, c->m, c->m_cap, c->K, c->opt.x_splits, c->opt.y_splits);
     AnlsParams &p = c->p;
     p.n = c->n;
     p.m = c->m;
@@ -147,6 +150,8 @@ static void refresh_shape(nmf_ctx *c) {
     p.Sy = c->plan.Sy;
     p.Tm = c->plan.Tm;
     p.yrows = c->plan.yrows;
+    p.Bx = c->plan.Bx;
+    p.By = c->plan.By;
 }
 
 extern "C" {
@@ -231,7 +236,8 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
     nmf_options o;
     if (opts) o = *opts;
     else nmf_default_options(&o);
-    if (o.inner_cap < 1 || o.check_every < 1 || !(o.tau > 0 && o.tau < 1) || !(o.eta > 0 && o.eta < 1))
+    if (o.inner_cap < 1 || o.check_every < 1 || !(o.tau > 0 && o.tau < 1) || !(o.eta > 0 && o.eta < 1) ||
+        o.x_splits < 0 || o.x_splits > kSxMax || o.y_splits < 0 || o.y_splits > kSyMax)
         return fail(nullptr, NMF_EINVAL, "invalid options");
     if (o.gram_precision != NMF_GRAM_FP64)
         return fail(nullptr, NMF_EINVAL, "only NMF_GRAM_FP64 is available in this build");
@@ -265,8 +271,6 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
     p.gy_part = (double *)(w + L.gy);
     p.xstat = (double *)(w + L.xst);
     p.ystat = (double *)(w + L.yst);
-    p.cnt_x = (unsigned *)(w + L.cntx);
-    p.cnt_y = (unsigned *)(w + L.cnty);
     p.cnt_fin = (unsigned *)(w + L.cntf);
     p.st = (DevStatus *)(w + L.status);
     c->red = (double *)(w + L.red);
@@ -431,7 +435,7 @@ nmf_status nmf_anls_profile(nmf_ctx *c, int32_t sweeps, double *ms_x, double *ms
     if (!c) return NMF_EINVAL;
     if (sweeps < 1) return fail(c, NMF_EINVAL, "sweeps < 1");
     if (c->stage != 1) return fail(c, NMF_ESTATE, "stage 2 has started");
-    std::vector<hipEvent_t> ev(4 * (size_t)sweeps, nullptr);
+    std::vector<hipEvent_t> ev(4 * (size_t)sweeps, nullptr);   // around each half (stream + NNLS kernel)
     nmf_status st = NMF_OK;
     for (auto &e : ev) {
         if (hipEventCreate(&e) != hipSuccess) { st = fail(c, NMF_EDEVICE, "hipEventCreate failed"); break; }

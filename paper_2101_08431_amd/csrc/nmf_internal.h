@@ -13,13 +13,15 @@
 namespace nmfk {
 
 constexpr int KMAX = 16;
-constexpr int NTHR = 256;      // threads per block (4 waves of 64)
-constexpr int XTILE = 64;      // rows of X per X-half tile (one row per lane)
-constexpr int YVALS = 64;      // J*K partial sums per Y-half tile, padded to a wave
-constexpr int NST = 8;         // doubles per tile statistics record
+constexpr int NTHR = 256;      // threads of the NNLS kernels (one problem per thread)
+constexpr int SWAVES = 8;      // waves of the streaming kernels
+constexpr int STHR = 64 * SWAVES;
+constexpr int XTILE = 64;      // rows of M per X-stream tile (one row per lane)
+constexpr int YVALS = 64;      // J*K partial sums per Y-stream column tile, padded to a wave
+constexpr int NST = 8;         // doubles per block statistics record
 constexpr int XCHUNK = 256;    // columns of Y staged in LDS at a time
 
-// Tile statistics record (per X-half or Y-half tile)
+// Block statistics record of the NNLS kernels
 enum { ST_STEP2 = 0, ST_NORM2 = 1, ST_EG2 = 2, ST_EC2 = 3, ST_SOLVES = 4, ST_FAILS = 5,
        ST_CHANGES = 6, ST_SPARE = 7 };
 
@@ -38,30 +40,35 @@ struct DevStatus {
     double f_direct;              // 1/2 ||XY - M||^2 from the last direct pass
 };
 
-// Parameters of the stage-1 kernels.
+// Parameters of the stage-1 kernels.  One sweep = k_xstream, k_xnnls,
+// k_ystream, k_ynnls; every hand-over between blocks crosses a kernel
+// boundary except the sweep summary at the end of k_ynnls.
 struct AnlsParams {
     int64_t n, m, ldM, ldX, ldY;
     const double *M;
     double *X, *Y;
     uint32_t *xmask, *ymask;
-    double *bx_part;   // [Sx][K][ldX]
-    double *by_part;   // [Tm][Sy][YVALS]
-    double *gx_part;   // [Tn][K*K]
-    double *gy_part;   // [Tm][K*K]
-    double *xstat;     // [Tn][NST]
-    double *ystat;     // [Tm][NST]
-    unsigned *cnt_x;   // [Tn]
-    unsigned *cnt_y;   // [Tm]
+    double *bx_part;   // [Sx][K][ldX]  split partials of B_X = M Y^T
+    double *by_part;   // [Sy][K][ldY]  split partials of B_Y = X^T M (as B_Y^T)
+    double *gx_part;   // [Bx][K*K]     block partials of G_X = X^T X (new X)
+    double *gy_part;   // [By][K*K]     block partials of G_Y = Y Y^T (new Y)
+    double *xstat;     // [Bx][NST]
+    double *ystat;     // [By][NST]
     unsigned *cnt_fin; // [4]
     DevStatus *st;
-    int Sx, Tn, xcols;
-    int Sy, Tm, yrows;
-    int mode;          // X-half: 0 = solve, 1 = measure E only; Y-half: 0 = sweep, 2 = appended columns
+    int Sx, Tn, xcols; // X stream: Tn row tiles x Sx column splits of xcols columns
+    int Sy, Tm, yrows; // Y stream: Tm column tiles x Sy row splits of yrows rows
+    int Bx, By;        // NNLS blocks: ceil(n / 256), ceil(m / 256)
+    int mode;          // X: 0 = solve, 1 = measure E only; Y: 0 = sweep, 2 = appended columns
 };
 
 // Launchers (anls.hip).  All enqueue on `s` and return hipSuccess or an error.
-hipError_t launch_xhalf(int K, const AnlsParams &p, hipStream_t s);
-hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s);
+hipError_t launch_xhalf(int K, const AnlsParams &p, hipStream_t s);   // k_xstream + k_xnnls
+hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s);   // k_ystream + k_ynnls
+hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s);
+hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s);
+hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s);
+hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_gram_y_init(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_objective(int K, const AnlsParams &p, double *part, int nblk, hipStream_t s);
@@ -73,6 +80,6 @@ hipError_t launch_factor_out(int K, const AnlsParams &p, double *dst_x, double *
 hipError_t launch_copy_columns_warm(int K, const AnlsParams &p, int64_t j_from, int64_t j0,
                                     int64_t j1, hipStream_t s);
 
-int yhalf_cols(int K);   // columns per Y-half tile, J = YVALS / K
+int yhalf_cols(int K);   // columns per Y-stream tile, J = YVALS / K
 
 }  // namespace nmfk
