@@ -105,41 +105,54 @@ __device__ __forceinline__ void reduce_records(const double *src, int cnt, int l
     __syncthreads();
 }
 
-// Fixed-order tree sum of v over the block (blockDim = NTHR); lds holds NTHR.
-// The result is valid in thread 0.  Ends with a barrier.
-__device__ __forceinline__ double block_sum(double v, double *lds) {
-    lds[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int h = NTHR / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
-        __syncthreads();
-    }
-    const double r = lds[0];
-    __syncthreads();
-    return r;
-}
-
-// Per-block statistics and the Gram partial of the new rows (columns).
+// Per-block statistics and the Gram partial of the new rows (columns): the
+// NST statistics and the upper triangle of x x^T ride in one vector of
+// K(K+1)/2 + NST values per thread, summed over each wave by transpose-reduce
+// passes of 64 values and then over the four waves in order.  lds holds
+// 4 * 64 doubles.  All threads of the block call it.
 template <int K>
 __device__ __forceinline__ void block_stats_and_gram(const double (&st)[NST], const double (&xn)[K],
-                                                     double *stat_out, double *gram_out, double *lds,
-                                                     double *xs) {
+                                                     double *stat_out, double *gram_out, double *lds) {
+    constexpr int NG = K * (K + 1) / 2;
+    constexpr int V = NG + NST;
+    constexpr int NPASS = (V + YVALS - 1) / YVALS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double vals[NPASS * YVALS];
+    {
+        int q = 0;
 #pragma unroll
-    for (int q = 0; q < NST; ++q) {
-        const double v = block_sum(st[q], lds);
-        if (threadIdx.x == 0) stat_out[q] = v;
-    }
-    if (gram_out) {
+        for (int a = 0; a < K; ++a) {
 #pragma unroll
-        for (int a = 0; a < K; ++a) xs[threadIdx.x * K + a] = xn[a];
-        __syncthreads();
-        for (int q = threadIdx.x; q < K * K; q += NTHR) {
-            const int a = q / K, c = q - a * K;
-            double v = 0.0;
-            for (int l = 0; l < NTHR; ++l) v = fma(xs[l * K + a], xs[l * K + c], v);
-            gram_out[q] = v;
+            for (int c = 0; c <= a; ++c) vals[q++] = xn[a] * xn[c];
         }
+#pragma unroll
+        for (int t = 0; t < NST; ++t) vals[NG + t] = st[t];
+#pragma unroll
+        for (int t = V; t < NPASS * YVALS; ++t) vals[t] = 0.0;
+    }
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+        double v[YVALS];
+#pragma unroll
+        for (int q = 0; q < YVALS; ++q) v[q] = vals[pass * YVALS + q];
+        lds[w * YVALS + lane] = wave_transpose_reduce(v, lane);
+        __syncthreads();
+        const int idx = pass * YVALS + (int)threadIdx.x;
+        if ((int)threadIdx.x < YVALS && idx < V) {
+            double sum = lds[threadIdx.x];
+#pragma unroll
+            for (int ww = 1; ww < NTHR / 64; ++ww) sum += lds[ww * YVALS + threadIdx.x];
+            if (idx >= NG) {
+                stat_out[idx - NG] = sum;
+            } else if (gram_out) {
+                int a = 0;
+                while ((a + 1) * (a + 2) / 2 <= idx) ++a;
+                const int c = idx - a * (a + 1) / 2;
+                gram_out[a * K + c] = sum;
+                gram_out[c * K + a] = sum;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -206,7 +219,6 @@ __global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) {
     if (p.mode == 0 && p.st->converged) return;
     __shared__ double G[K * K];
     __shared__ double lds[NTHR];
-    __shared__ double xs[NTHR * K];
     reduce_records(p.gy_part, p.By, K * K, G, lds);
     const int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x;
     double st[NST];
@@ -259,7 +271,7 @@ __global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) {
         }
     }
     block_stats_and_gram<K>(st, xn, p.xstat + (int64_t)blockIdx.x * NST,
-                            p.mode == 0 ? p.gx_part + (int64_t)blockIdx.x * K * K : nullptr, lds, xs);
+                            p.mode == 0 ? p.gx_part + (int64_t)blockIdx.x * K * K : nullptr, lds);
 }
 
 // ---------------------------------------------------------------- Y-half
@@ -307,7 +319,6 @@ __global__ __launch_bounds__(NTHR) void k_ynnls(AnlsParams p) {
     if (p.mode == 0 && p.st->converged) return;
     __shared__ double G[K * K];
     __shared__ double lds[NTHR];
-    __shared__ double xs[NTHR * K];
     __shared__ unsigned flag;
     reduce_records(p.gx_part, p.Bx, K * K, G, lds);
     const int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x;
@@ -356,7 +367,7 @@ __global__ __launch_bounds__(NTHR) void k_ynnls(AnlsParams p) {
         st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
     }
     block_stats_and_gram<K>(st, yn, p.ystat + (int64_t)blockIdx.x * NST, p.gy_part + (int64_t)blockIdx.x * K * K,
-                            lds, xs);
+                            lds);
     if (!last_arrival(p.cnt_fin, (unsigned)p.By, &flag)) return;
 
     // ---- last block of the sweep: statistics and the Sec. IV stop rule

@@ -47,11 +47,13 @@ __device__ __forceinline__ void put(double (&v)[K], int idx, double val) {
 }
 
 // z = (G masked to P)^-1 (b masked to P).  Returns false if a pivot on P is
-// not positive.
+// not positive.  The factor keeps the reciprocals of its diagonal, so a solve
+// costs K divisions.
 template <int K>
 __device__ __forceinline__ bool masked_solve(const double *G, const double (&b)[K], uint32_t P,
                                              double (&z)[K]) {
     double L[K * (K + 1) / 2];
+    double inv[K];
     bool ok = true;
 #pragma unroll
     for (int r = 0; r < K; ++r) {
@@ -64,9 +66,11 @@ __device__ __forceinline__ bool masked_solve(const double *G, const double (&b)[
             for (int q = 0; q < c; ++q) v -= L[r * (r + 1) / 2 + q] * L[c * (c + 1) / 2 + q];
             if (r == c) {
                 ok = ok && (v > 0.0);
-                L[r * (r + 1) / 2 + r] = sqrt(v > 0.0 ? v : 1.0);
+                const double d = sqrt(v > 0.0 ? v : 1.0);
+                L[r * (r + 1) / 2 + r] = d;
+                inv[r] = 1.0 / d;
             } else {
-                L[r * (r + 1) / 2 + c] = v / L[c * (c + 1) / 2 + c];
+                L[r * (r + 1) / 2 + c] = v * inv[c];
             }
         }
     }
@@ -76,14 +80,14 @@ __device__ __forceinline__ bool masked_solve(const double *G, const double (&b)[
         double v = ((P >> r) & 1u) ? b[r] : 0.0;
 #pragma unroll
         for (int q = 0; q < r; ++q) v -= L[r * (r + 1) / 2 + q] * t[q];
-        t[r] = v / L[r * (r + 1) / 2 + r];
+        t[r] = v * inv[r];
     }
 #pragma unroll
     for (int r = K - 1; r >= 0; --r) {
         double v = t[r];
 #pragma unroll
         for (int q = r + 1; q < K; ++q) v -= L[q * (q + 1) / 2 + r] * z[q];
-        z[r] = v / L[r * (r + 1) / 2 + r];
+        z[r] = v * inv[r];
     }
     return ok;
 }
