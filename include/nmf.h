@@ -157,6 +157,11 @@ nmf_status nmf_append_columns(nmf_ctx *ctx, const double *Mnew, int64_t mnew, in
  * row-major (host or device; either may be NULL).  Synchronises. */
 nmf_status nmf_get_factors(nmf_ctx *ctx, double *X, double *Y);
 
+/* Stage 2 only: copies the dual variables of eq. (3) at the current iterate,
+ * R as n x k row-major (r = vec(R^T)) and S as k x m row-major (s = vec(S)),
+ * host or device; either may be NULL.  NMF_ESTATE in stage 1. */
+nmf_status nmf_get_duals(nmf_ctx *ctx, double *R, double *S);
+
 /* Copies the stage-1 passive-set masks (bit a set when entry a is > 0) of the
  * n rows of X and the m columns of Y (host or device; either may be NULL). */
 nmf_status nmf_get_masks(nmf_ctx *ctx, uint32_t *xmask, uint32_t *ymask);

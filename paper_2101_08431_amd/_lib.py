@@ -22,6 +22,7 @@ EXPORTS = [
     "nmf_default_options", "nmf_workspace_bytes", "nmf_create", "nmf_anls_step", "nmf_ipm_step",
     "nmf_solve", "nmf_append_columns", "nmf_get_factors", "nmf_get_masks", "nmf_get_report",
     "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
+    "nmf_get_duals",
 ]
 
 
@@ -82,6 +83,8 @@ def load():
     L.nmf_append_columns.restype = ctypes.c_int
     L.nmf_get_factors.argtypes = [vp, vp, vp]
     L.nmf_get_factors.restype = ctypes.c_int
+    L.nmf_get_duals.argtypes = [vp, vp, vp]
+    L.nmf_get_duals.restype = ctypes.c_int
     L.nmf_get_masks.argtypes = [vp, vp, vp]
     L.nmf_get_masks.restype = ctypes.c_int
     L.nmf_get_report.argtypes = [vp, ctypes.POINTER(Report)]
@@ -230,6 +233,14 @@ class NMF:
         Y = np.empty((self.k, self.m))
         self._check(load().nmf_get_factors(self._ctx, _ptr(X), _ptr(Y)), ok=(NMF_OK,))
         return X, Y
+
+    def duals(self):
+        """Stage-2 duals (R (n, k), S (k, m)) as host numpy arrays."""
+        import numpy as np
+        R = np.empty((self.n, self.k))
+        S = np.empty((self.k, self.m))
+        self._check(load().nmf_get_duals(self._ctx, _ptr(R), _ptr(S)), ok=(NMF_OK,))
+        return R, S
 
     def masks(self):
         import numpy as np

@@ -22,88 +22,11 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "device_util.h"
 #include "nmf_internal.h"
 #include "nnls_lh.h"
 
 namespace nmfk {
-
-// Increments a counter; returns true in the block that arrives last (and
-// resets the counter).  All threads of the block call it.
-__device__ __forceinline__ bool last_arrival(unsigned *cnt, unsigned expected, unsigned *flag_lds) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned old = atomicAdd(cnt, 1u);
-        const bool last = (old == expected - 1u);
-        if (last) {
-            atomicExch(cnt, 0u);
-            __threadfence();
-        }
-        *flag_lds = last ? 1u : 0u;
-    }
-    __syncthreads();
-    const bool last = (*flag_lds != 0u);
-    if (last) __threadfence();
-    return last;
-}
-
-// One butterfly step: lanes that differ in bit H swap halves of v[0..2H) and
-// keep the sum of the half named by their bit.
-template <int H>
-__device__ __forceinline__ void transpose_step(double (&v)[YVALS], int lane) {
-    const bool up = (lane & H) != 0;
-#pragma unroll
-    for (int q = 0; q < H; ++q) {
-        const double send = up ? v[q] : v[q + H];
-        const double keep = up ? v[q + H] : v[q];
-        v[q] = keep + __shfl_xor(send, H, 64);
-    }
-}
-
-// Lane l of the wave ends up with the sum over the 64 lanes of v[l].
-__device__ __forceinline__ double wave_transpose_reduce(double (&v)[YVALS], int lane) {
-    transpose_step<32>(v, lane);
-    transpose_step<16>(v, lane);
-    transpose_step<8>(v, lane);
-    transpose_step<4>(v, lane);
-    transpose_step<2>(v, lane);
-    transpose_step<1>(v, lane);
-    return v[0];
-}
-
-// Fixed-order sum of `cnt` records of `len` doubles (stride `len`) into
-// out[0..len) (LDS), using the whole block: thread (q, g) sums the records
-// g, g + G, g + 2G, ... of entry q (G = blockDim / len groups), then the G
-// group sums are added in order.  `scratch` holds blockDim doubles of LDS.
-// Ends with a barrier.  len <= blockDim.
-__device__ __forceinline__ void reduce_records(const double *src, int cnt, int len, double *out,
-                                               double *scratch) {
-    const int G = (int)blockDim.x / len;
-    const int q = threadIdx.x % len, g = threadIdx.x / len;
-    if (g < G) {
-        double acc = 0.0;
-        int t = g;
-        for (; t + 3 * G < cnt; t += 4 * G) {
-            const double a0 = src[(size_t)t * len + q];
-            const double a1 = src[(size_t)(t + G) * len + q];
-            const double a2 = src[(size_t)(t + 2 * G) * len + q];
-            const double a3 = src[(size_t)(t + 3 * G) * len + q];
-            acc += a0;
-            acc += a1;
-            acc += a2;
-            acc += a3;
-        }
-        for (; t < cnt; t += G) acc += src[(size_t)t * len + q];
-        scratch[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < len) {
-        double acc = 0.0;
-        for (int gg = 0; gg < G; ++gg) acc += scratch[gg * len + threadIdx.x];
-        out[threadIdx.x] = acc;
-    }
-    __syncthreads();
-}
 
 // Per-block statistics and the Gram partial of the new rows (columns): the
 // NST statistics and the upper triangle of x x^T ride in one vector of
@@ -442,6 +365,22 @@ __global__ __launch_bounds__(NTHR) void k_gram_y_init(AnlsParams p) {
     }
 }
 
+// G_X block partials from the current X, in the k_xnnls block layout.
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_gram_x_init(AnlsParams p) {
+    __shared__ double xs[NTHR * K];
+    const int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < K; ++a) xs[threadIdx.x * K + a] = i < p.n ? p.X[(int64_t)a * p.ldX + i] : 0.0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < K * K; q += NTHR) {
+        const int a = q / K, c = q - a * K;
+        double v = 0.0;
+        for (int l = 0; l < NTHR; ++l) v = fma(xs[l * K + a], xs[l * K + c], v);
+        p.gx_part[(int64_t)blockIdx.x * K * K + q] = v;
+    }
+}
+
 // Direct objective 1/2 ||XY - M||^2: per-block partials, fixed order.
 template <int K>
 __global__ __launch_bounds__(NTHR) void k_objective(AnlsParams p, double *part) {
@@ -616,6 +555,11 @@ hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s) {
 
 hipError_t launch_gram_y_init(int K, const AnlsParams &p, hipStream_t s) {
     NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_y_init<KK>, dim3(p.By), dim3(NTHR), 0, s, p));
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_x_init(int K, const AnlsParams &p, hipStream_t s) {
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_x_init<KK>, dim3(p.Bx), dim3(NTHR), 0, s, p));
     return hipGetLastError();
 }
 

@@ -1,0 +1,124 @@
+// Block- and wave-level building blocks shared by the HIP kernels.  Every
+// reduction here runs in a fixed order, so results do not depend on block
+// scheduling.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "nmf_internal.h"
+
+namespace nmfk {
+
+// Increments a counter; returns true in the block that arrives last (and
+// resets the counter).  All threads of the block call it.
+__device__ __forceinline__ bool last_arrival(unsigned *cnt, unsigned expected, unsigned *flag_lds) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned old = atomicAdd(cnt, 1u);
+        const bool last = (old == expected - 1u);
+        if (last) {
+            atomicExch(cnt, 0u);
+            __threadfence();
+        }
+        *flag_lds = last ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool last = (*flag_lds != 0u);
+    if (last) __threadfence();
+    return last;
+}
+
+// One butterfly step: lanes that differ in bit H swap halves of v[0..2H) and
+// keep the sum of the half named by their bit.
+template <int H>
+__device__ __forceinline__ void transpose_step(double (&v)[YVALS], int lane) {
+    const bool up = (lane & H) != 0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        const double send = up ? v[q] : v[q + H];
+        const double keep = up ? v[q + H] : v[q];
+        v[q] = keep + __shfl_xor(send, H, 64);
+    }
+}
+
+// Lane l of the wave ends up with the sum over the 64 lanes of v[l].
+__device__ __forceinline__ double wave_transpose_reduce(double (&v)[YVALS], int lane) {
+    transpose_step<32>(v, lane);
+    transpose_step<16>(v, lane);
+    transpose_step<8>(v, lane);
+    transpose_step<4>(v, lane);
+    transpose_step<2>(v, lane);
+    transpose_step<1>(v, lane);
+    return v[0];
+}
+
+// Fixed-order sum of `cnt` records of `len` doubles (stride `len`) into
+// out[0..len) (LDS), using the whole block: thread (q, g) sums the records
+// g, g + G, g + 2G, ... of entry q (G = blockDim / len groups), then the G
+// group sums are added in order.  `scratch` holds blockDim doubles of LDS.
+// Ends with a barrier.  len <= blockDim.
+__device__ __forceinline__ void reduce_records(const double *src, int cnt, int len, double *out,
+                                               double *scratch) {
+    const int G = (int)blockDim.x / len;
+    const int q = threadIdx.x % len, g = threadIdx.x / len;
+    if (g < G) {
+        double acc = 0.0;
+        int t = g;
+        for (; t + 3 * G < cnt; t += 4 * G) {
+            const double a0 = src[(size_t)t * len + q];
+            const double a1 = src[(size_t)(t + G) * len + q];
+            const double a2 = src[(size_t)(t + 2 * G) * len + q];
+            const double a3 = src[(size_t)(t + 3 * G) * len + q];
+            acc += a0;
+            acc += a1;
+            acc += a2;
+            acc += a3;
+        }
+        for (; t < cnt; t += G) acc += src[(size_t)t * len + q];
+        scratch[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < len) {
+        double acc = 0.0;
+        for (int gg = 0; gg < G; ++gg) acc += scratch[gg * len + threadIdx.x];
+        out[threadIdx.x] = acc;
+    }
+    __syncthreads();
+}
+
+// Sums V values per thread over a block of NTHR threads: wave transpose-reduce
+// passes of 64 values, then the NTHR/64 waves in order.  Thread q < V ends up
+// writing the block sum of value q to out[q] (global).  lds holds NTHR doubles.
+// All threads call it.
+template <int V>
+__device__ __forceinline__ void block_reduce_to(const double (&vals)[V], double *out, double *lds) {
+    constexpr int NPASS = (V + YVALS - 1) / YVALS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+        double v[YVALS];
+#pragma unroll
+        for (int q = 0; q < YVALS; ++q) v[q] = (pass * YVALS + q < V) ? vals[(pass * YVALS + q) % V] : 0.0;
+        lds[w * YVALS + lane] = wave_transpose_reduce(v, lane);
+        __syncthreads();
+        const int idx = pass * YVALS + (int)threadIdx.x;
+        if ((int)threadIdx.x < YVALS && idx < V) {
+            double sum = lds[threadIdx.x];
+            for (int ww = 1; ww < (int)blockDim.x / 64; ++ww) sum += lds[ww * YVALS + threadIdx.x];
+            out[idx] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// Wave minimum (fixed butterfly order).
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int h = 32; h >= 1; h >>= 1) {
+        const double o = __shfl_xor(v, h, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+}  // namespace nmfk

@@ -1,5 +1,6 @@
 // Stage 2 of the two-stage NMF (Sec. III, IV, Alg. 3): transition and the
-// primal-dual line-search interior-point iterations.
+// primal-dual line-search interior-point iterations, on the device, with the
+// host steering the loop tests from a few device-computed scalars.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -11,8 +12,46 @@
 
 namespace nmfk {
 
+constexpr int PARTW = 16;      // doubles per block record of the small reductions
+constexpr int NTRIAL = 16;     // Armijo trial steps evaluated per batch
+
+// Small device-resident results (k x k matrices and reduction outputs).
+struct IpmScal {
+    double GX[KMAX * KMAX];    // X^T X at the current point
+    double GY[KMAX * KMAX];    // Y Y^T at the current point
+    double XtV[KMAX * KMAX];   // X^T V, V_i = Q1bar_i^-1 b1_i
+    double T[KMAX * KMAX];     // dY Y^T
+    double out[4 * PARTW];     // outputs of the last k_finish calls
+    double f;                  // 1/2 ||XY - M||^2 at the current point
+    int chol_fail;
+    int pad;
+};
+
 struct IpmState {
     bool bound = false;
+    int64_t n = 0, m_cap = 0, ldX = 0, ldY = 0, ldS = 0;
+    int K = 0;
+    // device buffers (component-major [K][ld] unless noted)
+    double *r = nullptr, *s = nullptr;         // duals
+    double *dx = nullptr, *dy = nullptr, *dr = nullptr, *ds = nullptr;
+    double *gx = nullptr, *gy = nullptr;       // graX, graY
+    double *V = nullptr;                       // Q1bar_i^-1 b1_i per row
+    double *tX = nullptr, *tY = nullptr;       // residual products (exact Hessian)
+    double *Lq = nullptr;                      // [K(K+1)/2 + K][ldX]: Cholesky of Q1bar_i and 1/diag
+    double *Qi = nullptr;                      // [K(K+1)/2][ldX]: Q1bar_i^-1 (exact Hessian)
+    double *Z = nullptr;                       // [n][K][ldY]: L_i^-1 Y
+    double *S = nullptr;                       // [mK][ldS] column-major, lower triangle used
+    double *vec = nullptr, *vec2 = nullptr;    // [ldS] right-hand side / solution
+    double *part = nullptr;                    // [nblk][PARTW] block records
+    double *fpart = nullptr;                   // [Tn * Sx] objective partials
+    IpmScal *sc = nullptr;
+    // host-side state of Alg. 3
+    double mu = 0, rho = 0, eps_mu = 0, E0 = 0, Emu = 0, sigma = 0, f = 0, slope = 0;
+    double S1 = 0, C0 = 0, Cmu = 0, SR = 0;    // KKT sums at the current point
+    int flag = 0, at_mu = 0;
+    bool in_inner = false;                     // inside the inner loop of the current mu
+    bool S_gn_valid = false;                   // S holds the factored Gauss-Newton Schur matrix of this point
+    int64_t iters = 0, outer = 0, backtracks = 0, exact_steps = 0, fallbacks = 0, cap_hits = 0;
     std::string err;
 };
 
@@ -22,6 +61,7 @@ nmf_status ipm_transition(IpmState &s, const AnlsParams &p, const nmf_options &o
 nmf_status ipm_iterate(IpmState &s, const AnlsParams &p, const nmf_options &o, int iters, hipStream_t st);
 nmf_status ipm_report(IpmState &s, nmf_report *r, double ms1, double ms2);
 nmf_status ipm_export(IpmState &s, const AnlsParams &p, hipStream_t st);
+nmf_status ipm_get_duals(IpmState &s, const AnlsParams &p, double *R, double *S, hipStream_t st);
 const char *ipm_last_error(const IpmState &s);
 
 }  // namespace nmfk

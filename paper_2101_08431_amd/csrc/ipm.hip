@@ -1,19 +1,1584 @@
+// Stage 2 of the two-stage NMF: the transition (eq. (21)-(25)) and the line-
+// search primal-dual interior-point method of Alg. 2 / Alg. 3, on the device.
+//
+// Newton system.  The reduced system eq. (12) is solved by the route of
+// Sec. III-B: Q1bar = P^T P block by block (one k x k Cholesky per row of X),
+// then the Schur complement eq. (20)
+//     S = Q2bar - (Cbar P^-1)(Cbar P^-1)^T,
+// whose (j, l) block is  delta_jl Q2bar_j - sum_i c_ijl X_i^T X_i  with
+// c_ijl = Y_j^T Q1bar_i^-1 Y_l = Z_i[:, j] . Z_i[:, l],  Z_i = L_i^-1 Y  (the
+// rank-one structure of the blocks of Cbar, Sec. III-B).  With the exact
+// Hessian (eq. (27), flag = 1) block (j, i) of C gains (XY - M)_ij I and the
+// sum gains three terms (R_il X_ia w_ij[b] + R_ij w_il[a] X_ib + R_ij R_il
+// Q1bar_i^-1[a][b], w_ij = Q1bar_i^-1 Y_j).
+// The products with Cbar that the right-hand side and the back substitution
+// need reduce to k x k matrices:  (Cbar v)_j = (X^T V) Y_j  and
+// (Cbar^T dy)_i = X_i (dY Y^T);  the exact-Hessian parts are one pass over M
+// with the residual formed on the fly.
+//
+// Line search.  With R0 = XY - M, A = dX Y + X dY, B = dX dY, the objective
+// along the step is 1/2 ||R0 + a A + a^2 B||^2, a quartic whose six
+// coefficients come from one pass over M; the barrier terms of phi for a batch
+// of trial steps a = a1max / 2^t come from one pass over (x, y).
+//
+// Dense linear algebra.  S (mk x mk) is factored by a blocked right-looking
+// Cholesky (diagonal block in LDS, panel solve, trailing update in 64 x 64
+// tiles), and the two triangular solves are blocked the same way.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "device_util.h"
 #include "ipm.h"
 
 namespace nmfk {
 
-size_t ipm_workspace_bytes(int64_t, int64_t, int) { return 0; }
-nmf_status ipm_bind(IpmState &s, uint8_t *, int64_t, int64_t, int) { s.bound = true; return NMF_OK; }
-nmf_status ipm_transition(IpmState &s, const AnlsParams &, const nmf_options &, hipStream_t) {
-    s.err = "stage 2 not available";
-    return NMF_ESTATE;
+constexpr int PRS = KMAX * KMAX;   // stride of block records in `part`
+constexpr int CB = 64;             // dense Cholesky / triangular-solve block
+constexpr int TJ = 16;             // Schur tile: 16 x 16 (j, l) pairs
+constexpr int SRB = 4;             // rows of X staged per Schur step
+constexpr int ZRB = 8;             // rows per block of the Z kernel
+
+struct IpmArgs {
+    double *r, *s, *dx, *dy, *dr, *ds, *gx, *gy, *V, *tX, *tY, *Lq, *Qi, *Z, *S, *vec, *vec2, *part;
+    IpmScal *sc;
+    int64_t ldS, N;
+};
+
+static IpmArgs args_of(const IpmState &s) {
+    IpmArgs a;
+    a.r = s.r; a.s = s.s; a.dx = s.dx; a.dy = s.dy; a.dr = s.dr; a.ds = s.ds;
+    a.gx = s.gx; a.gy = s.gy; a.V = s.V; a.tX = s.tX; a.tY = s.tY; a.Lq = s.Lq; a.Qi = s.Qi;
+    a.Z = s.Z; a.S = s.S; a.vec = s.vec; a.vec2 = s.vec2; a.part = s.part; a.sc = s.sc;
+    a.ldS = s.ldS;
+    a.N = 0;
+    return a;
 }
-nmf_status ipm_iterate(IpmState &s, const AnlsParams &, const nmf_options &, int, hipStream_t) {
-    s.err = "stage 2 not available";
-    return NMF_ESTATE;
+
+// Sums V values given by fn(idx) (compile-time idx after unrolling) over the
+// block; value q lands in out[q].  lds holds blockDim doubles.
+template <int V, class F>
+__device__ __forceinline__ void block_reduce_fn(F &&fn, double *out, double *lds) {
+    constexpr int NPASS = (V + YVALS - 1) / YVALS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+        double v[YVALS];
+#pragma unroll
+        for (int q = 0; q < YVALS; ++q) v[q] = (pass * YVALS + q < V) ? fn(pass * YVALS + q) : 0.0;
+        lds[w * YVALS + lane] = wave_transpose_reduce(v, lane);
+        __syncthreads();
+        const int idx = pass * YVALS + (int)threadIdx.x;
+        if ((int)threadIdx.x < YVALS && idx < V) {
+            double sum = lds[threadIdx.x];
+            for (int ww = 1; ww < (int)blockDim.x / 64; ++ww) sum += lds[ww * YVALS + threadIdx.x];
+            out[idx] = sum;
+        }
+        __syncthreads();
+    }
 }
-nmf_status ipm_report(IpmState &, nmf_report *, double, double) { return NMF_ESTATE; }
-nmf_status ipm_export(IpmState &, const AnlsParams &, hipStream_t) { return NMF_OK; }
+
+// out[q] = sum (or min, bit q of minmask) over nblk records part[b*stride + q].
+__global__ __launch_bounds__(NTHR) void k_finish(const double *part, int stride, int nblk, int nval,
+                                                 unsigned minmask, double *out) {
+    __shared__ double scr[NTHR];
+    const int G = NTHR / nval;
+    const int q = threadIdx.x % nval, g = threadIdx.x / nval;
+    const bool mn = (minmask >> q) & 1u;
+    if (g < G) {
+        double acc = mn ? INFINITY : 0.0;
+        for (int t = g; t < nblk; t += G) {
+            const double v = part[(size_t)t * stride + q];
+            acc = mn ? (v < acc ? v : acc) : acc + v;
+        }
+        scr[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nval) {
+        double acc = scr[threadIdx.x];
+        for (int gg = 1; gg < G; ++gg) {
+            const double v = scr[gg * nval + threadIdx.x];
+            acc = mn ? (v < acc ? v : acc) : acc + v;
+        }
+        out[threadIdx.x] = acc;
+    }
+}
+
+// out[a*ld + e] = sum_s part[(s*K + a)*ld + e], e < count.
+__global__ __launch_bounds__(NTHR) void k_sum_splits(const double *part, int S, int K, int64_t ld, int64_t count,
+                                                     double *out) {
+    const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    if (e >= count) return;
+    for (int a = 0; a < K; ++a) {
+        double v = 0.0;
+        for (int s = 0; s < S; ++s) v += part[((int64_t)s * K + a) * ld + e];
+        out[(int64_t)a * ld + e] = v;
+    }
+}
+
+// ---------------------------------------------------------------- residual streams
+// X side: out_part[split][a][i] = sum_{j in split} R_ij W[a][j], R = XY - M;
+// fpart[tile * Sx + split] = the block's share of sum R_ij^2 (if fpart).
+template <int K>
+__global__ __launch_bounds__(STHR) void k_rstream_x(AnlsParams p, const double *W, double *out_part,
+                                                    double *fpart) {
+    constexpr int RED = SWAVES * K * XTILE + SWAVES * XTILE;
+    constexpr int LDSN = (2 * XCHUNK * K > RED) ? 2 * XCHUNK * K : RED;
+    __shared__ double lds[LDSN];
+    double *ys = lds, *ws = lds + XCHUNK * K;
+    const int tile = blockIdx.x, split = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)tile * XTILE + lane;
+    const int64_t j0 = (int64_t)split * p.xcols;
+    const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
+    const bool row_ok = i < p.n;
+    double x[K], acc[K], f = 0.0;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        x[a] = row_ok ? p.X[(int64_t)a * p.ldX + i] : 0.0;
+        acc[a] = 0.0;
+    }
+    for (int64_t c0 = j0; c0 < j1; c0 += XCHUNK) {
+        const int nc = (int)min((int64_t)XCHUNK, j1 - c0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nc * K; q += STHR) {
+            const int jj = q / K, a = q - jj * K;
+            ys[q] = p.Y[(int64_t)a * p.ldY + c0 + jj];
+            ws[q] = W[(int64_t)a * p.ldY + c0 + jj];
+        }
+        __syncthreads();
+        const double *mp = p.M + c0 * p.ldM + (row_ok ? i : 0);
+        for (int jb = w; jb < nc; jb += 8 * SWAVES) {
+            double mv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int jj = jb + t * SWAVES;
+                mv[t] = (jj < nc && row_ok) ? mp[(int64_t)jj * p.ldM] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int jj = jb + t * SWAVES;
+                if (jj < nc) {
+                    double rr = -mv[t];
+#pragma unroll
+                    for (int a = 0; a < K; ++a) rr = fma(x[a], ys[jj * K + a], rr);
+                    if (!row_ok) rr = 0.0;
+#pragma unroll
+                    for (int a = 0; a < K; ++a) acc[a] = fma(rr, ws[jj * K + a], acc[a]);
+                    f = fma(rr, rr, f);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double *red = lds, *fred = lds + SWAVES * K * XTILE;
+#pragma unroll
+    for (int a = 0; a < K; ++a) red[(w * K + a) * XTILE + lane] = acc[a];
+    fred[w * XTILE + lane] = f;
+    __syncthreads();
+    if (w == 0) {
+        if (row_ok) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                double v = red[a * XTILE + lane];
+#pragma unroll
+                for (int ww = 1; ww < SWAVES; ++ww) v += red[(ww * K + a) * XTILE + lane];
+                out_part[((int64_t)split * K + a) * p.ldX + i] = v;
+            }
+        }
+        if (fpart) {
+            double fl = fred[lane];
+#pragma unroll
+            for (int ww = 1; ww < SWAVES; ++ww) fl += fred[ww * XTILE + lane];
+#pragma unroll
+            for (int h = 32; h >= 1; h >>= 1) fl += __shfl_xor(fl, h, 64);
+            if (lane == 0) fpart[(int64_t)tile * p.Sx + split] = fl;
+        }
+    }
+}
+
+// Y side: out_part[split][a][j] = sum_{i in split} R_ij Vm[a][i].
+template <int K>
+__global__ __launch_bounds__(STHR) void k_rstream_y(AnlsParams p, const double *Vm, double *out_part) {
+    constexpr int J = YVALS / K;
+    __shared__ double red[SWAVES * YVALS];
+    __shared__ double yts[J * K];
+    const int ct = blockIdx.x, split = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t jb = (int64_t)ct * J;
+    const int nj = (int)min((int64_t)J, p.m - jb);
+    const int64_t r0 = (int64_t)split * p.yrows;
+    const int64_t r1 = min(r0 + (int64_t)p.yrows, p.n);
+    if ((int)threadIdx.x < J * K) {
+        const int jj = threadIdx.x / K, a = threadIdx.x - jj * K;
+        yts[threadIdx.x] = jj < nj ? p.Y[(int64_t)a * p.ldY + jb + jj] : 0.0;
+    }
+    __syncthreads();
+    double v[YVALS];
+#pragma unroll
+    for (int q = 0; q < YVALS; ++q) v[q] = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += STHR) {
+        double x[K], vm[K], mv[J];
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            x[a] = p.X[(int64_t)a * p.ldX + i];
+            vm[a] = Vm[(int64_t)a * p.ldX + i];
+        }
+        const double *mp = p.M + jb * p.ldM + i;
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) mv[jj] = (jj < nj) ? mp[(int64_t)jj * p.ldM] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) {
+            double rr = -mv[jj];
+#pragma unroll
+            for (int a = 0; a < K; ++a) rr = fma(x[a], yts[jj * K + a], rr);
+#pragma unroll
+            for (int a = 0; a < K; ++a) v[jj * K + a] = fma(rr, vm[a], v[jj * K + a]);
+        }
+    }
+    red[w * YVALS + lane] = wave_transpose_reduce(v, lane);
+    __syncthreads();
+    if ((int)threadIdx.x < nj * K) {
+        double s = red[threadIdx.x];
+#pragma unroll
+        for (int ww = 1; ww < SWAVES; ++ww) s += red[ww * YVALS + threadIdx.x];
+        const int jj = threadIdx.x / K, a = threadIdx.x - jj * K;
+        out_part[((int64_t)split * K + a) * p.ldY + jb + jj] = s;
+    }
+}
+
+// Block partials of sum_e A_e B_e^T (K x K, row-major a*K + b) over
+// e < count, A and B component-major with leading dimension ld.
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_outer(const double *A, const double *B, int64_t ld, int64_t count,
+                                                double *part) {
+    __shared__ double lds[NTHR];
+    const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    double a[K], b[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        a[q] = e < count ? A[(int64_t)q * ld + e] : 0.0;
+        b[q] = e < count ? B[(int64_t)q * ld + e] : 0.0;
+    }
+    block_reduce_fn<K * K>([&](int idx) { return a[idx / K] * b[idx % K]; }, part + (size_t)blockIdx.x * PRS,
+                           lds);
+}
+
+// ---------------------------------------------------------------- point kernels
+// Blocks [0, Bx) cover rows (x, r, gx), blocks [Bx, Bx + By) columns (y, s, gy).
+struct Side {
+    const double *v, *d, *g;
+    double *dual;
+    int64_t ld, count, e;
+    bool ok;
+};
+
+template <int K>
+__device__ __forceinline__ Side side_of(const AnlsParams &p, const IpmArgs &ia, bool use_dir) {
+    Side sd;
+    const int b = blockIdx.x;
+    if (b < p.Bx) {
+        sd.v = p.X; sd.d = use_dir ? ia.dx : nullptr; sd.g = ia.gx; sd.dual = ia.r;
+        sd.ld = p.ldX; sd.count = p.n; sd.e = (int64_t)b * NTHR + threadIdx.x;
+    } else {
+        sd.v = p.Y; sd.d = use_dir ? ia.dy : nullptr; sd.g = ia.gy; sd.dual = ia.s;
+        sd.ld = p.ldY; sd.count = p.m; sd.e = (int64_t)(b - p.Bx) * NTHR + threadIdx.x;
+    }
+    sd.ok = sd.e < sd.count;
+    return sd;
+}
+
+// KKT sums at the current point: [0] sum (g - dual)^2, [1] sum (dual v)^2,
+// [2] sum (dual v - mu)^2, [3] sum dual v.
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_kkt(AnlsParams p, IpmArgs ia, double mu) {
+    __shared__ double lds[NTHR];
+    const Side sd = side_of<K>(p, ia, false);
+    double s1 = 0.0, c0 = 0.0, cm = 0.0, sr = 0.0;
+    if (sd.ok) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * sd.ld + sd.e;
+            const double gd = sd.g[o] - sd.dual[o];
+            const double c = sd.dual[o] * sd.v[o];
+            s1 = fma(gd, gd, s1);
+            c0 = fma(c, c, c0);
+            cm = fma(c - mu, c - mu, cm);
+            sr += c;
+        }
+    }
+    const double vals[4] = {s1, c0, cm, sr};
+    block_reduce_fn<4>([&](int idx) { return vals[idx]; }, ia.part + (size_t)blockIdx.x * PRS, lds);
+}
+
+// Transition helpers.  mode 0: [0] = -max v ; mode 1: [0] = -max |g|, per side
+// in its own slot ([0] rows, [1] columns), so that a min-finish gives both.
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_maxes(AnlsParams p, IpmArgs ia, int mode) {
+    __shared__ double lds[NTHR];
+    const Side sd = side_of<K>(p, ia, false);
+    double mx = -INFINITY;
+    if (sd.ok) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * sd.ld + sd.e;
+            const double v = mode == 0 ? sd.v[o] : fabs(sd.g[o]);
+            mx = v > mx ? v : mx;
+        }
+    }
+    lds[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = NTHR / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lds[threadIdx.x] = lds[threadIdx.x + h] > lds[threadIdx.x] ? lds[threadIdx.x + h] : lds[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool rows = (int)blockIdx.x < p.Bx;
+        double *rec = ia.part + (size_t)blockIdx.x * PRS;
+        rec[0] = rows ? -lds[0] : INFINITY;
+        rec[1] = rows ? INFINITY : -lds[0];
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_clamp(AnlsParams p, double lo) {
+    const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    if (e < p.n) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            double *q = p.X + (int64_t)a * p.ldX + e;
+            *q = *q > lo ? *q : lo;
+        }
+    }
+    if (e < p.m) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            double *q = p.Y + (int64_t)a * p.ldY + e;
+            *q = *q > lo ? *q : lo;
+        }
+    }
+}
+
+// r = rv, s = sv everywhere; records [0] sum x (rows), [1] sum y (columns).
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_fill_duals(AnlsParams p, IpmArgs ia, double rv, double sv) {
+    __shared__ double lds[NTHR];
+    const Side sd = side_of<K>(p, ia, false);
+    const bool rows = (int)blockIdx.x < p.Bx;
+    double sum = 0.0;
+    if (sd.ok) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * sd.ld + sd.e;
+            sd.dual[o] = rows ? rv : sv;
+            sum += sd.v[o];
+        }
+    }
+    const double vals[2] = {rows ? sum : 0.0, rows ? 0.0 : sum};
+    block_reduce_fn<2>([&](int idx) { return vals[idx]; }, ia.part + (size_t)blockIdx.x * PRS, lds);
+}
+
+// ---------------------------------------------------------------- direction
+// Per row i: the Cholesky factor L_i of Q1bar_i = Y Y^T + rho I + Diag(r_i / x_i)
+// (packed lower, then 1/diag), V_i = Q1bar_i^-1 b1_i with b1 = -(graX - mu/x),
+// and with EXACT also Q1bar_i^-1 (packed lower).
+template <int K, bool EXACT>
+__global__ __launch_bounds__(NTHR) void k_factor(AnlsParams p, IpmArgs ia, double mu, double rho) {
+    constexpr int NL = K * (K + 1) / 2;
+    __shared__ double G[K * K];
+    for (int q = threadIdx.x; q < K * K; q += NTHR) G[q] = ia.sc->GY[q];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    if (i >= p.n) return;
+    double L[NL], inv[K], x[K], b1[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        const int64_t o = (int64_t)a * p.ldX + i;
+        x[a] = p.X[o];
+        b1[a] = -(ia.gx[o] - mu / x[a]);
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+            double v = G[r * K + c];
+            if (r == c) v += rho + ia.r[(int64_t)r * p.ldX + i] / x[r];
+#pragma unroll
+            for (int q = 0; q < c; ++q) v -= L[r * (r + 1) / 2 + q] * L[c * (c + 1) / 2 + q];
+            if (r == c) {
+                const double d = sqrt(v);
+                L[r * (r + 1) / 2 + r] = d;
+                inv[r] = 1.0 / d;
+            } else {
+                L[r * (r + 1) / 2 + c] = v * inv[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) ia.Lq[(int64_t)q * p.ldX + i] = L[q];
+#pragma unroll
+    for (int a = 0; a < K; ++a) ia.Lq[(int64_t)(NL + a) * p.ldX + i] = inv[a];
+    // V_i = L^-T L^-1 b1
+    double t[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        double v = b1[r];
+#pragma unroll
+        for (int q = 0; q < r; ++q) v -= L[r * (r + 1) / 2 + q] * t[q];
+        t[r] = v * inv[r];
+    }
+#pragma unroll
+    for (int r = K - 1; r >= 0; --r) {
+        double v = t[r];
+#pragma unroll
+        for (int q = r + 1; q < K; ++q) v -= L[q * (q + 1) / 2 + r] * t[q];
+        t[r] = v * inv[r];
+    }
+#pragma unroll
+    for (int a = 0; a < K; ++a) ia.V[(int64_t)a * p.ldX + i] = t[a];
+    if (EXACT) {
+        // columns of Q^-1 = L^-T L^-1 e_c; store the lower triangle
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            double u[K];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                double v = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+                for (int q = 0; q < r; ++q) v -= L[r * (r + 1) / 2 + q] * u[q];
+                u[r] = v * inv[r];
+            }
+#pragma unroll
+            for (int r = K - 1; r >= 0; --r) {
+                double v = u[r];
+#pragma unroll
+                for (int q = r + 1; q < K; ++q) v -= L[q * (q + 1) / 2 + r] * u[q];
+                u[r] = v * inv[r];
+            }
+#pragma unroll
+            for (int a = c; a < K; ++a) ia.Qi[(int64_t)(a * (a + 1) / 2 + c) * p.ldX + i] = u[a];
+        }
+    }
+}
+
+// Z_i = L_i^-1 Y for ZRB rows per block: Z[(i*K + c)*ldY + j].
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_zmat(AnlsParams p, IpmArgs ia) {
+    constexpr int NL = K * (K + 1) / 2;
+    __shared__ double Ls[ZRB][NL + K];
+    const int64_t i0 = (int64_t)blockIdx.x * ZRB;
+    for (int q = threadIdx.x; q < ZRB * (NL + K); q += NTHR) {
+        const int rr = q / (NL + K), c = q - rr * (NL + K);
+        const int64_t i = i0 + rr;
+        Ls[rr][c] = i < p.n ? ia.Lq[(int64_t)c * p.ldX + i] : 1.0;
+    }
+    __syncthreads();
+    const int nr = (int)min((int64_t)ZRB, p.n - i0);
+    for (int64_t j = threadIdx.x; j < p.m; j += NTHR) {
+        double y[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) y[a] = p.Y[(int64_t)a * p.ldY + j];
+        for (int rr = 0; rr < nr; ++rr) {
+            double z[K];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                double v = y[r];
+#pragma unroll
+                for (int q = 0; q < r; ++q) v -= Ls[rr][r * (r + 1) / 2 + q] * z[q];
+                z[r] = v * Ls[rr][NL + r];
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c) ia.Z[((i0 + rr) * K + c) * p.ldY + j] = z[c];
+        }
+    }
+}
+
+// Schur matrix, lower block triangle: one 16 x 16 tile of (j, l) column pairs
+// (j-tile >= l-tile) per block, one (j, l) pair per thread, all (a, b).
+//   S[(j,a), (l,b)] = delta_jl Q2bar_j[a][b] - sum_i (c_ijl X_ia X_ib [+ exact terms])
+template <int K, bool EXACT>
+__global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double rho) {
+    constexpr int NL = K * (K + 1) / 2;
+    __shared__ double Zs[SRB][K][2 * TJ];
+    __shared__ double XX[SRB][K * K];
+    __shared__ double Xs[SRB][K];
+    __shared__ double Ws[EXACT ? SRB : 1][EXACT ? K : 1][2 * TJ];
+    __shared__ double Rs[EXACT ? SRB : 1][2 * TJ];
+    __shared__ double Qs[EXACT ? SRB : 1][EXACT ? K * K : 1];
+    __shared__ double Ls[EXACT ? SRB : 1][EXACT ? NL + K : 1];
+    // tile index -> (jt, lt), jt >= lt
+    const int64_t tix = blockIdx.x;
+    int64_t jt = (int64_t)((sqrt(8.0 * (double)tix + 1.0) - 1.0) * 0.5);
+    while ((jt + 1) * (jt + 2) / 2 <= tix) ++jt;
+    while (jt * (jt + 1) / 2 > tix) --jt;
+    const int64_t lt = tix - jt * (jt + 1) / 2;
+    const int jj = threadIdx.x / TJ, ll = threadIdx.x % TJ;
+    const int64_t j = jt * TJ + jj, l = lt * TJ + ll;
+
+    double acc[K * K];
+#pragma unroll
+    for (int q = 0; q < K * K; ++q) acc[q] = 0.0;
+
+    for (int64_t i0 = 0; i0 < p.n; i0 += SRB) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < SRB * K * 2 * TJ; q += 256) {
+            const int rr = q / (K * 2 * TJ), c = (q / (2 * TJ)) % K, col = q % (2 * TJ);
+            const int64_t i = i0 + rr;
+            const int64_t jc = col < TJ ? jt * TJ + col : lt * TJ + col - TJ;
+            Zs[rr][c][col] = (i < p.n && jc < p.m) ? ia.Z[(i * K + c) * p.ldY + jc] : 0.0;
+        }
+        for (int q = threadIdx.x; q < SRB * K; q += 256) {
+            const int rr = q / K, a = q % K;
+            const int64_t i = i0 + rr;
+            Xs[rr][a] = i < p.n ? p.X[(int64_t)a * p.ldX + i] : 0.0;
+        }
+        if (EXACT) {
+            for (int q = threadIdx.x; q < SRB * (NL + K); q += 256) {
+                const int rr = q / (NL + K), c = q % (NL + K);
+                const int64_t i = i0 + rr;
+                Ls[rr][c] = i < p.n ? ia.Lq[(int64_t)c * p.ldX + i] : 1.0;
+            }
+            for (int q = threadIdx.x; q < SRB * K * K; q += 256) {
+                const int rr = q / (K * K), a = (q / K) % K, b = q % K;
+                const int64_t i = i0 + rr;
+                const int hi = a > b ? a : b, lo = a > b ? b : a;
+                Qs[rr][a * K + b] = i < p.n ? ia.Qi[(int64_t)(hi * (hi + 1) / 2 + lo) * p.ldX + i] : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < SRB * K * K; q += 256) {
+            const int rr = q / (K * K), a = (q / K) % K, b = q % K;
+            XX[rr][a * K + b] = Xs[rr][a] * Xs[rr][b];
+        }
+        if (EXACT) {
+            // w = L^-T z for the 32 staged columns; R_ij = X_i . Y_j - M_ij
+            for (int q = threadIdx.x; q < SRB * 2 * TJ; q += 256) {
+                const int rr = q / (2 * TJ), col = q % (2 * TJ);
+                const int64_t i = i0 + rr;
+                const int64_t jc = col < TJ ? jt * TJ + col : lt * TJ + col - TJ;
+                double u[K];
+#pragma unroll
+                for (int c = 0; c < K; ++c) u[c] = Zs[rr][c][col];
+#pragma unroll
+                for (int r = K - 1; r >= 0; --r) {
+                    double v = u[r];
+#pragma unroll
+                    for (int qq = r + 1; qq < K; ++qq) v -= Ls[rr][qq * (qq + 1) / 2 + r] * u[qq];
+                    u[r] = v * Ls[rr][NL + r];
+                }
+#pragma unroll
+                for (int c = 0; c < K; ++c) Ws[rr][c][col] = u[c];
+                double res = 0.0;
+                if (i < p.n && jc < p.m) {
+                    res = -p.M[jc * p.ldM + i];
+#pragma unroll
+                    for (int a = 0; a < K; ++a) res = fma(Xs[rr][a], p.Y[(int64_t)a * p.ldY + jc], res);
+                }
+                Rs[rr][col] = res;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < SRB; ++rr) {
+            double c = 0.0;
+#pragma unroll
+            for (int q = 0; q < K; ++q) c = fma(Zs[rr][q][jj], Zs[rr][q][TJ + ll], c);
+#pragma unroll
+            for (int q = 0; q < K * K; ++q) acc[q] = fma(c, XX[rr][q], acc[q]);
+            if (EXACT) {
+                const double Rj = Rs[rr][jj], Rl = Rs[rr][TJ + ll];
+                const double RR = Rj * Rl;
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    const double xa_rl = Xs[rr][a] * Rl;
+                    const double wla_rj = Ws[rr][a][TJ + ll] * Rj;
+#pragma unroll
+                    for (int b = 0; b < K; ++b) {
+                        double v = acc[a * K + b];
+                        v = fma(xa_rl, Ws[rr][b][jj], v);
+                        v = fma(wla_rj, Xs[rr][b], v);
+                        v = fma(RR, Qs[rr][a * K + b], v);
+                        acc[a * K + b] = v;
+                    }
+                }
+            }
+        }
+    }
+    if (j < p.m && l < p.m) {
+        const double *G = ia.sc->GX;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+#pragma unroll
+            for (int b = 0; b < K; ++b) {
+                double v = -acc[a * K + b];
+                if (j == l) {
+                    v += G[a * K + b];
+                    if (a == b) v += rho + ia.s[(int64_t)a * p.ldY + j] / p.Y[(int64_t)a * p.ldY + j];
+                }
+                ia.S[(l * K + b) * ia.ldS + (j * K + a)] = v;
+            }
+        }
+    }
+}
+
+// Right-hand side of eq. (20): rhs_j = b2_j - (X^T V) Y_j [- (R^T V)_j], b2 = -(graY - mu/y).
+template <int K, bool EXACT>
+__global__ __launch_bounds__(NTHR) void k_rhs(AnlsParams p, IpmArgs ia, double mu) {
+    __shared__ double T[K * K];
+    for (int q = threadIdx.x; q < K * K; q += NTHR) T[q] = ia.sc->XtV[q];
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    if (j >= p.m) return;
+    double y[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) y[a] = p.Y[(int64_t)a * p.ldY + j];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double v = -(ia.gy[(int64_t)a * p.ldY + j] - mu / y[a]);
+#pragma unroll
+        for (int b = 0; b < K; ++b) v -= T[a * K + b] * y[b];
+        if (EXACT) v -= ia.tY[(int64_t)a * p.ldY + j];
+        ia.vec[j * K + a] = v;
+    }
+}
+
+// Column side after the Schur solve: dY from the solution, ds, and the
+// records [0] slope part, [1] alpha1 candidate, [2] alpha2 candidate.
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_post_y(AnlsParams p, IpmArgs ia, double mu, double tau, int recbase) {
+    __shared__ double lds[NTHR];
+    const int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    double slope = 0.0, a1 = INFINITY, a2 = INFINITY;
+    if (j < p.m) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * p.ldY + j;
+            const double d = ia.vec2[j * K + a];
+            const double y = p.Y[o], s = ia.s[o];
+            ia.dy[o] = d;
+            const double dsv = mu / y - s - (s / y) * d;
+            ia.ds[o] = dsv;
+            slope = fma(d, ia.gy[o] - mu / y, slope);
+            if (d < 0.0) { const double c = -tau * y / d; a1 = c < a1 ? c : a1; }
+            if (dsv < 0.0) { const double c = -tau * s / dsv; a2 = c < a2 ? c : a2; }
+        }
+    }
+    a1 = wave_min(a1);
+    a2 = wave_min(a2);
+    const double vals[1] = {slope};
+    double *rec = ia.part + (size_t)(recbase + blockIdx.x) * PRS;
+    block_reduce_fn<1>([&](int idx) { return vals[idx]; }, rec, lds);
+    __shared__ double mins[2][NTHR / 64];
+    if ((threadIdx.x & 63) == 0) {
+        mins[0][threadIdx.x >> 6] = a1;
+        mins[1][threadIdx.x >> 6] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double m = mins[threadIdx.x][0];
+        for (int w = 1; w < NTHR / 64; ++w) m = mins[threadIdx.x][w] < m ? mins[threadIdx.x][w] : m;
+        rec[1 + threadIdx.x] = m;
+    }
+}
+
+// Row side: dx_i = V_i - Q1bar_i^-1 (X_i (dY Y^T) [+ (R dY^T)_i]), dr, and the
+// same three records.
+template <int K, bool EXACT>
+__global__ __launch_bounds__(NTHR) void k_post_x(AnlsParams p, IpmArgs ia, double mu, double tau, int recbase) {
+    constexpr int NL = K * (K + 1) / 2;
+    __shared__ double T[K * K];
+    __shared__ double lds[NTHR];
+    for (int q = threadIdx.x; q < K * K; q += NTHR) T[q] = ia.sc->T[q];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    double slope = 0.0, a1 = INFINITY, a2 = INFINITY;
+    if (i < p.n) {
+        double x[K], u[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) x[a] = p.X[(int64_t)a * p.ldX + i];
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            double v = EXACT ? ia.tX[(int64_t)b * p.ldX + i] : 0.0;
+#pragma unroll
+            for (int a = 0; a < K; ++a) v = fma(x[a], T[a * K + b], v);
+            u[b] = v;
+        }
+        // w = L^-T L^-1 u
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            double v = u[r];
+#pragma unroll
+            for (int q = 0; q < r; ++q) v -= ia.Lq[(int64_t)(r * (r + 1) / 2 + q) * p.ldX + i] * u[q];
+            u[r] = v * ia.Lq[(int64_t)(NL + r) * p.ldX + i];
+        }
+#pragma unroll
+        for (int r = K - 1; r >= 0; --r) {
+            double v = u[r];
+#pragma unroll
+            for (int q = r + 1; q < K; ++q) v -= ia.Lq[(int64_t)(q * (q + 1) / 2 + r) * p.ldX + i] * u[q];
+            u[r] = v * ia.Lq[(int64_t)(NL + r) * p.ldX + i];
+        }
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * p.ldX + i;
+            const double d = ia.V[o] - u[a];
+            const double r = ia.r[o];
+            ia.dx[o] = d;
+            const double drv = mu / x[a] - r - (r / x[a]) * d;
+            ia.dr[o] = drv;
+            slope = fma(d, ia.gx[o] - mu / x[a], slope);
+            if (d < 0.0) { const double c = -tau * x[a] / d; a1 = c < a1 ? c : a1; }
+            if (drv < 0.0) { const double c = -tau * r / drv; a2 = c < a2 ? c : a2; }
+        }
+    }
+    a1 = wave_min(a1);
+    a2 = wave_min(a2);
+    const double vals[1] = {slope};
+    double *rec = ia.part + (size_t)(recbase + blockIdx.x) * PRS;
+    block_reduce_fn<1>([&](int idx) { return vals[idx]; }, rec, lds);
+    __shared__ double mins[2][NTHR / 64];
+    if ((threadIdx.x & 63) == 0) {
+        mins[0][threadIdx.x >> 6] = a1;
+        mins[1][threadIdx.x >> 6] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double m = mins[threadIdx.x][0];
+        for (int w = 1; w < NTHR / 64; ++w) m = mins[threadIdx.x][w] < m ? mins[threadIdx.x][w] : m;
+        rec[1 + threadIdx.x] = m;
+    }
+}
+
+// ---------------------------------------------------------------- dense Cholesky of S
+// Diagonal block [k0, k0 + nb) factored in LDS.  Sets sc->chol_fail on a
+// non-positive pivot (the factorisation then continues with pivot 1).
+__global__ __launch_bounds__(256) void k_chol_diag(double *S, int64_t ldS, int64_t N, int64_t k0, IpmScal *sc) {
+    __shared__ double A[CB][CB + 1];
+    const int nb = (int)min((int64_t)CB, N - k0);
+    for (int q = threadIdx.x; q < CB * CB; q += 256) {
+        const int r = q % CB, c = q / CB;
+        A[r][c] = (r < nb && c < nb && r >= c) ? S[(k0 + c) * ldS + k0 + r] : 0.0;
+    }
+    __syncthreads();
+    const int r = threadIdx.x & 63, part = threadIdx.x >> 6;
+    bool bad = false;
+    for (int c = 0; c < nb; ++c) {
+        if (threadIdx.x == 0) {
+            const double d = A[c][c];
+            if (!(d > 0.0)) bad = true;
+            A[c][c] = sqrt(d > 0.0 ? d : 1.0);
+        }
+        __syncthreads();
+        const double ip = 1.0 / A[c][c];
+        if (part == 0 && r > c && r < nb) A[r][c] *= ip;
+        __syncthreads();
+        if (r > c && r < nb) {
+            const double arc = A[r][c];
+            for (int c2 = c + 1 + part; c2 <= r; c2 += 4) A[r][c2] -= arc * A[c2][c];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && bad) sc->chol_fail = 1;
+    for (int q = threadIdx.x; q < CB * CB; q += 256) {
+        const int rr = q % CB, c = q / CB;
+        if (rr < nb && c < nb && rr >= c) S[(k0 + c) * ldS + k0 + rr] = A[rr][c];
+    }
+}
+
+// Panel below the diagonal block: L[r, k0:k0+CB] = S[r, k0:k0+CB] L_kk^-T, one row per thread.
+__global__ __launch_bounds__(256) void k_chol_trsm(double *S, int64_t ldS, int64_t N, int64_t k0) {
+    __shared__ double Lk[CB][CB + 1];
+    for (int q = threadIdx.x; q < CB * CB; q += 256) {
+        const int r = q % CB, c = q / CB;
+        Lk[r][c] = r >= c ? S[(k0 + c) * ldS + k0 + r] : 0.0;
+    }
+    __syncthreads();
+    const int64_t row = k0 + CB + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= N) return;
+    double x[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        double v = S[(k0 + c) * ldS + row];
+#pragma unroll
+        for (int q = 0; q < c; ++q) v -= x[q] * Lk[c][q];
+        x[c] = v / Lk[c][c];
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) S[(k0 + c) * ldS + row] = x[c];
+}
+
+// Trailing update of the lower triangle: S[r][c] -= sum_q P[r][q] P[c][q] over
+// 64 x 64 tiles (R >= C) of [k0 + CB, N)^2.
+__global__ __launch_bounds__(256) void k_chol_syrk(double *S, int64_t ldS, int64_t N, int64_t k0) {
+    __shared__ double PR[CB][CB + 1];
+    __shared__ double PC[CB][CB + 1];
+    const int64_t T0 = k0 + CB;
+    const int64_t tix = blockIdx.x;
+    int64_t R = (int64_t)((sqrt(8.0 * (double)tix + 1.0) - 1.0) * 0.5);
+    while ((R + 1) * (R + 2) / 2 <= tix) ++R;
+    while (R * (R + 1) / 2 > tix) --R;
+    const int64_t C = tix - R * (R + 1) / 2;
+    const int64_t rb = T0 + R * CB, cb = T0 + C * CB;
+    for (int q = threadIdx.x; q < CB * CB; q += 256) {
+        const int rr = q % CB, kk = q / CB;
+        PR[rr][kk] = (rb + rr < N) ? S[(k0 + kk) * ldS + rb + rr] : 0.0;
+        PC[rr][kk] = (cb + rr < N) ? S[(k0 + kk) * ldS + cb + rr] : 0.0;
+    }
+    __syncthreads();
+    const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int kk = 0; kk < CB; ++kk) {
+        double pr[4], pc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            pr[a] = PR[tr + a][kk];
+            pc[a] = PC[tc + a][kk];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = fma(pr[a], pc[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t row = rb + tr + a, col = cb + tc + b;
+            if (row < N && col < N && row >= col) S[col * ldS + row] -= acc[a][b];
+        }
+    }
+}
+
+// Forward solve step: every block solves y_k = L_kk^-1 b_k (b_k read from
+// vec); block 0 stores y_k in out; the others update the rows below.
+__global__ __launch_bounds__(256) void k_trsv_fwd(const double *S, int64_t ldS, int64_t N, int64_t k0, double *vec,
+                                                  double *out) {
+    __shared__ double Lk[CB][CB + 1];
+    __shared__ double y[CB];
+    const int nb = (int)min((int64_t)CB, N - k0);
+    for (int q = threadIdx.x; q < CB * CB; q += 256) {
+        const int r = q % CB, c = q / CB;
+        Lk[r][c] = (r < nb && c < nb && r >= c) ? S[(k0 + c) * ldS + k0 + r] : 0.0;
+    }
+    if ((int)threadIdx.x < CB) y[threadIdx.x] = (int)threadIdx.x < nb ? vec[k0 + threadIdx.x] : 0.0;
+    __syncthreads();
+    {
+        const int r = threadIdx.x;   // every thread reaches every barrier
+        for (int c = 0; c < nb; ++c) {
+            if (r == c) y[c] = y[c] / Lk[c][c];
+            __syncthreads();
+            if (r > c && r < nb) y[r] -= Lk[r][c] * y[c];
+            __syncthreads();
+        }
+    }
+    if (blockIdx.x == 0) {
+        if ((int)threadIdx.x < nb) out[k0 + threadIdx.x] = y[threadIdx.x];
+        return;
+    }
+    const int64_t row = k0 + nb + (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x;
+    if (row >= N) return;
+    double v = vec[row];
+    for (int q = 0; q < nb; ++q) v -= S[(k0 + q) * ldS + row] * y[q];
+    vec[row] = v;
+}
+
+// Backward solve step with L^T: blocks solve L_kk^T x_k = vec_k; block 0
+// stores x_k; the others update the rows above: vec[r] -= sum_q L[k0+q][r] x_q.
+__global__ __launch_bounds__(256) void k_trsv_bwd(const double *S, int64_t ldS, int64_t N, int64_t k0, double *vec,
+                                                  double *out) {
+    __shared__ double Lk[CB][CB + 1];
+    __shared__ double x[CB];
+    const int nb = (int)min((int64_t)CB, N - k0);
+    for (int q = threadIdx.x; q < CB * CB; q += 256) {
+        const int r = q % CB, c = q / CB;
+        Lk[r][c] = (r < nb && c < nb && r >= c) ? S[(k0 + c) * ldS + k0 + r] : 0.0;
+    }
+    if ((int)threadIdx.x < CB) x[threadIdx.x] = (int)threadIdx.x < nb ? vec[k0 + threadIdx.x] : 0.0;
+    __syncthreads();
+    {
+        const int r = threadIdx.x;   // every thread reaches every barrier
+        for (int c = nb - 1; c >= 0; --c) {
+            if (r == c) x[c] = x[c] / Lk[c][c];
+            __syncthreads();
+            if (r < c) x[r] -= Lk[c][r] * x[c];
+            __syncthreads();
+        }
+    }
+    if (blockIdx.x == 0) {
+        if ((int)threadIdx.x < nb) out[k0 + threadIdx.x] = x[threadIdx.x];
+        return;
+    }
+    const int64_t row = (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x;
+    if (row >= k0) return;
+    double v = vec[row];
+    for (int q = 0; q < nb; ++q) v -= S[row * ldS + k0 + q] * x[q];
+    vec[row] = v;
+}
+
+// ---------------------------------------------------------------- line search
+// Six inner products over M: [0] <R0,R0>, [1] <R0,A>, [2] <A,A>, [3] <R0,B>,
+// [4] <A,B>, [5] <B,B>, R0 = XY - M, A = dX Y + X dY, B = dX dY.
+template <int K>
+__global__ __launch_bounds__(STHR) void k_ls_quartic(AnlsParams p, IpmArgs ia, double *lspart) {
+    __shared__ double lds[2 * XCHUNK * K > STHR ? 2 * XCHUNK * K : STHR];
+    double *ys = lds, *dys = lds + XCHUNK * K;
+    const int tile = blockIdx.x, split = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)tile * XTILE + lane;
+    const int64_t j0 = (int64_t)split * p.xcols;
+    const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
+    const bool row_ok = i < p.n;
+    double x[K], dx[K], c[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        x[a] = row_ok ? p.X[(int64_t)a * p.ldX + i] : 0.0;
+        dx[a] = row_ok ? ia.dx[(int64_t)a * p.ldX + i] : 0.0;
+    }
+    for (int64_t c0 = j0; c0 < j1; c0 += XCHUNK) {
+        const int nc = (int)min((int64_t)XCHUNK, j1 - c0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nc * K; q += STHR) {
+            const int jj = q / K, a = q - jj * K;
+            ys[q] = p.Y[(int64_t)a * p.ldY + c0 + jj];
+            dys[q] = ia.dy[(int64_t)a * p.ldY + c0 + jj];
+        }
+        __syncthreads();
+        if (row_ok) {
+            const double *mp = p.M + c0 * p.ldM + i;
+            for (int jj = w; jj < nc; jj += SWAVES) {
+                const double mv = mp[(int64_t)jj * p.ldM];
+                double R0 = -mv, A = 0.0, B = 0.0;
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    const double y = ys[jj * K + a], dy = dys[jj * K + a];
+                    R0 = fma(x[a], y, R0);
+                    A = fma(dx[a], y, A);
+                    A = fma(x[a], dy, A);
+                    B = fma(dx[a], dy, B);
+                }
+                c[0] = fma(R0, R0, c[0]);
+                c[1] = fma(R0, A, c[1]);
+                c[2] = fma(A, A, c[2]);
+                c[3] = fma(R0, B, c[3]);
+                c[4] = fma(A, B, c[4]);
+                c[5] = fma(B, B, c[5]);
+            }
+        }
+    }
+    __syncthreads();
+    block_reduce_fn<6>([&](int idx) { return c[idx]; }, lspart + ((int64_t)tile * p.Sx + split) * 8, lds);
+}
+
+// Barrier sums for NTRIAL steps a_t = a_base / 2^t:
+// record[t] = sum over the block's entries of log1p(a_t d / v).
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_ls_barrier(AnlsParams p, IpmArgs ia, double a_base) {
+    __shared__ double lds[NTHR];
+    const Side sd = side_of<K>(p, ia, true);
+    double acc[NTRIAL];
+#pragma unroll
+    for (int t = 0; t < NTRIAL; ++t) acc[t] = 0.0;
+    if (sd.ok) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * sd.ld + sd.e;
+            const double q = sd.d[o] / sd.v[o];
+            double at = a_base;
+#pragma unroll
+            for (int t = 0; t < NTRIAL; ++t) {
+                acc[t] += log1p(at * q);
+                at *= 0.5;
+            }
+        }
+    }
+    block_reduce_fn<NTRIAL>([&](int idx) { return acc[idx]; }, ia.part + (size_t)blockIdx.x * PRS, lds);
+}
+
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_update(AnlsParams p, IpmArgs ia, double a1, double a2) {
+    const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    if (e < p.n) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * p.ldX + e;
+            p.X[o] += a1 * ia.dx[o];
+            ia.r[o] += a2 * ia.dr[o];
+        }
+    }
+    if (e < p.m) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * p.ldY + e;
+            p.Y[o] += a1 * ia.dy[o];
+            ia.s[o] += a2 * ia.ds[o];
+        }
+    }
+}
+
+// Predictor probe, eq. (8): [0] sum (v + a1 d)(dual + a2 ddual).
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_muaff(AnlsParams p, IpmArgs ia, double a1, double a2) {
+    __shared__ double lds[NTHR];
+    const Side sd = side_of<K>(p, ia, true);
+    const double *dd = (int)blockIdx.x < p.Bx ? ia.dr : ia.ds;
+    double acc = 0.0;
+    if (sd.ok) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const int64_t o = (int64_t)a * sd.ld + sd.e;
+            acc += (sd.v[o] + a1 * sd.d[o]) * (sd.dual[o] + a2 * dd[o]);
+        }
+    }
+    const double vals[1] = {acc};
+    block_reduce_fn<1>([&](int idx) { return vals[idx]; }, ia.part + (size_t)blockIdx.x * PRS, lds);
+}
+
+// Stage-1 masks from the signs (used when the context returns to stage 1).
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_masks(AnlsParams p) {
+    const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    if (e < p.n) {
+        uint32_t P = 0;
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+            if (p.X[(int64_t)a * p.ldX + e] > 0.0) P |= 1u << a;
+        p.xmask[e] = P;
+    }
+    if (e < p.m) {
+        uint32_t P = 0;
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+            if (p.Y[(int64_t)a * p.ldY + e] > 0.0) P |= 1u << a;
+        p.ymask[e] = P;
+    }
+}
+
+// Duals out: R as n x K row-major, S as K x m row-major.
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_duals_out(AnlsParams p, IpmArgs ia, double *R, double *S) {
+    const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    if (R && e < p.n) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) R[e * K + a] = ia.r[(int64_t)a * p.ldX + e];
+    }
+    if (S && e < p.m) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) S[(int64_t)a * p.m + e] = ia.s[(int64_t)a * p.ldY + e];
+    }
+}
+
+// ================================================================= host side
+#define IPM_K_SWITCH(K, CALL)                                \
+    switch (K) {                                             \
+        case 1: { constexpr int KK = 1; CALL; } break;       \
+        case 2: { constexpr int KK = 2; CALL; } break;       \
+        case 3: { constexpr int KK = 3; CALL; } break;       \
+        case 4: { constexpr int KK = 4; CALL; } break;       \
+        case 5: { constexpr int KK = 5; CALL; } break;       \
+        case 6: { constexpr int KK = 6; CALL; } break;       \
+        case 7: { constexpr int KK = 7; CALL; } break;       \
+        case 8: { constexpr int KK = 8; CALL; } break;       \
+        case 9: { constexpr int KK = 9; CALL; } break;       \
+        case 10: { constexpr int KK = 10; CALL; } break;     \
+        case 11: { constexpr int KK = 11; CALL; } break;     \
+        case 12: { constexpr int KK = 12; CALL; } break;     \
+        case 13: { constexpr int KK = 13; CALL; } break;     \
+        case 14: { constexpr int KK = 14; CALL; } break;     \
+        case 15: { constexpr int KK = 15; CALL; } break;     \
+        case 16: { constexpr int KK = 16; CALL; } break;     \
+        default: return hipErrorInvalidValue;                \
+    }
+
+#define IPM_KS(K, CALL)                                \
+    switch (K) {                                             \
+        case 1: { constexpr int KK = 1; CALL; } break;       \
+        case 2: { constexpr int KK = 2; CALL; } break;       \
+        case 3: { constexpr int KK = 3; CALL; } break;       \
+        case 4: { constexpr int KK = 4; CALL; } break;       \
+        case 5: { constexpr int KK = 5; CALL; } break;       \
+        case 6: { constexpr int KK = 6; CALL; } break;       \
+        case 7: { constexpr int KK = 7; CALL; } break;       \
+        case 8: { constexpr int KK = 8; CALL; } break;       \
+        case 9: { constexpr int KK = 9; CALL; } break;       \
+        case 10: { constexpr int KK = 10; CALL; } break;     \
+        case 11: { constexpr int KK = 11; CALL; } break;     \
+        case 12: { constexpr int KK = 12; CALL; } break;     \
+        case 13: { constexpr int KK = 13; CALL; } break;     \
+        case 14: { constexpr int KK = 14; CALL; } break;     \
+        case 15: { constexpr int KK = 15; CALL; } break;     \
+        case 16: { constexpr int KK = 16; CALL; } break;     \
+        default: return NMF_EINVAL;                    \
+    }
+
+static size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+struct IpmLayout {
+    size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Qi, Z, S, vec, vec2, part, fpart, sc, total;
+    int64_t ldX, ldY, ldS;
+};
+
+static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
+    IpmLayout L;
+    L.ldX = (n + 63) / 64 * 64;
+    L.ldY = (m_cap + 63) / 64 * 64;
+    const int64_t N = m_cap * K;
+    L.ldS = (N + 63) / 64 * 64;
+    const int NL = K * (K + 1) / 2;
+    const int64_t Tn = (n + XTILE - 1) / XTILE;
+    // block records: rows + columns, then a second column-sized range
+    const int64_t nblk = (n + NTHR - 1) / NTHR + 2 * ((m_cap + NTHR - 1) / NTHR) + 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t at = off; off = al(off + bytes); return at; };
+    const size_t vx = (size_t)K * L.ldX * 8, vy = (size_t)K * L.ldY * 8;
+    L.r = take(vx); L.dx = take(vx); L.dr = take(vx); L.gx = take(vx); L.V = take(vx); L.tX = take(vx);
+    L.s = take(vy); L.dy = take(vy); L.ds = take(vy); L.gy = take(vy); L.tY = take(vy);
+    L.Lq = take((size_t)(NL + K) * L.ldX * 8);
+    L.Qi = take((size_t)NL * L.ldX * 8);
+    L.Z = take((size_t)n * K * L.ldY * 8);
+    L.S = take((size_t)N * L.ldS * 8);
+    L.vec = take((size_t)L.ldS * 8);
+    L.vec2 = take((size_t)L.ldS * 8);
+    L.part = take((size_t)nblk * PRS * 8);
+    L.fpart = take((size_t)Tn * 64 * 8 * sizeof(double));   // Tn * Sx records of 8 (Sx <= 64)
+    L.sc = take(sizeof(IpmScal));
+    L.total = off;
+    return L;
+}
+
+size_t ipm_workspace_bytes(int64_t n, int64_t m_cap, int K) { return ipm_layout(n, m_cap, K).total + 256; }
+
+nmf_status ipm_bind(IpmState &s, uint8_t *base, int64_t n, int64_t m_cap, int K) {
+    const IpmLayout L = ipm_layout(n, m_cap, K);
+    s.n = n; s.m_cap = m_cap; s.K = K; s.ldX = L.ldX; s.ldY = L.ldY; s.ldS = L.ldS;
+    s.r = (double *)(base + L.r); s.s = (double *)(base + L.s);
+    s.dx = (double *)(base + L.dx); s.dy = (double *)(base + L.dy);
+    s.dr = (double *)(base + L.dr); s.ds = (double *)(base + L.ds);
+    s.gx = (double *)(base + L.gx); s.gy = (double *)(base + L.gy);
+    s.V = (double *)(base + L.V); s.tX = (double *)(base + L.tX); s.tY = (double *)(base + L.tY);
+    s.Lq = (double *)(base + L.Lq); s.Qi = (double *)(base + L.Qi); s.Z = (double *)(base + L.Z);
+    s.S = (double *)(base + L.S); s.vec = (double *)(base + L.vec); s.vec2 = (double *)(base + L.vec2);
+    s.part = (double *)(base + L.part); s.fpart = (double *)(base + L.fpart);
+    s.sc = (IpmScal *)(base + L.sc);
+    s.bound = true;
+    return NMF_OK;
+}
+
 const char *ipm_last_error(const IpmState &s) { return s.err.c_str(); }
+
+namespace {
+
+struct Ctx {
+    IpmState &s;
+    const AnlsParams &p;
+    const nmf_options &o;
+    hipStream_t st;
+    IpmArgs ia;
+    int K;
+};
+
+#define HCK(call)                                             \
+    do {                                                      \
+        hipError_t _e = (call);                               \
+        if (_e != hipSuccess) {                               \
+            c.s.err = std::string(#call) + ": " + hipGetErrorString(_e); \
+            return NMF_EDEVICE;                               \
+        }                                                     \
+    } while (0)
+
+dim3 g1(int64_t count) { return dim3((unsigned)((count + NTHR - 1) / NTHR)); }
+
+hipError_t finish(Ctx &c, const double *part, int stride, int nblk, int nval, unsigned minmask, double *out) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(NTHR), 0, c.st, part, stride, nblk, nval, minmask, out);
+    return hipGetLastError();
+}
+
+nmf_status read_out(Ctx &c, double *host, int nval) {
+    HCK(hipMemcpyAsync(host, c.s.sc->out, sizeof(double) * nval, hipMemcpyDeviceToHost, c.st));
+    HCK(hipStreamSynchronize(c.st));
+    return NMF_OK;
+}
+
+// Gradients (residual form), f, G_X and G_Y at the current point.
+hipError_t point_products(Ctx &c) {
+    const AnlsParams &p = c.p;
+    hipError_t e;
+    IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_rstream_x<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, p.Y,
+                                          p.bx_part, c.s.fpart));
+    hipLaunchKernelGGL(k_sum_splits, g1(p.n), dim3(NTHR), 0, c.st, p.bx_part, p.Sx, c.K, p.ldX, p.n, c.s.gx);
+    if ((e = finish(c, c.s.fpart, 1, p.Tn * p.Sx, 1, 0u, &c.s.sc->f)) != hipSuccess) return e;
+    IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_rstream_y<KK>, dim3(p.Tm, p.Sy), dim3(STHR), 0, c.st, p, p.X,
+                                          p.by_part));
+    hipLaunchKernelGGL(k_sum_splits, g1(p.m), dim3(NTHR), 0, c.st, p.by_part, p.Sy, c.K, p.ldY, p.m, c.s.gy);
+    IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, p.X, p.ldX, p.n, c.s.part));
+    if ((e = finish(c, c.s.part, PRS, p.Bx, c.K * c.K, 0u, c.s.sc->GX)) != hipSuccess) return e;
+    IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_outer<KK>, g1(p.m), dim3(NTHR), 0, c.st, p.Y, p.Y, p.ldY, p.m, c.s.part));
+    if ((e = finish(c, c.s.part, PRS, p.By, c.K * c.K, 0u, c.s.sc->GY)) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+// KKT sums at the current point for barrier parameter mu; fills S1, C0, Cmu,
+// E0, Emu and f.
+nmf_status kkt(Ctx &c, double mu) {
+    const AnlsParams &p = c.p;
+    IPM_KS(c.K, hipLaunchKernelGGL(k_kkt<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, mu));
+    HCK(finish(c, c.s.part, PRS, p.Bx + p.By, 4, 0u, c.s.sc->out));
+    double h[4];
+    nmf_status st = read_out(c, h, 4);
+    if (st != NMF_OK) return st;
+    double f = 0.0;
+    HCK(hipMemcpyAsync(&f, &c.s.sc->f, sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HCK(hipStreamSynchronize(c.st));
+    c.s.S1 = h[0];
+    c.s.SR = h[3];
+    c.s.C0 = h[1];
+    c.s.Cmu = h[2];
+    c.s.f = 0.5 * f;
+    c.s.E0 = fmax(sqrt(h[0]), sqrt(h[1]));
+    c.s.Emu = fmax(sqrt(h[0]), sqrt(h[2]));
+    return NMF_OK;
+}
+
+nmf_status cholesky(Ctx &c, int64_t N) {
+    double *S = c.s.S;
+    const int64_t ldS = c.s.ldS;
+    for (int64_t k0 = 0; k0 < N; k0 += CB) {
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, c.st, S, ldS, N, k0, c.s.sc);
+        const int64_t below = N - k0 - CB;
+        if (below > 0) {
+            hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, c.st, S, ldS, N, k0);
+            const int64_t nt = (below + CB - 1) / CB;
+            hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, c.st, S, ldS, N, k0);
+        }
+    }
+    HCK(hipGetLastError());
+    return NMF_OK;
+}
+
+// vec2 = S^-1 vec (S = L L^T, factored in place); vec is overwritten.
+nmf_status solve_S(Ctx &c, int64_t N) {
+    double *S = c.s.S;
+    const int64_t ldS = c.s.ldS;
+    for (int64_t k0 = 0; k0 < N; k0 += CB) {
+        const int64_t below = N - k0 - CB;
+        const unsigned nb = 1 + (below > 0 ? (unsigned)((below + 255) / 256) : 0u);
+        hipLaunchKernelGGL(k_trsv_fwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, c.s.vec, c.s.vec2);
+    }
+    // backward on vec2 (y) -> vec (x)
+    const int64_t last = (N - 1) / CB * CB;
+    for (int64_t k0 = last; k0 >= 0; k0 -= CB) {
+        const unsigned nb = 1 + (unsigned)((k0 + 255) / 256);
+        hipLaunchKernelGGL(k_trsv_bwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, c.s.vec2, c.s.vec);
+    }
+    HCK(hipMemcpyAsync(c.s.vec2, c.s.vec, sizeof(double) * N, hipMemcpyDeviceToDevice, c.st));
+    HCK(hipGetLastError());
+    return NMF_OK;
+}
+
+struct Dir {
+    bool ok;        // false: Cholesky of S failed
+    double slope, a1, a2;
+};
+
+// Newton direction of eq. (12) at the current point with barrier parameter
+// mu (0 for the predictor) and the Hessian eq. (26) (exact = false) or eq.
+// (27) (exact = true).  Leaves dx, dy, dr, ds and the step-rule quantities.
+nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
+    const AnlsParams &p = c.p;
+    const int K = c.K;
+    const int64_t N = p.m * K;
+    const double rho = c.s.rho;
+    // factors of Q1bar, V = Q1bar^-1 b1, X^T V
+    if (exact) {
+        IPM_KS(K, hipLaunchKernelGGL((k_factor<KK, true>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, rho));
+    } else {
+        IPM_KS(K, hipLaunchKernelGGL((k_factor<KK, false>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, rho));
+    }
+    IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, c.s.V, p.ldX, p.n, c.s.part));
+    HCK(finish(c, c.s.part, PRS, p.Bx, K * K, 0u, c.s.sc->XtV));
+    const bool reuse = !exact && c.s.S_gn_valid;
+    if (!reuse) {
+        static const int zero = 0;
+        HCK(hipMemcpyAsync(&c.s.sc->chol_fail, &zero, sizeof(int), hipMemcpyHostToDevice, c.st));
+        IPM_KS(K, hipLaunchKernelGGL(k_zmat<KK>, dim3((unsigned)((p.n + ZRB - 1) / ZRB)), dim3(NTHR), 0, c.st,
+                                           p, c.ia));
+        const int64_t nt = (p.m + TJ - 1) / TJ;
+        const dim3 gs((unsigned)(nt * (nt + 1) / 2));
+        if (exact) {
+            IPM_KS(K, hipLaunchKernelGGL((k_schur<KK, true>), gs, dim3(256), 0, c.st, p, c.ia, rho));
+        } else {
+            IPM_KS(K, hipLaunchKernelGGL((k_schur<KK, false>), gs, dim3(256), 0, c.st, p, c.ia, rho));
+        }
+        nmf_status st = cholesky(c, N);
+        if (st != NMF_OK) return st;
+        int fail = 0;
+        HCK(hipMemcpyAsync(&fail, &c.s.sc->chol_fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
+        HCK(hipStreamSynchronize(c.st));
+        c.s.S_gn_valid = false;
+        if (fail) {
+            d.ok = false;
+            return NMF_OK;
+        }
+        c.s.S_gn_valid = !exact;
+    }
+    if (exact) {
+        IPM_KS(K, hipLaunchKernelGGL(k_rstream_y<KK>, dim3(p.Tm, p.Sy), dim3(STHR), 0, c.st, p, c.s.V,
+                                           p.by_part));
+        hipLaunchKernelGGL(k_sum_splits, g1(p.m), dim3(NTHR), 0, c.st, p.by_part, p.Sy, K, p.ldY, p.m, c.s.tY);
+        IPM_KS(K, hipLaunchKernelGGL((k_rhs<KK, true>), g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu));
+    } else {
+        IPM_KS(K, hipLaunchKernelGGL((k_rhs<KK, false>), g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu));
+    }
+    nmf_status st = solve_S(c, N);
+    if (st != NMF_OK) return st;
+    IPM_KS(K, hipLaunchKernelGGL(k_post_y<KK>, g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu, tau, 0));
+    IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.m), dim3(NTHR), 0, c.st, c.s.dy, p.Y, p.ldY, p.m,
+                                       c.s.part + (size_t)(p.By + p.Bx) * PRS));
+    HCK(finish(c, c.s.part + (size_t)(p.By + p.Bx) * PRS, PRS, p.By, K * K, 0u, c.s.sc->T));
+    if (exact) {
+        IPM_KS(K, hipLaunchKernelGGL(k_rstream_x<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, c.s.dy,
+                                           p.bx_part, (double *)nullptr));
+        hipLaunchKernelGGL(k_sum_splits, g1(p.n), dim3(NTHR), 0, c.st, p.bx_part, p.Sx, K, p.ldX, p.n, c.s.tX);
+        IPM_KS(K, hipLaunchKernelGGL((k_post_x<KK, true>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, tau,
+                                           p.By));
+    } else {
+        IPM_KS(K, hipLaunchKernelGGL((k_post_x<KK, false>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, tau,
+                                           p.By));
+    }
+    HCK(finish(c, c.s.part, PRS, p.By + p.Bx, 3, 0x6u, c.s.sc->out));
+    double h[3];
+    st = read_out(c, h, 3);
+    if (st != NMF_OK) return st;
+    d.ok = true;
+    d.slope = h[0];
+    d.a1 = h[1] < 1.0 ? h[1] : 1.0;
+    d.a2 = h[2] < 1.0 ? h[2] : 1.0;
+    return NMF_OK;
+}
+
+// Armijo backtracking (eq. (13)) on the closed-form quartic plus barrier sums.
+// Returns the accepted step in *al.
+nmf_status line_search(Ctx &c, const Dir &d, double mu, double *al) {
+    const AnlsParams &p = c.p;
+    double *lspart = c.s.fpart;   // reused: Tn*Sx records of 8
+    IPM_KS(c.K, hipLaunchKernelGGL(k_ls_quartic<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, c.ia, lspart));
+    HCK(finish(c, lspart, 8, p.Tn * p.Sx, 6, 0u, c.s.sc->out));
+    double q[6];
+    nmf_status st = read_out(c, q, 6);
+    if (st != NMF_OK) return st;
+    const int maxb = c.o.max_backtracks;
+    for (int t0 = 0; t0 <= maxb; t0 += NTRIAL) {
+        const double abase = d.a1 / ldexp(1.0, t0);
+        IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, abase));
+        HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out));
+        double bar[NTRIAL];
+        st = read_out(c, bar, NTRIAL);
+        if (st != NMF_OK) return st;
+        for (int t = 0; t < NTRIAL && t0 + t <= maxb; ++t) {
+            const double a = d.a1 / ldexp(1.0, t0 + t);
+            const double dq = 0.5 * (2.0 * a * q[1] + a * a * (q[2] + 2.0 * q[3]) + 2.0 * a * a * a * q[4] +
+                                     a * a * a * a * q[5]);
+            const double dphi = dq - mu * bar[t];
+            if (dphi <= c.o.eta * a * d.slope) {
+                c.s.backtracks += t0 + t;
+                *al = a;
+                return NMF_OK;
+            }
+        }
+    }
+    c.s.backtracks += maxb;
+    c.s.cap_hits += 1;
+    *al = d.a1 / ldexp(1.0, maxb);
+    return NMF_OK;
+}
+
+nmf_status update_point(Ctx &c, double a1, double a2) {
+    const AnlsParams &p = c.p;
+    const int64_t e = p.n > p.m ? p.n : p.m;
+    IPM_KS(c.K, hipLaunchKernelGGL(k_update<KK>, g1(e), dim3(NTHR), 0, c.st, p, c.ia, a1, a2));
+    c.s.S_gn_valid = false;
+    HCK(point_products(c));
+    return kkt(c, c.s.mu);
+}
+
+// One inner iteration of Alg. 3 (direction with the flag rule, step rules,
+// Armijo search, update).
+nmf_status inner_iteration(Ctx &c) {
+    IpmState &s = c.s;
+    const double mu = s.mu;
+    Dir d;
+    d.ok = false;
+    bool have = false;
+    nmf_status st;
+    if (s.flag == 1 && c.o.exact_hessian_switch) {
+        st = direction(c, mu, true, c.o.tau, d);
+        if (st != NMF_OK) return st;
+        if (d.ok && d.slope < 0.0) {
+            have = true;
+            s.exact_steps += 1;
+        } else {
+            s.flag = 0;
+            s.fallbacks += 1;
+        }
+    }
+    if (!have) {
+        st = direction(c, mu, false, c.o.tau, d);
+        if (st != NMF_OK) return st;
+        if (!d.ok) {
+            s.err = "Cholesky factorisation of the Gauss-Newton Schur matrix failed";
+            return NMF_ESINGULAR;
+        }
+    }
+    double al = 0.0;
+    st = line_search(c, d, mu, &al);
+    if (st != NMF_OK) return st;
+    s.iters += 1;
+    s.at_mu += 1;
+    return update_point(c, al, d.a2);
+}
+
+// Predictor probe and the mu update of Alg. 3 (eq. (8), (9)).
+nmf_status mu_update(Ctx &c) {
+    IpmState &s = c.s;
+    const AnlsParams &p = c.p;
+    Dir d;
+    nmf_status st = direction(c, 0.0, false, 1.0, d);
+    if (st != NMF_OK) return st;
+    if (!d.ok) {
+        s.err = "Cholesky factorisation of the predictor Schur matrix failed";
+        return NMF_ESINGULAR;
+    }
+    IPM_KS(c.K, hipLaunchKernelGGL(k_muaff<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, d.a1, d.a2));
+    HCK(finish(c, s.part, PRS, p.Bx + p.By, 1, 0u, s.sc->out));
+    double h[1];
+    st = read_out(c, h, 1);
+    if (st != NMF_OK) return st;
+    const double Nn = (double)(p.n + p.m) * c.K;
+    const double avg = s.SR / Nn;   // current average complementarity
+    const double mu_aff = h[0] / Nn;
+    double r = mu_aff / avg;
+    double sigma = r * r * r;
+    if (sigma > 0.99) sigma = 0.99;
+    s.sigma = sigma;
+    s.mu = sigma * avg;
+    s.flag = (sigma <= c.o.sigma_c) ? 1 : 0;
+    return kkt(c, s.mu);
+}
+
+}  // namespace
+
+nmf_status ipm_transition(IpmState &s, const AnlsParams &p, const nmf_options &o, hipStream_t st) {
+    if (!s.bound) { s.err = "no stage-2 workspace"; return NMF_ESTATE; }
+    Ctx c{s, p, o, st, args_of(s), s.K};
+    // rho0 = 1e-6 max(x, y) on the stage-1 point, eq. (22)
+    IPM_KS(c.K, hipLaunchKernelGGL(k_maxes<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, st, p, c.ia, 0));
+    HCK(finish(c, s.part, PRS, p.Bx + p.By, 2, 0x3u, s.sc->out));
+    double mx[2];
+    nmf_status r = read_out(c, mx, 2);
+    if (r != NMF_OK) return r;
+    const double vmax = fmax(-mx[0], -mx[1]);
+    const double rho0 = o.rho0_factor * vmax;
+    IPM_KS(c.K, hipLaunchKernelGGL(k_clamp<KK>, g1(p.n > p.m ? p.n : p.m), dim3(NTHR), 0, st, p, rho0));
+    HCK(point_products(c));
+    // r = max |graX| e, s = max |graY| e at the clamped point, eq. (23)
+    IPM_KS(c.K, hipLaunchKernelGGL(k_maxes<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, st, p, c.ia, 1));
+    HCK(finish(c, s.part, PRS, p.Bx + p.By, 2, 0x3u, s.sc->out));
+    r = read_out(c, mx, 2);
+    if (r != NMF_OK) return r;
+    const double rv = fmax(-mx[0], o.eps_tol), sv = fmax(-mx[1], o.eps_tol);
+    IPM_KS(c.K, hipLaunchKernelGGL(k_fill_duals<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, st, p, c.ia, rv, sv));
+    HCK(finish(c, s.part, PRS, p.Bx + p.By, 2, 0u, s.sc->out));
+    double sums[2];
+    r = read_out(c, sums, 2);
+    if (r != NMF_OK) return r;
+    const double Nn = (double)(p.n + p.m) * c.K;
+    s.mu = (rv * sums[0] + sv * sums[1]) / Nn;   // eq. (24)
+    s.rho = o.rho;                               // eq. (25)
+    s.flag = 0;
+    s.in_inner = false;
+    s.S_gn_valid = false;
+    s.at_mu = 0;
+    s.iters = s.outer = s.backtracks = s.exact_steps = s.fallbacks = s.cap_hits = 0;
+    s.sigma = 0.0;
+    return kkt(c, s.mu);
+}
+
+nmf_status ipm_iterate(IpmState &s, const AnlsParams &p, const nmf_options &o, int iters, hipStream_t st) {
+    Ctx c{s, p, o, st, args_of(s), s.K};
+    int budget = iters;
+    for (;;) {
+        if (!s.in_inner) {
+            if (s.E0 <= o.eps_tol) return NMF_CONVERGED;
+            if (s.iters >= o.max_ipm_iters || s.outer >= o.max_ipm_iters) return NMF_ENOTCONV;
+            s.outer += 1;
+            s.eps_mu = s.mu;
+            s.at_mu = 0;
+            s.in_inner = true;
+        }
+        if (s.Emu > s.eps_mu && s.E0 > o.eps_tol && s.iters < o.max_ipm_iters && s.at_mu < o.inner_cap) {
+            if (budget <= 0) return NMF_OK;
+            nmf_status r = inner_iteration(c);
+            if (r != NMF_OK) return r;
+            --budget;
+            continue;
+        }
+        s.in_inner = false;
+        if (s.E0 <= o.eps_tol) return NMF_CONVERGED;
+        if (s.iters >= o.max_ipm_iters) return NMF_ENOTCONV;
+        nmf_status r = mu_update(c);
+        if (r != NMF_OK) return r;
+    }
+}
+
+nmf_status ipm_report(IpmState &s, nmf_report *r, double ms1, double ms2) {
+    r->stage = 2;
+    r->f = s.f;
+    r->E0 = s.E0;
+    r->Emu = s.Emu;
+    r->mu = s.mu;
+    r->sigma = s.sigma;
+    r->flag = s.flag;
+    r->ipm_iters = s.iters;
+    r->ipm_outer = s.outer;
+    r->backtracks = s.backtracks;
+    r->exact_steps = s.exact_steps;
+    r->fallbacks = s.fallbacks;
+    r->ms_stage1 = ms1;
+    r->ms_stage2 = ms2;
+    return NMF_OK;
+}
+
+nmf_status ipm_export(IpmState &s, const AnlsParams &p, hipStream_t st) {
+    if (!s.bound) return NMF_OK;
+    const int64_t e = p.n > p.m ? p.n : p.m;
+    switch (s.K) {
+#define MK(KK) case KK: hipLaunchKernelGGL(k_masks<KK>, dim3((unsigned)((e + NTHR - 1) / NTHR)), dim3(NTHR), 0, st, p); break;
+        MK(1) MK(2) MK(3) MK(4) MK(5) MK(6) MK(7) MK(8) MK(9) MK(10) MK(11) MK(12) MK(13) MK(14) MK(15) MK(16)
+#undef MK
+        default: return NMF_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? NMF_OK : NMF_EDEVICE;
+}
+
+nmf_status ipm_get_duals(IpmState &s, const AnlsParams &p, double *R, double *S, hipStream_t st) {
+    if (!s.bound) return NMF_ESTATE;
+    const int64_t e = p.n > p.m ? p.n : p.m;
+    IpmArgs ia = args_of(s);
+    double *stR = s.tX, *stS = s.tY;
+    switch (s.K) {
+#define MK(KK) case KK: hipLaunchKernelGGL(k_duals_out<KK>, dim3((unsigned)((e + NTHR - 1) / NTHR)), dim3(NTHR), 0, st, p, ia, R ? stR : nullptr, S ? stS : nullptr); break;
+        MK(1) MK(2) MK(3) MK(4) MK(5) MK(6) MK(7) MK(8) MK(9) MK(10) MK(11) MK(12) MK(13) MK(14) MK(15) MK(16)
+#undef MK
+        default: return NMF_EINVAL;
+    }
+    if (R && hipMemcpyAsync(R, stR, (size_t)p.n * s.K * 8, hipMemcpyDefault, st) != hipSuccess) return NMF_EDEVICE;
+    if (S && hipMemcpyAsync(S, stS, (size_t)p.m * s.K * 8, hipMemcpyDefault, st) != hipSuccess) return NMF_EDEVICE;
+    return hipStreamSynchronize(st) == hipSuccess ? NMF_OK : NMF_EDEVICE;
+}
 
 }  // namespace nmfk

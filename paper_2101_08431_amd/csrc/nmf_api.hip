@@ -119,6 +119,7 @@ struct nmf_ctx {
     double mnorm2 = 0.0;
     double ms1 = 0.0, ms2 = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevStatus last1;   // stage-1 status at the hand-over to stage 2
     nmfk::IpmState ipm;
     std::string err;
 };
@@ -483,7 +484,12 @@ static nmf_status measure_stage1(nmf_ctx *c) {
 nmf_status nmf_get_report(nmf_ctx *c, nmf_report *r) {
     if (!c || !r) return NMF_EINVAL;
     memset(r, 0, sizeof(*r));
-    if (c->stage == 2) return nmfk::ipm_report(c->ipm, r, c->ms1, c->ms2);
+    if (c->stage == 2) {
+        nmfk::ipm_report(c->ipm, r, c->ms1, c->ms2);
+        r->sweeps = c->last1.sweeps;
+        r->nnls_solves = (int64_t)c->last1.solves;
+        return NMF_OK;
+    }
     nmf_status st = measure_stage1(c);
     if (st != NMF_OK) return st;
     DevStatus ds;
@@ -514,6 +520,13 @@ nmf_status nmf_get_masks(nmf_ctx *c, uint32_t *xm, uint32_t *ym) {
     if (ym) HIPCHK(c, hipMemcpyAsync(ym, c->p.ymask, (size_t)c->m * 4, hipMemcpyDefault, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return NMF_OK;
+}
+
+nmf_status nmf_get_duals(nmf_ctx *c, double *R, double *S) {
+    if (!c) return NMF_EINVAL;
+    if (c->stage != 2) return fail(c, NMF_ESTATE, "duals exist in stage 2 only");
+    nmf_status st = nmfk::ipm_get_duals(c->ipm, c->p, R, S, c->stream);
+    return st == NMF_OK ? NMF_OK : fail(c, st, "dual export failed");
 }
 
 nmf_status nmf_append_columns(nmf_ctx *c, const double *Mnew, int64_t mnew, int64_t ldm) {
@@ -547,6 +560,7 @@ nmf_status nmf_append_columns(nmf_ctx *c, const double *Mnew, int64_t mnew, int6
     c->m = m_old + mnew;
     refresh_shape(c);
     // the Y-half over all columns: the new ones start from their neighbour
+    HIPCHK(c, nmfk::launch_gram_x_init(c->K, c->p, s));
     AnlsParams p = c->p;
     p.mode = 2;
     HIPCHK(c, nmfk::launch_yhalf(c->K, p, s));
@@ -562,6 +576,8 @@ nmf_status nmf_ipm_step(nmf_ctx *c, int32_t iters, nmf_report *r) {
     if (!c->opt.with_ipm) return fail(c, NMF_ESTATE, "context created without stage-2 workspace");
     if (iters < 0) return fail(c, NMF_EINVAL, "iters < 0");
     if (c->stage == 1) {
+        nmf_status rs = read_status(c, c->last1);
+        if (rs != NMF_OK) return rs;
         nmf_status st = nmfk::ipm_transition(c->ipm, c->p, c->opt, c->stream);
         if (st != NMF_OK) return fail(c, st, nmfk::ipm_last_error(c->ipm));
         c->stage = 2;
@@ -579,6 +595,11 @@ nmf_status nmf_ipm_step(nmf_ctx *c, int32_t iters, nmf_report *r) {
         memset(r, 0, sizeof(*r));
         nmf_status rs = nmfk::ipm_report(c->ipm, r, c->ms1, c->ms2);
         if (rs != NMF_OK) return fail(c, rs, "report failed");
+        r->sweeps = c->last1.sweeps;
+        r->nnls_solves = (int64_t)c->last1.solves;
+        r->nnls_failed = (int64_t)c->last1.fails;
+        r->mask_changes = (int64_t)c->last1.changes;
+        r->step_rel = sqrt(c->last1.step2) / (1.0 + sqrt(c->last1.norm2));
     }
     return st;
 }

@@ -71,6 +71,7 @@ hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_gram_y_init(int K, const AnlsParams &p, hipStream_t s);
+hipError_t launch_gram_x_init(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_objective(int K, const AnlsParams &p, double *part, int nblk, hipStream_t s);
 hipError_t launch_check_finite(const double *M, int64_t n, int64_t m, int64_t ldM, double *part,
                                int nblk, hipStream_t s);

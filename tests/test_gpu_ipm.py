@@ -1,0 +1,160 @@
+"""Stage 2 (transition and interior-point iterations) on the GPU against the
+CPU oracle, from the same starting point.
+
+The starting point is the oracle's own stage-1 end point (inputs flow from the
+oracle to the GPU, never back).  The transition is deterministic and is
+compared entry by entry; a few IPM iterations are compared as trajectories
+(the Armijo decisions agree away from rounding ties); converged end points are
+compared after removing the scaling freedom, and certified independently by
+the KKT conditions eq. (3).
+"""
+import numpy as np
+import pytest
+
+from paper_2101_08431_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def start_point(orc, name, seed, sweeps=None, eps_stol=1e-6):
+    M, X0, Y0 = synth.make(name, seed)
+    if sweeps is None:
+        r = orc.anls(M, X0, Y0.T.copy(), eps_stol=eps_stol, max_sweeps=5000)
+    else:
+        r = orc.anls(M, X0, Y0.T.copy(), exact_sweeps=sweeps)
+    return np.asarray(M), r["X"], r["Yt"]
+
+
+def gpu_ctx(M, X, Yt, **opt):
+    from paper_2101_08431_amd import NMF, default_options
+    base = dict(eps_stol=-1.0, max_anls_sweeps=1 << 30)
+    base.update(opt)
+    return NMF(np.asfortranarray(M), X.shape[1], np.ascontiguousarray(X), np.ascontiguousarray(Yt.T),
+               options=default_options(**base))
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_transition_matches_oracle(orc):
+    M, X, Yt = start_point(orc, "pdf_200x50_k3", 0)
+    print("case transition pdf_200x50_k3 seed 0", flush=True)
+    ctx = gpu_ctx(M, X, Yt, eps_tol=1e-10)
+    st, rep = ctx.ipm_step(0)
+    Xo, Yo, ro, so, muo, rhoo = orc.transition(M, X, Yt, 1e-10)
+    Xg, Yg = ctx.factors()
+    Rg, Sg = ctx.duals()
+    assert rel(Xg, Xo) <= 1e-14 and rel(Yg.T, Yo) <= 1e-14
+    assert rel(Rg, ro) <= 1e-10 and rel(Sg.T, so) <= 1e-10
+    assert rep["mu"] == pytest.approx(muo, rel=1e-10)
+    gx, gy, _ = orc.gradients(M, Xo, Yo)
+    assert rep["E0"] == pytest.approx(orc.kkt_error(Xo, Yo, ro, so, 0.0, gx, gy), rel=1e-8)
+    assert rep["Emu"] == pytest.approx(orc.kkt_error(Xo, Yo, ro, so, muo, gx, gy), rel=1e-8)
+
+
+@pytest.mark.parametrize("name,seed,iters", [("pdf_200x50_k3", 0, 1), ("pdf_200x50_k3", 0, 3),
+                                             ("pdf_200x50_k3", 1, 6)])
+def test_first_iterations_match_oracle(orc, name, seed, iters):
+    M, X, Yt = start_point(orc, name, seed)
+    print(f"case ipm iterations {name} seed {seed} iters {iters}", flush=True)
+    ctx = gpu_ctx(M, X, Yt, eps_tol=1e-10)
+    ctx.ipm_step(iters)
+    Xg, Yg = ctx.factors()
+    Rg, Sg = ctx.duals()
+    opts = orc.IPMOptions(eps_tol=1e-10, max_inner=iters)
+    X1, Y1, r1, s1, mu1, rho1 = orc.transition(M, X, Yt, 1e-10)
+    res = orc.ipm(M, X1, Y1, r1, s1, mu1, rho1, opts)
+    assert res.inner == iters
+    assert rel(Xg, res.X) <= 1e-7 and rel(Yg.T, res.Yt) <= 1e-7
+    assert rel(Rg, res.r) <= 1e-6 and rel(Sg.T, res.s) <= 1e-6
+
+
+@pytest.mark.parametrize("seed", [0, 1, 4])
+def test_full_solve_200x50x3_matches_oracle(orc, seed):
+    M, X, Yt = start_point(orc, "pdf_200x50_k3", seed)
+    print(f"case full solve pdf_200x50_k3 seed {seed}", flush=True)
+    ctx = gpu_ctx(M, X, Yt, eps_tol=1e-10)
+    st, rep = ctx.ipm_step(1000)
+    assert st == 1, rep
+    Xg, Yg = ctx.factors()
+    X1, Y1, r1, s1, mu1, rho1 = orc.transition(M, X, Yt, 1e-10)
+    res = orc.ipm(M, X1, Y1, r1, s1, mu1, rho1, orc.IPMOptions(eps_tol=1e-10))
+    assert res.converged
+    fg = orc.objective(M, Xg, Yg.T.copy())
+    fo = orc.objective(M, res.X, res.Yt)
+    assert abs(fg - fo) <= 1e-10 * fo + 1e-16 * 0.5 * np.sum(M * M)
+    Xn, Yn = orc.normalise(Xg, Yg.T)
+    Xon, Yon = orc.normalise(res.X, res.Yt)
+    assert rel(Xn, Xon) <= 1e-6 and rel(Yn, Yon) <= 1e-6
+    # independent certificate: E(.;0) from the GPU's own iterate and duals
+    Rg, Sg = ctx.duals()
+    gx, gy, _ = orc.gradients(M, Xg, Yg.T)
+    assert orc.kkt_error(Xg, Yg.T, Rg, Sg.T, 0.0, gx, gy) <= 2e-10
+    assert rep["E0"] <= 1e-10
+
+
+def test_nmf_solve_two_stages_200x50x3(orc):
+    M, X0, Y0 = synth.make("pdf_200x50_k3", 2)
+    from paper_2101_08431_amd import NMF, default_options
+    ctx = NMF(np.asarray(M), 3, X0, Y0, options=default_options(eps_tol=1e-10))
+    st, rep = ctx.solve()
+    assert st == 1 and rep["stage"] == 2 and rep["E0"] <= 1e-10
+    ref = orc.solve(np.asarray(M), X0, Y0.T.copy(), orc.IPMOptions(eps_tol=1e-10))
+    assert ref["converged"]
+    Xg, Yg = ctx.factors()
+    fg = orc.objective(M, Xg, Yg.T.copy())
+    assert abs(fg - ref["f"]) <= 1e-10 * ref["f"]
+    assert abs(rep["sweeps"] - ref["stage1"]["sweeps"]) <= 1
+
+
+def test_separable_recovery_gpu(orc):
+    n, m, k = 40, 20, 3
+    M, xs, ys = synth.separable(n, m, k, 3)
+    X0, Y0 = synth.perturbed_init(xs, ys, 3, 0.1)
+    from paper_2101_08431_amd import NMF, default_options
+    ctx = NMF(np.asarray(M), k, X0, Y0, options=default_options(eps_tol=1e-10))
+    st, rep = ctx.solve()
+    assert st == 1
+    Xg, Yg = ctx.factors()
+    assert orc.objective(M, Xg, Yg.T.copy()) <= 1e-14 * 0.5 * np.sum(np.asarray(M) ** 2)
+    Xn, Ytn = orc.normalise(Xg, Yg.T)
+    Xt, Ytt = orc.normalise(xs, ys.T)
+    perm = [int(np.argmax(np.abs(Xn.T @ Xt[:, a]))) for a in range(k)]
+    assert sorted(perm) == list(range(k))
+    np.testing.assert_allclose(Xn[:, perm], Xt, atol=1e-6)
+
+
+def test_full_solve_3000x500x5_certificate(orc):
+    M, X0, Y0 = synth.make("pdf_3000x500_k5", 0)
+    print("case nmf_solve pdf_3000x500_k5 seed 0 to 1e-8", flush=True)
+    from paper_2101_08431_amd import NMF, default_options
+    ctx = NMF(np.asarray(M), 5, X0, Y0, options=default_options(eps_tol=1e-8, max_ipm_iters=400))
+    st, rep = ctx.solve()
+    print(rep, flush=True)
+    assert st == 1 and rep["E0"] <= 1e-8
+    Xg, Yg = ctx.factors()
+    Rg, Sg = ctx.duals()
+    gx, gy, _ = orc.gradients(np.asarray(M), Xg, Yg.T)
+    assert orc.kkt_error(Xg, Yg.T, Rg, Sg.T, 0.0, gx, gy) <= 2e-8
+    assert np.all(Xg > 0) and np.all(Yg > 0)
+
+
+def test_append_after_stage2_returns_to_stage1(orc):
+    n, k, m0, add = 300, 3, 40, 16
+    M, _, _ = synth.pdf_like(n, m0 + add, k, 9, sigma=1e-3, sigma_relative=True)
+    M = np.asarray(M)
+    X0, Y0 = synth.random_init(n, m0, k, 9, float(np.linalg.norm(M[:, :m0])))
+    from paper_2101_08431_amd import NMF, default_options
+    ctx = NMF(np.asfortranarray(M[:, :m0]), k, X0, Y0, m_capacity=m0 + add,
+              options=default_options(eps_tol=1e-9))
+    st, rep = ctx.solve()
+    assert st == 1
+    ctx.append_columns(np.asfortranarray(M[:, m0:]))
+    assert ctx.m == m0 + add
+    st, rep = ctx.solve()
+    assert st == 1 and rep["E0"] <= 1e-9
+    Xg, Yg = ctx.factors()
+    Rg, Sg = ctx.duals()
+    gx, gy, _ = orc.gradients(M, Xg, Yg.T)
+    assert orc.kkt_error(Xg, Yg.T, Rg, Sg.T, 0.0, gx, gy) <= 2e-9
