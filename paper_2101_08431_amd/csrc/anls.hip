@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "../../include/nmf.h"
 #include "device_util.h"
 #include "nmf_internal.h"
 #include "nnls_lh.h"
@@ -80,12 +81,39 @@ __device__ __forceinline__ void block_stats_and_gram(const double (&st)[NST], co
 }
 
 // ---------------------------------------------------------------- X-half
-template <int K>
+// Element (i, j) of M in the arithmetic type of precision P: FP64 from M,
+// FP32 from the 4-byte copy, or the sum of its BF16 high and low parts.
+template <int P>
+struct MElem;
+template <>
+struct MElem<NMF_GRAM_FP64> {
+    using T = double;
+    static __device__ __forceinline__ double load(const AnlsParams &p, int64_t off) { return p.M[off]; }
+};
+template <>
+struct MElem<NMF_GRAM_FP32> {
+    using T = float;
+    static __device__ __forceinline__ float load(const AnlsParams &p, int64_t off) {
+        return __uint_as_float(p.Mlo[off]);
+    }
+};
+template <>
+struct MElem<NMF_GRAM_BF16X2> {
+    using T = float;
+    static __device__ __forceinline__ float load(const AnlsParams &p, int64_t off) {
+        const uint32_t u = p.Mlo[off];
+        return __uint_as_float(u & 0xFFFF0000u) + __uint_as_float(u << 16);
+    }
+};
+
+template <int K, int P>
 __global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) {
     if (p.mode == 0 && p.st->converged) return;
+    using T = typename MElem<P>::T;
     constexpr int RED = SWAVES * K * XTILE;
     constexpr int LDSN = (XCHUNK * K > RED) ? XCHUNK * K : RED;
     __shared__ double lds[LDSN];   // Y chunk while streaming, then the wave sums
+    T *ys = reinterpret_cast<T *>(lds);
     const int tile = blockIdx.x, split = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = (int64_t)tile * XTILE + lane;
@@ -93,38 +121,38 @@ __global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) {
     const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
     const bool row_ok = i < p.n;
 
-    double acc[K];
+    T acc[K];
 #pragma unroll
-    for (int a = 0; a < K; ++a) acc[a] = 0.0;
+    for (int a = 0; a < K; ++a) acc[a] = T(0);
     for (int64_t c0 = j0; c0 < j1; c0 += XCHUNK) {
         const int nc = (int)min((int64_t)XCHUNK, j1 - c0);
         __syncthreads();
         for (int q = threadIdx.x; q < nc * K; q += STHR) {
             const int jj = q / K, a = q - jj * K;
-            lds[q] = p.Y[(int64_t)a * p.ldY + c0 + jj];
+            ys[q] = (T)p.Y[(int64_t)a * p.ldY + c0 + jj];
         }
         __syncthreads();
-        const double *mp = p.M + c0 * p.ldM + (row_ok ? i : 0);
+        const int64_t base = c0 * p.ldM + (row_ok ? i : 0);
         for (int jb = w; jb < nc; jb += 8 * SWAVES) {
-            double mv[8];
+            T mv[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int jj = jb + t * SWAVES;
-                mv[t] = (jj < nc && row_ok) ? mp[(int64_t)jj * p.ldM] : 0.0;
+                mv[t] = (jj < nc && row_ok) ? MElem<P>::load(p, base + (int64_t)jj * p.ldM) : T(0);
             }
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const int jj = jb + t * SWAVES;
                 if (jj < nc) {
 #pragma unroll
-                    for (int a = 0; a < K; ++a) acc[a] = fma(mv[t], lds[jj * K + a], acc[a]);
+                    for (int a = 0; a < K; ++a) acc[a] = fma(mv[t], ys[jj * K + a], acc[a]);
                 }
             }
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < K; ++a) lds[(w * K + a) * XTILE + lane] = acc[a];
+    for (int a = 0; a < K; ++a) lds[(w * K + a) * XTILE + lane] = (double)acc[a];
     __syncthreads();
     if (w == 0 && row_ok) {
 #pragma unroll
@@ -198,9 +226,10 @@ __global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) {
 }
 
 // ---------------------------------------------------------------- Y-half
-template <int K>
+template <int K, int P>
 __global__ __launch_bounds__(STHR) void k_ystream(AnlsParams p) {
     if (p.mode == 0 && p.st->converged) return;
+    using T = typename MElem<P>::T;
     constexpr int J = YVALS / K;
     __shared__ double red[SWAVES * YVALS];
     const int ct = blockIdx.x, split = blockIdx.y;
@@ -210,23 +239,23 @@ __global__ __launch_bounds__(STHR) void k_ystream(AnlsParams p) {
     const int64_t r0 = (int64_t)split * p.yrows;
     const int64_t r1 = min(r0 + (int64_t)p.yrows, p.n);
 
-    double v[YVALS];
+    T v[YVALS];
 #pragma unroll
-    for (int q = 0; q < YVALS; ++q) v[q] = 0.0;
+    for (int q = 0; q < YVALS; ++q) v[q] = T(0);
     for (int64_t i = r0 + threadIdx.x; i < r1; i += STHR) {
-        double x[K], mv[J];
+        T x[K], mv[J];
 #pragma unroll
-        for (int a = 0; a < K; ++a) x[a] = p.X[(int64_t)a * p.ldX + i];
-        const double *mp = p.M + jb * p.ldM + i;
+        for (int a = 0; a < K; ++a) x[a] = (T)p.X[(int64_t)a * p.ldX + i];
+        const int64_t base = jb * p.ldM + i;
 #pragma unroll
-        for (int jj = 0; jj < J; ++jj) mv[jj] = (jj < nj) ? mp[(int64_t)jj * p.ldM] : 0.0;
+        for (int jj = 0; jj < J; ++jj) mv[jj] = (jj < nj) ? MElem<P>::load(p, base + (int64_t)jj * p.ldM) : T(0);
 #pragma unroll
         for (int jj = 0; jj < J; ++jj) {
 #pragma unroll
             for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
         }
     }
-    red[w * YVALS + lane] = wave_transpose_reduce(v, lane);
+    red[w * YVALS + lane] = (double)wave_transpose_reduce(v, lane);
     __syncthreads();
     if ((int)threadIdx.x < nj * K) {
         double s = red[threadIdx.x];
@@ -483,6 +512,30 @@ __global__ void k_factor_out(AnlsParams p, double *dx, double *dy) {
     }
 }
 
+// The 4-byte copy of columns [j0, j1) of M: FP32 (round to nearest), or the
+// BF16 high part (round to nearest of the FP32 value) with the BF16 of the
+// remainder in the low half.
+__global__ __launch_bounds__(NTHR) void k_make_lowprec(AnlsParams p, int64_t j0, int64_t j1) {
+    const int64_t total = p.n * (j1 - j0);
+    for (int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x; e < total; e += (int64_t)gridDim.x * NTHR) {
+        const int64_t j = j0 + e / p.n, i = e % p.n;
+        const int64_t off = j * p.ldM + i;
+        const float f = (float)p.M[off];
+        uint32_t out;
+        if (p.prec == NMF_GRAM_FP32) {
+            out = __float_as_uint(f);
+        } else {
+            const uint32_t u = __float_as_uint(f);
+            const uint32_t hi = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;   // round to nearest even
+            const float rem = f - __uint_as_float(hi);
+            const uint32_t ur = __float_as_uint(rem);
+            const uint32_t lo = ((ur + 0x7FFFu + ((ur >> 16) & 1u)) >> 16) & 0xFFFFu;
+            out = hi | lo;
+        }
+        const_cast<uint32_t *>(p.Mlo)[off] = out;
+    }
+}
+
 // Columns [j0, j1) of Y start from column j_from and its passive set (the
 // neighbouring-column warm start for appended time instants).
 template <int K>
@@ -519,7 +572,14 @@ __global__ void k_copy_columns_warm(AnlsParams p, int64_t j_from, int64_t j0, in
 int yhalf_cols(int K) { return K >= 1 && K <= KMAX ? YVALS / K : 0; }
 
 hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s) {
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_xstream<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, s, p));
+    const dim3 g(p.Tn, p.Sx);
+    if (p.prec == NMF_GRAM_FP32) {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xstream<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
+    } else if (p.prec == NMF_GRAM_BF16X2) {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xstream<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, p));
+    } else {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xstream<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, p));
+    }
     return hipGetLastError();
 }
 
@@ -529,7 +589,14 @@ hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s) {
 }
 
 hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s) {
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_ystream<KK>, dim3(p.Tm, p.Sy), dim3(STHR), 0, s, p));
+    const dim3 g(p.Tm, p.Sy);
+    if (p.prec == NMF_GRAM_FP32) {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_ystream<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
+    } else if (p.prec == NMF_GRAM_BF16X2) {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_ystream<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, p));
+    } else {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_ystream<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, p));
+    }
     return hipGetLastError();
 }
 
@@ -587,6 +654,12 @@ hipError_t launch_factor_in(int K, const double *sx, const double *sy, const Anl
 
 hipError_t launch_factor_out(int K, const AnlsParams &p, double *dx, double *dy, hipStream_t s) {
     NMF_K_SWITCH(K, hipLaunchKernelGGL(k_factor_out<KK>, grid_rows(p), dim3(NTHR), 0, s, p, dx, dy));
+    return hipGetLastError();
+}
+
+hipError_t launch_make_lowprec(const AnlsParams &p, int64_t j0, int64_t j1, hipStream_t s) {
+    if (p.prec == NMF_GRAM_FP64 || j1 <= j0) return hipSuccess;
+    hipLaunchKernelGGL(k_make_lowprec, dim3(1024), dim3(NTHR), 0, s, p, j0, j1);
     return hipGetLastError();
 }
 

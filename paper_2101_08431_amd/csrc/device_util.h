@@ -30,8 +30,8 @@ __device__ __forceinline__ bool last_arrival(unsigned *cnt, unsigned expected, u
 
 // One butterfly step: lanes that differ in bit H swap halves of v[0..2H) and
 // keep the sum of the half named by their bit.
-template <int H>
-__device__ __forceinline__ void transpose_step(double (&v)[YVALS], int lane) {
+template <int H, class T>
+__device__ __forceinline__ void transpose_step(T (&v)[YVALS], int lane) {
     const bool up = (lane & H) != 0;
 #pragma unroll
     for (int q = 0; q < H; ++q) {
@@ -42,7 +42,8 @@ __device__ __forceinline__ void transpose_step(double (&v)[YVALS], int lane) {
 }
 
 // Lane l of the wave ends up with the sum over the 64 lanes of v[l].
-__device__ __forceinline__ double wave_transpose_reduce(double (&v)[YVALS], int lane) {
+template <class T>
+__device__ __forceinline__ T wave_transpose_reduce(T (&v)[YVALS], int lane) {
     transpose_step<32>(v, lane);
     transpose_step<16>(v, lane);
     transpose_step<8>(v, lane);

@@ -70,7 +70,7 @@ struct Carve {
 };
 
 struct Offsets {
-    size_t M, X, Y, xmask, ymask, bx, by, gx, gy, xst, yst, cntf, status, red, io, bad;
+    size_t M, Mlo, X, Y, xmask, ymask, bx, by, gx, gy, xst, yst, cntf, status, red, io, bad;
     size_t ipm_base, total;
 };
 
@@ -80,6 +80,7 @@ Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
     Offsets L;
     Carve c;
     L.M = c.take<double>((size_t)P.ldM * m_cap);
+    L.Mlo = c.take<uint32_t>(o.gram_precision != NMF_GRAM_FP64 ? (size_t)P.ldM * m_cap : 0);
     L.X = c.take<double>((size_t)K * P.ldX);
     L.Y = c.take<double>((size_t)K * P.ldY);
     L.xmask = c.take<uint32_t>(P.ldX);
@@ -240,8 +241,8 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
     if (o.inner_cap < 1 || o.check_every < 1 || !(o.tau > 0 && o.tau < 1) || !(o.eta > 0 && o.eta < 1) ||
         o.x_splits < 0 || o.x_splits > kSxMax || o.y_splits < 0 || o.y_splits > kSyMax)
         return fail(nullptr, NMF_EINVAL, "invalid options");
-    if (o.gram_precision != NMF_GRAM_FP64)
-        return fail(nullptr, NMF_EINVAL, "only NMF_GRAM_FP64 is available in this build");
+    if (o.gram_precision < NMF_GRAM_FP64 || o.gram_precision > NMF_GRAM_BF16X2)
+        return fail(nullptr, NMF_EINVAL, "unknown gram_precision");
     const Offsets L = layout(n, m_capacity, k, o);
     if (!device_workspace || ws_bytes < L.total)
         return fail(nullptr, NMF_ENOMEM, "workspace smaller than nmf_workspace_bytes()");
@@ -262,6 +263,8 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
     memset(&p, 0, sizeof(p));
     uint8_t *w = c->ws;
     p.M = (const double *)(w + L.M);
+    p.Mlo = (const uint32_t *)(w + L.Mlo);
+    p.prec = o.gram_precision;
     p.X = (double *)(w + L.X);
     p.Y = (double *)(w + L.Y);
     p.xmask = (uint32_t *)(w + L.xmask);
@@ -305,6 +308,7 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
     CHK(hipMemcpy2DAsync((void *)p.M, (size_t)p.ldM * 8, M, (size_t)ldm * 8, (size_t)n * 8, (size_t)m,
                          hipMemcpyDefault, s));
     CHK(nmfk::launch_check_finite(p.M, n, m, p.ldM, c->red, kRedBlocks, s));
+    CHK(nmfk::launch_make_lowprec(p, 0, m, s));
     std::vector<double> red(2 * kRedBlocks);
     CHK(hipMemcpyAsync(red.data(), c->red, red.size() * 8, hipMemcpyDeviceToHost, s));
     CHK(hipStreamSynchronize(s));
@@ -475,6 +479,7 @@ nmf_status nmf_anls_profile(nmf_ctx *c, int32_t sweeps, double *ms_x, double *ms
 static nmf_status measure_stage1(nmf_ctx *c) {
     AnlsParams p = c->p;
     p.mode = 1;
+    p.prec = NMF_GRAM_FP64;   // the reported KKT error is always measured in FP64
     HIPCHK(c, nmfk::launch_xhalf(c->K, p, c->stream));
     HIPCHK(c, nmfk::launch_measure_finish(c->K, p, c->stream));
     HIPCHK(c, nmfk::launch_objective(c->K, p, c->red, kRedBlocks, c->stream));
@@ -556,6 +561,7 @@ nmf_status nmf_append_columns(nmf_ctx *c, const double *Mnew, int64_t mnew, int6
     }
     const int64_t m_old = c->m;
     c->mnorm2 += add;
+    HIPCHK(c, nmfk::launch_make_lowprec(c->p, m_old, m_old + mnew, s));
     HIPCHK(c, nmfk::launch_copy_columns_warm(c->K, c->p, m_old - 1, m_old, m_old + mnew, s));
     c->m = m_old + mnew;
     refresh_shape(c);

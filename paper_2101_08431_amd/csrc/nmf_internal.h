@@ -46,6 +46,8 @@ struct DevStatus {
 struct AnlsParams {
     int64_t n, m, ldM, ldX, ldY;
     const double *M;
+    const uint32_t *Mlo;   // 4-byte copy of M (FP32, or BF16 hi << 16 | BF16 lo), same layout
+    int prec;              // nmf_gram_precision of the two streaming kernels
     double *X, *Y;
     uint32_t *xmask, *ymask;
     double *bx_part;   // [Sx][K][ldX]  split partials of B_X = M Y^T
@@ -78,6 +80,7 @@ hipError_t launch_check_finite(const double *M, int64_t n, int64_t m, int64_t ld
 hipError_t launch_factor_in(int K, const double *src_x, const double *src_y, const AnlsParams &p,
                             unsigned *bad, hipStream_t s);
 hipError_t launch_factor_out(int K, const AnlsParams &p, double *dst_x, double *dst_y, hipStream_t s);
+hipError_t launch_make_lowprec(const AnlsParams &p, int64_t j0, int64_t j1, hipStream_t s);
 hipError_t launch_copy_columns_warm(int K, const AnlsParams &p, int64_t j_from, int64_t j0,
                                     int64_t j1, hipStream_t s);
 

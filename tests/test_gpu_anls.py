@@ -166,3 +166,35 @@ def test_seeded_start_without_x0():
     X, Y = ctx.factors()
     assert np.all(X >= 0) and np.all(Y >= 0)
     assert np.linalg.norm(X @ Y) == pytest.approx(np.linalg.norm(M), rel=1e-12)
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 2e-5), (2, 5e-4)])
+def test_reduced_precision_gram_sweeps(orc, prec, tol):
+    # FP32 or BF16 hi+lo copies of M in the two streaming products, FP32
+    # accumulation; the NNLS stays FP64.  The error against the FP64 oracle
+    # after a few sweeps is bounded by the input rounding (2^-24, resp. about
+    # 2^-16 relative per element) amplified by the conditioning of the sweep.
+    M, X0, Y0 = synth.make("pdf_3000x500_k5", 0)
+    print(f"case precision {prec} pdf_3000x500_k5 sweeps 5", flush=True)
+    ctx = gpu_ctx(M, 5, X0, Y0, gram_precision=prec)
+    ctx.anls_step(5)
+    X, Y = ctx.factors()
+    ref = orc.anls(M, X0, Y0.T.copy(), exact_sweeps=5)
+    err = rel_err(X, Y, ref["X"], ref["Yt"])
+    print(f"precision {prec}: max factor error vs FP64 oracle {err:.3e}", flush=True)
+    assert err <= tol
+    assert err > 0.0      # the reduced path really ran
+
+
+def test_reduced_precision_solve_reaches_fp64_kkt(orc):
+    from paper_2101_08431_amd import NMF, default_options
+    M, X0, Y0 = synth.make("pdf_200x50_k3", 1)
+    out = {}
+    for prec in (0, 1, 2):
+        ctx = NMF(M, 3, X0, Y0, options=default_options(eps_tol=1e-10, gram_precision=prec))
+        st, rep = ctx.solve()
+        assert st == 1 and rep["E0"] <= 1e-10
+        X, Y = ctx.factors()
+        out[prec] = orc.objective(M, X, Y.T.copy())
+    assert abs(out[1] - out[0]) <= 1e-10 * out[0]
+    assert abs(out[2] - out[0]) <= 1e-10 * out[0]
