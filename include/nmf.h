@@ -178,6 +178,43 @@ nmf_status nmf_get_report(nmf_ctx *ctx, nmf_report *report);
  * at once and are still counted. */
 nmf_status nmf_anls_profile(nmf_ctx *ctx, int32_t sweeps, double *ms_xhalf, double *ms_yhalf);
 
+/* Re-plans the stage-1 launch shape of a context: column splits of the X-half
+ * and row splits of the Y-half (0 = automatic, at most 64 each).  Results do
+ * not change beyond the rounding of the split sums.  Used by the autotuner. */
+nmf_status nmf_set_launch_shape(nmf_ctx *ctx, int32_t x_splits, int32_t y_splits);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent problems swept together (stage 1): the contexts of a batch
+ * are grouped by (k, gram precision) and every group runs each of the four
+ * stage-1 kernels as one flattened launch in which each block serves one
+ * problem's block of its own launch shape.  A problem's results are bitwise
+ * the ones its own nmf_anls_step() would give; problems that meet their stop
+ * rule idle.  For callers that sweep many small problems at once. */
+typedef struct nmf_batch nmf_batch;
+
+/* Device workspace a batch of `count` contexts needs (tables and offsets). */
+size_t nmf_batch_workspace_bytes(int32_t count);
+
+/* Builds a batch over ctxs[0..count) (all in stage 1, same device; each stays
+ * owned by the caller and must outlive the batch).  All batch work is
+ * enqueued on hip_stream, which must not be the default stream when graphs
+ * are used.  Errors: NMF_EINVAL, NMF_ENOMEM, NMF_ESTATE, NMF_EDEVICE. */
+nmf_status nmf_batch_create(nmf_ctx *const *ctxs, int32_t count, void *device_workspace, size_t ws_bytes,
+                            void *hip_stream, nmf_batch **out);
+
+/* Re-reads the contexts' sizes and launch shapes (after nmf_set_launch_shape
+ * or nmf_append_columns) and drops any captured graph. */
+nmf_status nmf_batch_refresh(nmf_batch *b);
+
+/* Enqueues `sweeps` stage-1 sweeps of every problem.  use_graph = 1 captures
+ * the sweeps into a HIP graph on first use (per sweep count) and replays it. */
+nmf_status nmf_batch_anls_step(nmf_batch *b, int32_t sweeps, int32_t use_graph);
+
+/* Waits for the batch's stream. */
+nmf_status nmf_batch_sync(nmf_batch *b);
+
+nmf_status nmf_batch_destroy(nmf_batch *b);
+
 /* Current sizes: rows n, columns m, rank k. */
 nmf_status nmf_get_shape(const nmf_ctx *ctx, int64_t *n, int64_t *m, int32_t *k);
 

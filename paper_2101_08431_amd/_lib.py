@@ -22,7 +22,8 @@ EXPORTS = [
     "nmf_default_options", "nmf_workspace_bytes", "nmf_create", "nmf_anls_step", "nmf_ipm_step",
     "nmf_solve", "nmf_append_columns", "nmf_get_factors", "nmf_get_masks", "nmf_get_report",
     "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
-    "nmf_get_duals",
+    "nmf_get_duals", "nmf_set_launch_shape", "nmf_batch_workspace_bytes", "nmf_batch_create",
+    "nmf_batch_refresh", "nmf_batch_anls_step", "nmf_batch_sync", "nmf_batch_destroy",
 ]
 
 
@@ -91,6 +92,17 @@ def load():
     L.nmf_get_report.restype = ctypes.c_int
     L.nmf_anls_profile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.nmf_anls_profile.restype = ctypes.c_int
+    L.nmf_set_launch_shape.argtypes = [vp, i32, i32]
+    L.nmf_set_launch_shape.restype = ctypes.c_int
+    L.nmf_batch_workspace_bytes.argtypes = [i32]
+    L.nmf_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.nmf_batch_create.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.nmf_batch_create.restype = ctypes.c_int
+    for name in ("nmf_batch_refresh", "nmf_batch_sync", "nmf_batch_destroy"):
+        getattr(L, name).argtypes = [vp]
+        getattr(L, name).restype = ctypes.c_int
+    L.nmf_batch_anls_step.argtypes = [vp, i32, i32]
+    L.nmf_batch_anls_step.restype = ctypes.c_int
     L.nmf_get_shape.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.nmf_get_shape.restype = ctypes.c_int
     L.nmf_destroy.argtypes = [vp]
@@ -249,10 +261,60 @@ class NMF:
         self._check(load().nmf_get_masks(self._ctx, _ptr(xm), _ptr(ym)), ok=(NMF_OK,))
         return xm, ym
 
+    def set_launch_shape(self, x_splits, y_splits):
+        self._check(load().nmf_set_launch_shape(self._ctx, int(x_splits), int(y_splits)), ok=(NMF_OK,))
+
     def close(self):
         if getattr(self, "_ctx", None):
             load().nmf_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Stage-1 sweeps of many contexts in shared launches (see nmf_batch_* in
+    include/nmf.h).  Uses its own non-default stream so sweeps can be captured
+    into a HIP graph."""
+
+    def __init__(self, contexts, stream=None):
+        import torch
+        L = load()
+        self.contexts = list(contexts)
+        n = len(self.contexts)
+        nbytes = int(L.nmf_batch_workspace_bytes(n))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        arr = (ctypes.c_void_p * n)(*[c._ctx.value for c in self.contexts])
+        out = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        st = L.nmf_batch_create(arr, n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(out))
+        if st != NMF_OK:
+            raise NMFError(st, L.nmf_last_error(None).decode())
+        self._b = out
+
+    def step(self, sweeps, graph=True):
+        st = load().nmf_batch_anls_step(self._b, int(sweeps), 1 if graph else 0)
+        if st != NMF_OK:
+            raise NMFError(st, "batched sweep failed")
+
+    def refresh(self):
+        st = load().nmf_batch_refresh(self._b)
+        if st != NMF_OK:
+            raise NMFError(st, "batch refresh failed")
+
+    def sync(self):
+        load().nmf_batch_sync(self._b)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            load().nmf_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -107,14 +107,13 @@ struct MElem<NMF_GRAM_BF16X2> {
 };
 
 template <int K, int P>
-__global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) {
+__device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int split) {
     if (p.mode == 0 && p.st->converged) return;
     using T = typename MElem<P>::T;
     constexpr int RED = SWAVES * K * XTILE;
     constexpr int LDSN = (XCHUNK * K > RED) ? XCHUNK * K : RED;
     __shared__ double lds[LDSN];   // Y chunk while streaming, then the wave sums
     T *ys = reinterpret_cast<T *>(lds);
-    const int tile = blockIdx.x, split = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = (int64_t)tile * XTILE + lane;
     const int64_t j0 = (int64_t)split * p.xcols;
@@ -166,12 +165,12 @@ __global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) {
 }
 
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) {
+__device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
     if (p.mode == 0 && p.st->converged) return;
     __shared__ double G[K * K];
     __shared__ double lds[NTHR];
     reduce_records(p.gy_part, p.By, K * K, G, lds);
-    const int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    const int64_t i = (int64_t)bid * NTHR + threadIdx.x;
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
@@ -221,18 +220,17 @@ __global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) {
             st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
         }
     }
-    block_stats_and_gram<K>(st, xn, p.xstat + (int64_t)blockIdx.x * NST,
-                            p.mode == 0 ? p.gx_part + (int64_t)blockIdx.x * K * K : nullptr, lds);
+    block_stats_and_gram<K>(st, xn, p.xstat + (int64_t)bid * NST,
+                            p.mode == 0 ? p.gx_part + (int64_t)bid * K * K : nullptr, lds);
 }
 
 // ---------------------------------------------------------------- Y-half
 template <int K, int P>
-__global__ __launch_bounds__(STHR) void k_ystream(AnlsParams p) {
+__device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int split) {
     if (p.mode == 0 && p.st->converged) return;
     using T = typename MElem<P>::T;
     constexpr int J = YVALS / K;
     __shared__ double red[SWAVES * YVALS];
-    const int ct = blockIdx.x, split = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t jb = (int64_t)ct * J;
     const int nj = (int)min((int64_t)J, p.m - jb);
@@ -267,13 +265,13 @@ __global__ __launch_bounds__(STHR) void k_ystream(AnlsParams p) {
 }
 
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_ynnls(AnlsParams p) {
+__device__ __forceinline__ void ynnls_body(const AnlsParams &p, int bid) {
     if (p.mode == 0 && p.st->converged) return;
     __shared__ double G[K * K];
     __shared__ double lds[NTHR];
     __shared__ unsigned flag;
     reduce_records(p.gx_part, p.Bx, K * K, G, lds);
-    const int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    const int64_t j = (int64_t)bid * NTHR + threadIdx.x;
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
@@ -318,8 +316,7 @@ __global__ __launch_bounds__(NTHR) void k_ynnls(AnlsParams p) {
         st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
         st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
     }
-    block_stats_and_gram<K>(st, yn, p.ystat + (int64_t)blockIdx.x * NST, p.gy_part + (int64_t)blockIdx.x * K * K,
-                            lds);
+    block_stats_and_gram<K>(st, yn, p.ystat + (int64_t)bid * NST, p.gy_part + (int64_t)bid * K * K, lds);
     if (!last_arrival(p.cnt_fin, (unsigned)p.By, &flag)) return;
 
     // ---- last block of the sweep: statistics and the Sec. IV stop rule
@@ -359,6 +356,57 @@ __global__ __launch_bounds__(NTHR) void k_ynnls(AnlsParams p) {
         s->sweeps += 1;
         if (sqrt(step2) <= s->eps_stol * (1.0 + sqrt(norm2)) || s->sweeps >= s->max_sweeps) s->converged = 1;
     }
+}
+
+// ---------------------------------------------------------------- kernels
+// One problem: the grid is the problem's own launch shape.
+template <int K, int P>
+__global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) { xstream_body<K, P>(p, blockIdx.x, blockIdx.y); }
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) { xnnls_body<K>(p, blockIdx.x); }
+template <int K, int P>
+__global__ __launch_bounds__(STHR) void k_ystream(AnlsParams p) { ystream_body<K, P>(p, blockIdx.x, blockIdx.y); }
+template <int K>
+__global__ __launch_bounds__(NTHR) void k_ynnls(AnlsParams p) { ynnls_body<K>(p, blockIdx.x); }
+
+// A batch of problems with the same K and precision: one flattened grid, block
+// b belongs to the problem q with off[q] <= b < off[q + 1] and runs that
+// problem's block b - off[q] of its own launch shape.
+__device__ __forceinline__ int batch_problem(const int *off, int np, int b) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int K, int P>
+__global__ __launch_bounds__(STHR) void kb_xstream(const AnlsParams *tab, const int *off, int np) {
+    const int q = batch_problem(off, np, blockIdx.x);
+    const AnlsParams p = tab[q];
+    const int local = blockIdx.x - off[q];
+    xstream_body<K, P>(p, local % p.Tn, local / p.Tn);
+}
+template <int K>
+__global__ __launch_bounds__(NTHR) void kb_xnnls(const AnlsParams *tab, const int *off, int np) {
+    const int q = batch_problem(off, np, blockIdx.x);
+    const AnlsParams p = tab[q];
+    xnnls_body<K>(p, blockIdx.x - off[q]);
+}
+template <int K, int P>
+__global__ __launch_bounds__(STHR) void kb_ystream(const AnlsParams *tab, const int *off, int np) {
+    const int q = batch_problem(off, np, blockIdx.x);
+    const AnlsParams p = tab[q];
+    const int local = blockIdx.x - off[q];
+    ystream_body<K, P>(p, local % p.Tm, local / p.Tm);
+}
+template <int K>
+__global__ __launch_bounds__(NTHR) void kb_ynnls(const AnlsParams *tab, const int *off, int np) {
+    const int q = batch_problem(off, np, blockIdx.x);
+    const AnlsParams p = tab[q];
+    ynnls_body<K>(p, blockIdx.x - off[q]);
 }
 
 // E(.;0) at the current iterate after a measure-mode k_xnnls: X part from the
@@ -613,6 +661,29 @@ hipError_t launch_xhalf(int K, const AnlsParams &p, hipStream_t s) {
 hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s) {
     hipError_t e = launch_ystream(K, p, s);
     return e != hipSuccess ? e : launch_ynnls(K, p, s);
+}
+
+hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t s) {
+    const AnlsParams *t = g.table;
+    const int *o = g.off;
+    const int np = g.count;
+    if (prec == NMF_GRAM_FP32) {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_xstream<KK, NMF_GRAM_FP32>), dim3(g.blocks[0]), dim3(STHR), 0, s, t, o, np));
+    } else if (prec == NMF_GRAM_BF16X2) {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_xstream<KK, NMF_GRAM_BF16X2>), dim3(g.blocks[0]), dim3(STHR), 0, s, t, o, np));
+    } else {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_xstream<KK, NMF_GRAM_FP64>), dim3(g.blocks[0]), dim3(STHR), 0, s, t, o, np));
+    }
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_xnnls<KK>, dim3(g.blocks[1]), dim3(NTHR), 0, s, t, o + (np + 1), np));
+    if (prec == NMF_GRAM_FP32) {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_ystream<KK, NMF_GRAM_FP32>), dim3(g.blocks[2]), dim3(STHR), 0, s, t, o + 2 * (np + 1), np));
+    } else if (prec == NMF_GRAM_BF16X2) {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_ystream<KK, NMF_GRAM_BF16X2>), dim3(g.blocks[2]), dim3(STHR), 0, s, t, o + 2 * (np + 1), np));
+    } else {
+        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_ystream<KK, NMF_GRAM_FP64>), dim3(g.blocks[2]), dim3(STHR), 0, s, t, o + 2 * (np + 1), np));
+    }
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_ynnls<KK>, dim3(g.blocks[3]), dim3(NTHR), 0, s, t, o + 3 * (np + 1), np));
+    return hipGetLastError();
 }
 
 hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s) {

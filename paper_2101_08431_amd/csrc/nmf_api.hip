@@ -527,6 +527,15 @@ nmf_status nmf_get_masks(nmf_ctx *c, uint32_t *xm, uint32_t *ym) {
     return NMF_OK;
 }
 
+nmf_status nmf_set_launch_shape(nmf_ctx *c, int32_t xs, int32_t ys) {
+    if (!c) return NMF_EINVAL;
+    if (xs < 0 || xs > kSxMax || ys < 0 || ys > kSyMax) return fail(c, NMF_EINVAL, "splits out of range");
+    c->opt.x_splits = xs;
+    c->opt.y_splits = ys;
+    refresh_shape(c);
+    return NMF_OK;
+}
+
 nmf_status nmf_get_duals(nmf_ctx *c, double *R, double *S) {
     if (!c) return NMF_EINVAL;
     if (c->stage != 2) return fail(c, NMF_ESTATE, "duals exist in stage 2 only");
@@ -635,6 +644,178 @@ nmf_status nmf_solve(nmf_ctx *c, nmf_report *r) {
     }
     st = nmf_ipm_step(c, c->opt.max_ipm_iters, r);
     return st;
+}
+
+// ------------------------------------------------------------------ batches
+struct nmf_batch {
+    struct Group {
+        int K = 0, prec = 0;
+        std::vector<int> members;
+        nmfk::BatchGroup g;
+    };
+    std::vector<nmf_ctx *> ctxs;
+    std::vector<Group> groups;
+    hipStream_t stream = nullptr;
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_sweeps = 0;
+    std::string err;
+};
+
+static size_t batch_bytes(int32_t count) {
+    return align_up((size_t)count * sizeof(AnlsParams), 256) + align_up((size_t)4 * (count + 1) * sizeof(int), 256) +
+           256;
+}
+
+static void drop_graph(nmf_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_sweeps = 0;
+}
+
+size_t nmf_batch_workspace_bytes(int32_t count) { return count < 1 ? 0 : batch_bytes(count); }
+
+nmf_status nmf_batch_refresh(nmf_batch *b) {
+    if (!b) return NMF_EINVAL;
+    drop_graph(b);
+    b->groups.clear();
+    for (int q = 0; q < (int)b->ctxs.size(); ++q) {
+        nmf_ctx *c = b->ctxs[q];
+        if (c->stage != 1) {
+            b->err = "every context of a batch must be in stage 1";
+            return NMF_ESTATE;
+        }
+        int gi = -1;
+        for (int t = 0; t < (int)b->groups.size(); ++t)
+            if (b->groups[t].K == c->K && b->groups[t].prec == c->opt.gram_precision) gi = t;
+        if (gi < 0) {
+            b->groups.emplace_back();
+            b->groups.back().K = c->K;
+            b->groups.back().prec = c->opt.gram_precision;
+            gi = (int)b->groups.size() - 1;
+        }
+        b->groups[gi].members.push_back(q);
+    }
+    // tables: all groups' AnlsParams back to back, then their offsets
+    std::vector<AnlsParams> tab;
+    std::vector<int> offs;
+    AnlsParams *dtab = (AnlsParams *)b->ws;
+    int *doff = (int *)(b->ws + align_up(b->ctxs.size() * sizeof(AnlsParams), 256));
+    for (auto &g : b->groups) {
+        const int np = (int)g.members.size();
+        g.g.table = dtab + tab.size();
+        g.g.off = doff + offs.size();
+        g.g.count = np;
+        std::vector<int> o[4];
+        for (auto &v : o) v.assign(1, 0);
+        for (int q : g.members) {
+            AnlsParams p = b->ctxs[q]->p;
+            p.mode = 0;
+            tab.push_back(p);
+            const int cnt[4] = {p.Tn * p.Sx, p.Bx, p.Tm * p.Sy, p.By};
+            for (int k = 0; k < 4; ++k) o[k].push_back(o[k].back() + cnt[k]);
+        }
+        for (int k = 0; k < 4; ++k) {
+            g.g.blocks[k] = o[k].back();
+            offs.insert(offs.end(), o[k].begin(), o[k].end());
+        }
+    }
+    if (hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(AnlsParams), hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(doff, offs.data(), offs.size() * sizeof(int), hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        b->err = "table upload failed";
+        return NMF_EDEVICE;
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_batch_create(nmf_ctx *const *ctxs, int32_t count, void *ws, size_t ws_bytes, void *stream,
+                            nmf_batch **out) {
+    if (!out || !ctxs || count < 1) return fail(nullptr, NMF_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    if (!ws || ws_bytes < batch_bytes(count)) return fail(nullptr, NMF_ENOMEM, "batch workspace too small");
+    if (((uintptr_t)ws) % 256 != 0) return fail(nullptr, NMF_EINVAL, "batch workspace not 256-byte aligned");
+    nmf_batch *b = new (std::nothrow) nmf_batch();
+    if (!b) return fail(nullptr, NMF_ENOMEM, "host allocation failed");
+    for (int q = 0; q < count; ++q) {
+        if (!ctxs[q]) {
+            delete b;
+            return fail(nullptr, NMF_EINVAL, "NULL context in batch");
+        }
+        b->ctxs.push_back(ctxs[q]);
+    }
+    b->stream = (hipStream_t)stream;
+    b->ws = (uint8_t *)ws;
+    b->ws_bytes = ws_bytes;
+    nmf_status st = nmf_batch_refresh(b);
+    if (st != NMF_OK) {
+        g_create_error = b->err;
+        delete b;
+        return st;
+    }
+    *out = b;
+    return NMF_OK;
+}
+
+static nmf_status batch_enqueue(nmf_batch *b, int sweeps) {
+    for (int t = 0; t < sweeps; ++t)
+        for (auto &g : b->groups)
+            if (nmfk::launch_batch_sweep(g.K, g.prec, g.g, b->stream) != hipSuccess) {
+                b->err = "batched launch failed";
+                return NMF_EDEVICE;
+            }
+    return NMF_OK;
+}
+
+nmf_status nmf_batch_anls_step(nmf_batch *b, int32_t sweeps, int32_t use_graph) {
+    if (!b || sweeps < 0) return NMF_EINVAL;
+    if (sweeps == 0) return NMF_OK;
+    if (!use_graph) return batch_enqueue(b, sweeps);
+    if (!b->exec || b->graph_sweeps != sweeps) {
+        drop_graph(b);
+        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            b->err = "stream capture failed (the batch stream must not be the default stream)";
+            return NMF_EDEVICE;
+        }
+        nmf_status st = batch_enqueue(b, sweeps);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (st != NMF_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            b->err = "graph capture failed";
+            return NMF_EDEVICE;
+        }
+        b->graph = g;
+        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(b);
+            b->err = "graph instantiation failed";
+            return NMF_EDEVICE;
+        }
+        b->graph_sweeps = sweeps;
+    }
+    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) {
+        b->err = "graph launch failed";
+        return NMF_EDEVICE;
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_batch_sync(nmf_batch *b) {
+    if (!b) return NMF_EINVAL;
+    return hipStreamSynchronize(b->stream) == hipSuccess ? NMF_OK : NMF_EDEVICE;
+}
+
+nmf_status nmf_batch_destroy(nmf_batch *b) {
+    if (!b) return NMF_OK;
+    drop_graph(b);
+    delete b;
+    return NMF_OK;
 }
 
 }  // extern "C"

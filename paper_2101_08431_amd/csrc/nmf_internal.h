@@ -84,6 +84,17 @@ hipError_t launch_make_lowprec(const AnlsParams &p, int64_t j0, int64_t j1, hipS
 hipError_t launch_copy_columns_warm(int K, const AnlsParams &p, int64_t j_from, int64_t j0,
                                     int64_t j1, hipStream_t s);
 
+// A group of problems sharing K and precision, launched as one flattened grid
+// per stage-1 kernel.  Device arrays: table[count] and off[4][count + 1]
+// (block prefix sums of k_xstream, k_xnnls, k_ystream, k_ynnls).
+struct BatchGroup {
+    const AnlsParams *table;
+    const int *off;
+    int count;
+    int blocks[4];
+};
+hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t s);
+
 int yhalf_cols(int K);   // columns per Y-stream tile, J = YVALS / K
 
 }  // namespace nmfk

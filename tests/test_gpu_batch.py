@@ -1,0 +1,92 @@
+"""Batched stage-1 sweeps: every problem of a batch ends bitwise where its own
+standalone sweeps end, with eager launches and with HIP-graph replays."""
+import numpy as np
+import pytest
+
+from paper_2101_08431_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def problems(count, seed0=10000):
+    rng = np.random.default_rng(seed0)
+    out = []
+    for q in range(count):
+        n = int(rng.integers(100, 900))
+        m = int(rng.integers(20, 200))
+        k = int(rng.integers(2, 9))
+        M, X0, Y0 = synth.make(dict(kind="pdf", n=n, m=m, k=k, sigma=1e-3, sigma_relative=True), seed0 + q)
+        out.append((M, X0, Y0, k))
+    return out
+
+
+def contexts(probs, **opt):
+    from paper_2101_08431_amd import NMF, default_options
+    base = dict(eps_stol=-1.0, max_anls_sweeps=1 << 30, with_ipm=0)
+    base.update(opt)
+    return [NMF(M, k, X0, Y0, options=default_options(**base)) for (M, X0, Y0, k) in probs]
+
+
+def test_batch_matches_standalone_eager_and_graph():
+    import torch
+    from paper_2101_08431_amd import Batch
+    probs = problems(14)
+    print("case batch of 14 uneven problems", flush=True)
+    solo = contexts(probs)
+    for c in solo:
+        c.anls_step(12, report=False)
+    torch.cuda.synchronize()
+    ref = [c.factors() for c in solo]
+    for graph in (False, True):
+        ctxs = contexts(probs)
+        b = Batch(ctxs)
+        for _ in range(3):                       # 3 x 4 = 12 sweeps
+            b.step(4, graph=graph)
+            b.sync()
+            torch.cuda.synchronize()             # eager work between replays
+        for c, (X, Y) in zip(ctxs, ref):
+            Xb, Yb = c.factors()
+            assert np.array_equal(Xb, X) and np.array_equal(Yb, Y)
+        b.close()
+
+
+def test_batch_problems_stop_independently():
+    import torch
+    from paper_2101_08431_amd import Batch
+    probs = problems(6, seed0=10100)
+    ctxs = contexts(probs, eps_stol=1e-6, max_anls_sweeps=40)
+    b = Batch(ctxs)
+    b.step(50, graph=True)
+    b.sync()
+    torch.cuda.synchronize()
+    for c in ctxs:
+        st, rep = c.anls_step(0)
+        assert st == 1 and rep["sweeps"] <= 40
+    solo = contexts(probs, eps_stol=1e-6, max_anls_sweeps=40)
+    for c, s in zip(ctxs, solo):
+        s.anls_step(50)
+        assert np.array_equal(c.factors()[0], s.factors()[0])
+
+
+def test_batch_after_relaunch_shape_change():
+    import torch
+    from paper_2101_08431_amd import Batch
+    probs = problems(5, seed0=10200)
+    ctxs = contexts(probs)
+    b = Batch(ctxs)
+    b.step(3, graph=True)
+    b.sync()
+    for c in ctxs:
+        c.set_launch_shape(2, 1)
+    b.refresh()
+    b.step(3, graph=True)
+    b.sync()
+    torch.cuda.synchronize()
+    solo = contexts(probs)
+    for c in solo:
+        c.anls_step(3, report=False)
+        c.set_launch_shape(2, 1)
+        c.anls_step(3, report=False)
+    torch.cuda.synchronize()
+    for c, s in zip(ctxs, solo):
+        assert np.array_equal(c.factors()[0], s.factors()[0])
