@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark: column NNLS solves/s of the ANLS stage on one MI355X.
 
-Workload: PDF-like streaming data, n = 3000 rows, m = 500 time columns,
-rank k = 5, noise 1e-3 * max(X* Y*), seed 0 (synthetic stand-in for the
-streaming PDF data of Sec. V-B).  A timed step is one ANLS sweep (Alg. 1):
-the X-half (B_X = M Y^T, G_Y, one warm-started NNLS per row) and the Y-half
-(B_Y = X^T M, G_X, one NNLS per column), i.e. n + m column NNLS solves.
-Inputs are resident in HBM before timing starts.
+Headline workload: PDF-like streaming data, n = 3000 rows, m = 500 time
+columns, rank k = 5, noise 1e-3 * max(X* Y*), seed 0 (a synthetic stand-in for
+the streaming PDF data of Sec. V-B).  A timed step is one ANLS sweep (Alg. 1):
+the X-half (B_X = M Y^T, then one warm-started NNLS per row) and the Y-half
+(B_Y = X^T M, one NNLS per column), i.e. n + m column NNLS solves, replayed
+from a captured HIP graph.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  Extra objects: ``roofline`` for the dominant kernel
-(per-kernel device time measured with HIP events on the library's stream),
-``cpu_baseline`` (the FP64 CPU oracle timed on a bounded number of sweeps of
-the same workload on the host cores), and ``full_solve`` (Alg. 3 to
-E(.;0) <= 1e-8 from the seeded start, when stage 2 is available).
+Prints one JSON line.  Besides the headline fields:
+  roofline      the dominant stage-1 kernel; per-kernel device times come from
+                HIP events around each launch on the library's stream
+  full_solve    Alg. 3 (ANLS, transition, interior point) to E(.;0) <= 1e-8 on
+                four seeds of the headline workload
+  precision     sweep time and error against the FP64 oracle of the FP32 and
+                split-BF16 Gram forms on n = 10000, m = 2000, k = 10
+  batching      256 uneven problems (n ~ U[500, 4000], m ~ U[100, 1000],
+                k in 2..8): batched graph-replayed sweeps vs the plain
+                per-problem launches
+  cpu_baseline  the FP64 CPU oracle timed on a bounded number of sweeps of the
+                headline workload on the host cores
 """
 from __future__ import annotations
 
@@ -28,17 +35,169 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "column NNLS solves/s + full-solve time at KKT ≤1e-8; serving p50/p99 latency"
 WORKLOAD = "pdf_3000x500_k5"
+KERNELS = ("k_xstream", "k_xnnls", "k_ystream", "k_ynnls")
 
 
 def algorithmic_bytes(n, m, k):
-    """Bytes one sweep must move at minimum, per kernel.
+    """Bytes each stage-1 kernel must move at minimum per launch.
 
-    X-half: read M (8nm), Y (8km), X (8nk) and the row masks (4n); write X (8nk)
-    and masks (4n).  Y-half: read M (8nm), X (8nk), Y (8km), masks (4m); write Y
-    (8km) and masks (4m)."""
-    xh = 8 * n * m + 8 * k * m + 16 * n * k + 8 * n
-    yh = 8 * n * m + 8 * n * k + 16 * k * m + 8 * m
-    return xh, yh
+    k_xstream: read M (8nm) and Y (8km), write B_X (8nk).
+    k_xnnls:   read B_X and X (16nk) and the row masks (4n), write X (8nk) and
+               the masks (4n).
+    k_ystream: read M (8nm) and X (8nk), write B_Y (8km).
+    k_ynnls:   read B_Y and Y (16km), masks (4m), write Y (8km), masks (4m)."""
+    return (8 * n * m + 8 * k * m + 8 * n * k,
+            24 * n * k + 8 * n,
+            8 * n * m + 8 * n * k + 8 * k * m,
+            24 * k * m + 8 * m)
+
+
+def make_ctx(M, X0, Y0, k, **opt):
+    import numpy as np
+    import torch
+    from paper_2101_08431_amd import NMF, default_options
+    base = dict(eps_stol=-1.0, max_anls_sweeps=1 << 30, with_ipm=0)
+    base.update(opt)
+    Md = torch.from_numpy(np.ascontiguousarray(M.T)).cuda()
+    return NMF(Md, k, torch.from_numpy(X0).cuda(), torch.from_numpy(Y0).cuda(), options=default_options(**base))
+
+
+def time_graph_sweeps(ctx, steps, warmup):
+    """ms per sweep of graph-replayed sweeps (a batch of one problem)."""
+    import torch
+    from paper_2101_08431_amd import Batch
+    b = Batch([ctx])
+    b.step(warmup, graph=True)
+    b.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(b.stream)
+    b.step(steps, graph=True)
+    e1.record(b.stream)
+    b.sync()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    dev = e0.elapsed_time(e1)
+    b.close()
+    return dev / steps, wall
+
+
+def time_eager_sweeps(ctx, steps, warmup):
+    import torch
+    ctx.anls_step(warmup, report=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    ctx.anls_step(steps, report=False)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def roofline(ctx, n, m, k, sweeps=100):
+    ms = ctx.anls_profile(sweeps)
+    by = algorithmic_bytes(n, m, k)
+    per = {}
+    for name, t, b in zip(KERNELS, ms, by):
+        per[name] = {"ms": t, "bytes": b, "GBs": b / (t * 1e-3) / 1e9}
+    dom = max(per, key=lambda q: per[q]["ms"])
+    ach = per[dom]["GBs"]
+    return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": per[dom]["bytes"],
+            "per_kernel": per}
+
+
+def full_solve(name, seeds, tol, cap):
+    import torch
+    from paper_2101_08431_amd import NMF, default_options, synth
+    out = []
+    for seed in seeds:
+        M, X0, Y0 = synth.make(name, seed)
+        ctx = NMF(M, X0.shape[1], X0, Y0, options=default_options(eps_tol=tol, max_ipm_iters=cap))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep = ctx.solve()
+        torch.cuda.synchronize()
+        out.append({"seed": seed, "ms": (time.perf_counter() - t0) * 1e3, "converged": st == 1,
+                    "E0": rep["E0"], "f": rep["f"], "sweeps": rep["sweeps"], "ipm_iters": rep["ipm_iters"],
+                    "ms_stage1": rep["ms_stage1"], "ms_stage2": rep["ms_stage2"]})
+        ctx.close()
+    conv = [r["ms"] for r in out if r["converged"]]
+    return {"workload": name, "tol": tol, "ipm_cap": cap, "runs": out,
+            "converged": f"{len(conv)}/{len(out)}",
+            "median_ms_converged": sorted(conv)[len(conv) // 2] if conv else None}
+
+
+def precision_section(steps):
+    import numpy as np
+    import oracle
+    from paper_2101_08431_amd import synth
+    M, X0, Y0 = synth.make("pdf_10000x2000_k10", 0)
+    n, m = M.shape
+    k = X0.shape[1]
+    ref = oracle.anls(M, X0, Y0.T.copy(), exact_sweeps=5)
+    scale = max(np.abs(ref["X"]).max(), np.abs(ref["Yt"]).max())
+    f_ref = oracle.objective(M, ref["X"], ref["Yt"])
+    res = {"workload": "pdf_10000x2000_k10", "n": n, "m": m, "k": k}
+    for name, prec in (("fp64", 0), ("fp32", 1), ("bf16x2", 2)):
+        ctx = make_ctx(M, X0, Y0, k, gram_precision=prec)
+        ctx.anls_step(5, report=False)
+        X, Y = ctx.factors()
+        err = max(np.abs(X - ref["X"]).max(), np.abs(Y.T - ref["Yt"]).max()) / scale
+        f = oracle.objective(M, X, Y.T.copy())
+        ms, _ = time_graph_sweeps(ctx, steps, 5)
+        ms4 = ctx.anls_profile(20)
+        res[name] = {"ms_per_sweep": ms, "solves_per_s": (n + m) / (ms * 1e-3),
+                     "stream_ms": [ms4[0], ms4[2]],
+                     "stream_GBs": [(8 if prec == 0 else 4) * n * m / (t * 1e-3) / 1e9 for t in (ms4[0], ms4[2])],
+                     "factor_rel_err_after_5_sweeps": err, "objective_rel_err": abs(f - f_ref) / f_ref}
+        ctx.close()
+    return res
+
+
+def batching_section(count, sweeps):
+    import numpy as np
+    import torch
+    from paper_2101_08431_amd import Batch, autotune, synth
+    rng = np.random.default_rng(4)
+    ctxs, solves = [], 0
+    for p in range(count):
+        n = int(rng.integers(500, 4001))
+        m = int(rng.integers(100, 1001))
+        k = int(rng.integers(2, 9))
+        M, X0, Y0 = synth.make(dict(kind="pdf", n=n, m=m, k=k, sigma=1e-3, sigma_relative=True), 10000 + p)
+        ctxs.append(make_ctx(M, X0, Y0, k))
+        solves += n + m
+    torch.cuda.synchronize()
+    # plain method: every problem's own four launches per sweep
+    for c in ctxs:
+        c.anls_step(1, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        for c in ctxs:
+            c.anls_step(1, report=False)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / sweeps
+    b = Batch(ctxs)
+    waves, tuned_ms = autotune.tune_batch(b, sweeps=5, use_cache=False)
+    b.step(sweeps, graph=True)
+    b.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(sweeps, graph=True)
+    e1.record(b.stream)
+    b.sync()
+    batch_ms = e0.elapsed_time(e1) / sweeps
+    b.close()
+    return {"problems": count, "column_solves_per_sweep": solves,
+            "plain_ms_per_sweep": plain_ms, "plain_solves_per_s": solves / (plain_ms * 1e-3),
+            "batched_ms_per_sweep": batch_ms, "batched_solves_per_s": solves / (batch_ms * 1e-3),
+            "speedup": plain_ms / batch_ms, "autotuned_waves": waves}
 
 
 def cpu_baseline(M, X0, Y0, budget_s=15.0):
@@ -47,102 +206,59 @@ def cpu_baseline(M, X0, Y0, budget_s=15.0):
     t0 = time.perf_counter()
     oracle.anls(M, X0, Y0.T.copy(), exact_sweeps=2)
     per = (time.perf_counter() - t0) / 2
-    sweeps = max(2, min(2000, int(budget_s / max(per, 1e-6))))
+    sweeps = max(2, min(4000, int(budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
     oracle.anls(M, X0, Y0.T.copy(), exact_sweeps=sweeps)
     dt = time.perf_counter() - t0
-    return {"value": (n + m) * sweeps / dt, "unit": "solves/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{sweeps} ANLS sweeps of the same {n}x{m} k={X0.shape[1]} workload "
-                      f"from the same start ({dt:.1f} s)"}
-
-
-def full_solve(M, X0, Y0, k, tol):
-    from paper_2101_08431_amd import NMF, default_options
-    import torch
-    opts = default_options(eps_tol=tol)
-    ctx = NMF(M, k, X0, Y0, options=opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, rep = ctx.solve()
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3
-    return {"tol": tol, "ms": wall, "converged": st == 1, "E0": rep["E0"], "f": rep["f"],
-            "sweeps": rep["sweeps"], "ipm_iters": rep["ipm_iters"],
-            "ms_stage1": rep["ms_stage1"], "ms_stage2": rep["ms_stage2"]}
+    return {"value": (n + m) * sweeps / dt, "unit": "solves/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{sweeps} ANLS sweeps of the same {n}x{m} k={X0.shape[1]} workload from the same start "
+                      f"({dt:.1f} s)"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-solve", action="store_true", help="skip the full two-stage solve")
-    ap.add_argument("--workload", default=WORKLOAD, help="named synthetic workload (default: the metric's)")
+    ap.add_argument("--no-solve", action="store_true", help="skip the full two-stage solves")
+    ap.add_argument("--no-layers", action="store_true", help="skip the precision and batching sections")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path in this library "
+              "(the sharding design is written down, not built)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2101_08431_amd import NMF, default_options, synth
+    from paper_2101_08431_amd import synth
 
     M, X0, Y0 = synth.make(args.workload, 0)
     n, m = M.shape
     k = X0.shape[1]
-    Md = torch.from_numpy(np.ascontiguousarray(M.T)).cuda()   # resident in HBM
-    Xd = torch.from_numpy(X0).cuda()
-    Yd = torch.from_numpy(Y0).cuda()
-    opts = default_options(eps_stol=-1.0, max_anls_sweeps=1 << 30)
-    ctx = NMF(Md, k, Xd, Yd, options=opts)
-    stream = ctx.stream
-
-    ctx.anls_step(args.warmup, report=False)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    ctx.anls_step(args.steps, report=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - t0) * 1e3
-    dev_ms = e0.elapsed_time(e1)
-    ms_per_step = dev_ms / args.steps
-    value = (n + m) / (ms_per_step * 1e-3)
-
-    # per-kernel device time (events around each launch), same workload
-    prof_sweeps = max(20, min(args.steps, 200))
-    ms_x, ms_y = ctx.anls_profile(prof_sweeps)
-    bx, by = algorithmic_bytes(n, m, k)
-    if ms_x >= ms_y:
-        kname, kms, kbytes = "k_xhalf", ms_x, bx
-    else:
-        kname, kms, kbytes = "k_yhalf", ms_y, by
-    achieved = kbytes / (kms * 1e-3) / 1e9
+    ctx = make_ctx(M, X0, Y0, k)
+    ms_graph, wall_ms = time_graph_sweeps(ctx, args.steps, args.warmup)
+    ms_eager = time_eager_sweeps(ctx, args.steps, args.warmup)
+    value = (n + m) / (ms_graph * 1e-3)
+    rl = roofline(ctx, n, m, k)
     _, rep = ctx.anls_step(0)
-
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "k": k,
-                   "step": "one ANLS sweep (X-half + Y-half kernels), n + m NNLS solves",
-                   "wall_ms_timed": wall_ms},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "ms_xhalf": ms_x, "ms_yhalf": ms_y,
-                     "bytes_per_launch": kbytes},
+                   "step": "one ANLS sweep (4 kernels: X stream, row NNLS, Y stream, column NNLS), "
+                           "n + m NNLS solves, replayed from a captured HIP graph",
+                   "wall_ms_timed": wall_ms, "eager_ms_per_step": ms_eager},
+        "roofline": rl,
         "nnls_solves_per_problem": rep["nnls_solves"] / max(1, rep["sweeps"] * (n + m)),
     }
+    ctx.close()
     if not args.no_solve:
-        try:
-            out["full_solve"] = full_solve(M, X0, Y0, k, 1e-8)
-        except Exception as e:  # stage 2 missing or failed: say so in the record
-            out["full_solve"] = {"error": str(e)}
+        out["full_solve"] = full_solve(args.workload, [0, 1, 2, 3], 1e-8, 300)
+    if not args.no_layers:
+        out["precision"] = precision_section(200)
+        out["batching"] = batching_section(256, 10)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(M, X0, Y0)
     print(json.dumps(out), flush=True)

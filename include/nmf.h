@@ -171,12 +171,12 @@ nmf_status nmf_get_masks(nmf_ctx *ctx, uint32_t *xmask, uint32_t *ymask);
 nmf_status nmf_get_report(nmf_ctx *ctx, nmf_report *report);
 
 /* Profiling: enqueues `sweeps` stage-1 sweeps like nmf_anls_step() with a
- * pair of HIP events around every kernel, synchronises, and returns the mean
- * device time in milliseconds of the X-half kernel (the B_X = M Y^T product and
- * the row NNLS of Alg. 1) and of the Y-half kernel (B_Y = X^T M and the column
- * NNLS).  Either output may be NULL.  Sweeps after the stop rule holds return
- * at once and are still counted. */
-nmf_status nmf_anls_profile(nmf_ctx *ctx, int32_t sweeps, double *ms_xhalf, double *ms_yhalf);
+ * pair of HIP events around every kernel, synchronises, and writes the mean
+ * device time in milliseconds of the four stage-1 kernels to ms[0..3]: the
+ * X-half stream (B_X = M Y^T), the row NNLS, the Y-half stream (B_Y = X^T M)
+ * and the column NNLS.  Sweeps after the stop rule holds return at once and
+ * are still counted. */
+nmf_status nmf_anls_profile(nmf_ctx *ctx, int32_t sweeps, double *ms);
 
 /* Re-plans the stage-1 launch shape of a context: column splits of the X-half
  * and row splits of the Y-half (0 = automatic, at most 64 each).  Results do

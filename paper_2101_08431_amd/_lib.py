@@ -90,7 +90,7 @@ def load():
     L.nmf_get_masks.restype = ctypes.c_int
     L.nmf_get_report.argtypes = [vp, ctypes.POINTER(Report)]
     L.nmf_get_report.restype = ctypes.c_int
-    L.nmf_anls_profile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.nmf_anls_profile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.nmf_anls_profile.restype = ctypes.c_int
     L.nmf_set_launch_shape.argtypes = [vp, i32, i32]
     L.nmf_set_launch_shape.restype = ctypes.c_int
@@ -210,11 +210,11 @@ class NMF:
         return (st, r.as_dict()) if r is not None else st
 
     def anls_profile(self, sweeps):
-        """Mean device ms of the X-half and Y-half kernels over `sweeps` sweeps."""
-        a, b = ctypes.c_double(), ctypes.c_double()
-        self._check(load().nmf_anls_profile(self._ctx, int(sweeps), ctypes.byref(a), ctypes.byref(b)),
-                    ok=(NMF_OK,))
-        return a.value, b.value
+        """Mean device ms of the four stage-1 kernels over `sweeps` sweeps:
+        (x stream, row NNLS, y stream, column NNLS)."""
+        ms = (ctypes.c_double * 4)()
+        self._check(load().nmf_anls_profile(self._ctx, int(sweeps), ms), ok=(NMF_OK,))
+        return tuple(ms)
 
     def solve(self):
         r = Report()

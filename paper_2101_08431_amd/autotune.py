@@ -1,0 +1,114 @@
+"""Launch-shape autotuner for the stage-1 kernels.
+
+The shape knobs are the column splits of the X-half streaming kernel and the
+row splits of the Y-half one (more splits: more waves streaming M, more
+partial sums to reduce).  The tuner times candidate shapes on the device with
+the library's own per-kernel event profiler (single problem) or with replayed
+batched sweeps (batch), keeps the fastest, and caches the choice in a JSON file
+(``NMF_TUNE_CACHE``, default ``~/.cache/nmf_mi355x_tune.json``) keyed by the
+problem signature.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+import time
+
+XTILE, SWAVES, STHR = 64, 8, 512
+
+
+def _cache_path():
+    return os.environ.get("NMF_TUNE_CACHE", os.path.expanduser("~/.cache/nmf_mi355x_tune.json"))
+
+
+def _load():
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def splits_for_waves(n, m, k, waves):
+    """Split counts that give about `waves` streaming waves per kernel."""
+    tn = math.ceil(n / XTILE)
+    xs = max(1, min(math.ceil(waves / (SWAVES * tn)), 64, m))
+    j = max(1, 64 // k)
+    tm = math.ceil(m / j)
+    ys = max(1, min(math.ceil(waves / (SWAVES * tm)), max(1, n // (4 * STHR)), 64, n))
+    return xs, ys
+
+
+def tune_single(ctx, xs_cands=(1, 2, 4, 8, 16), ys_cands=(1, 2, 4), sweeps=30, use_cache=True):
+    """Pick (x_splits, y_splits) for one context; returns the choice and sets it."""
+    key = f"single:{ctx.n}:{ctx.m}:{ctx.k}:{int(ctx.options.gram_precision)}"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        xs, ys = cache[key]["choice"]
+        ctx.set_launch_shape(xs, ys)
+        return tuple(cache[key]["choice"])
+    timings = {}
+    for xs in xs_cands:
+        for ys in ys_cands:
+            ctx.set_launch_shape(xs, ys)
+            ctx.anls_profile(3)
+            timings[(xs, ys)] = sum(ctx.anls_profile(sweeps))
+    best = min(timings, key=timings.get)
+    ctx.set_launch_shape(*best)
+    cache = _load()
+    cache[key] = {"choice": list(best), "ms": timings[best],
+                  "tried": {f"{a},{b}": v for (a, b), v in timings.items()}}
+    _store(cache)
+    return best
+
+
+def tune_batch(batch, waves_cands=(256, 512, 1024, 2048, 4096), sweeps=10, use_cache=True):
+    """Pick one target wave count for every problem of a batch by timing replayed
+    batched sweeps; sets the shapes and returns (waves, ms_per_sweep)."""
+    import torch
+    sig = hashlib.sha1(json.dumps([(c.n, c.m, c.k, int(c.options.gram_precision))
+                                   for c in batch.contexts]).encode()).hexdigest()[:16]
+    key = f"batch:{len(batch.contexts)}:{sig}"
+    cache = _load() if use_cache else {}
+
+    def apply(w):
+        for c in batch.contexts:
+            c.set_launch_shape(*splits_for_waves(c.n, c.m, c.k, w))
+        batch.refresh()
+
+    if key in cache:
+        apply(cache[key]["choice"])
+        return cache[key]["choice"], cache[key]["ms"]
+    timings = {}
+    for w in waves_cands:
+        apply(w)
+        batch.step(sweeps, graph=True)
+        batch.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(batch.stream)
+        batch.step(sweeps, graph=True)
+        e1.record(batch.stream)
+        batch.sync()
+        timings[w] = e0.elapsed_time(e1) / sweeps
+    best = min(timings, key=timings.get)
+    apply(best)
+    cache = _load()
+    cache[key] = {"choice": best, "ms": timings[best], "tried": {str(k): v for k, v in timings.items()},
+                  "when": time.time()}
+    _store(cache)
+    return best, timings[best]

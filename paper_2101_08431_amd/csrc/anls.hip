@@ -664,6 +664,10 @@ hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s) {
 }
 
 hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t s) {
+    if (g.count == 1) {
+        hipError_t e = launch_xhalf(K, g.single, s);
+        return e != hipSuccess ? e : launch_yhalf(K, g.single, s);
+    }
     const AnlsParams *t = g.table;
     const int *o = g.off;
     const int np = g.count;

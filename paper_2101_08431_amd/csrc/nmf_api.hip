@@ -436,11 +436,11 @@ nmf_status nmf_anls_step(nmf_ctx *c, int32_t sweeps, nmf_report *r) {
     return ds.converged ? NMF_CONVERGED : NMF_OK;
 }
 
-nmf_status nmf_anls_profile(nmf_ctx *c, int32_t sweeps, double *ms_x, double *ms_y) {
-    if (!c) return NMF_EINVAL;
+nmf_status nmf_anls_profile(nmf_ctx *c, int32_t sweeps, double *ms) {
+    if (!c || !ms) return NMF_EINVAL;
     if (sweeps < 1) return fail(c, NMF_EINVAL, "sweeps < 1");
     if (c->stage != 1) return fail(c, NMF_ESTATE, "stage 2 has started");
-    std::vector<hipEvent_t> ev(4 * (size_t)sweeps, nullptr);   // around each half (stream + NNLS kernel)
+    std::vector<hipEvent_t> ev(8 * (size_t)sweeps, nullptr);   // a pair around each kernel
     nmf_status st = NMF_OK;
     for (auto &e : ev) {
         if (hipEventCreate(&e) != hipSuccess) { st = fail(c, NMF_EDEVICE, "hipEventCreate failed"); break; }
@@ -448,29 +448,31 @@ nmf_status nmf_anls_profile(nmf_ctx *c, int32_t sweeps, double *ms_x, double *ms
     AnlsParams p = c->p;
     p.mode = 0;
     for (int t = 0; st == NMF_OK && t < sweeps; ++t) {
-        if (hipEventRecord(ev[4 * t + 0], c->stream) != hipSuccess ||
-            nmfk::launch_xhalf(c->K, p, c->stream) != hipSuccess ||
-            hipEventRecord(ev[4 * t + 1], c->stream) != hipSuccess ||
-            hipEventRecord(ev[4 * t + 2], c->stream) != hipSuccess ||
-            nmfk::launch_yhalf(c->K, p, c->stream) != hipSuccess ||
-            hipEventRecord(ev[4 * t + 3], c->stream) != hipSuccess)
-            st = fail(c, NMF_EDEVICE, "launch failed");
+        hipEvent_t *e = &ev[8 * (size_t)t];
+        bool ok = hipEventRecord(e[0], c->stream) == hipSuccess && nmfk::launch_xstream(c->K, p, c->stream) == hipSuccess &&
+                  hipEventRecord(e[1], c->stream) == hipSuccess && hipEventRecord(e[2], c->stream) == hipSuccess &&
+                  nmfk::launch_xnnls(c->K, p, c->stream) == hipSuccess && hipEventRecord(e[3], c->stream) == hipSuccess &&
+                  hipEventRecord(e[4], c->stream) == hipSuccess && nmfk::launch_ystream(c->K, p, c->stream) == hipSuccess &&
+                  hipEventRecord(e[5], c->stream) == hipSuccess && hipEventRecord(e[6], c->stream) == hipSuccess &&
+                  nmfk::launch_ynnls(c->K, p, c->stream) == hipSuccess && hipEventRecord(e[7], c->stream) == hipSuccess;
+        if (!ok) st = fail(c, NMF_EDEVICE, "launch failed");
     }
-    double sx = 0.0, sy = 0.0;
+    double sum[4] = {0, 0, 0, 0};
     if (st == NMF_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, NMF_EDEVICE, "sync failed");
     for (int t = 0; st == NMF_OK && t < sweeps; ++t) {
-        float a = 0.f, b = 0.f;
-        if (hipEventElapsedTime(&a, ev[4 * t + 0], ev[4 * t + 1]) != hipSuccess ||
-            hipEventElapsedTime(&b, ev[4 * t + 2], ev[4 * t + 3]) != hipSuccess)
-            st = fail(c, NMF_EDEVICE, "hipEventElapsedTime failed");
-        sx += a;
-        sy += b;
+        for (int k = 0; k < 4; ++k) {
+            float a = 0.f;
+            if (hipEventElapsedTime(&a, ev[8 * (size_t)t + 2 * k], ev[8 * (size_t)t + 2 * k + 1]) != hipSuccess) {
+                st = fail(c, NMF_EDEVICE, "hipEventElapsedTime failed");
+                break;
+            }
+            sum[k] += a;
+        }
     }
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
     if (st != NMF_OK) return st;
-    if (ms_x) *ms_x = sx / sweeps;
-    if (ms_y) *ms_y = sy / sweeps;
+    for (int k = 0; k < 4; ++k) ms[k] = sum[k] / sweeps;
     return NMF_OK;
 }
 
@@ -716,6 +718,7 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
             AnlsParams p = b->ctxs[q]->p;
             p.mode = 0;
             tab.push_back(p);
+            g.g.single = p;
             const int cnt[4] = {p.Tn * p.Sx, p.Bx, p.Tm * p.Sy, p.By};
             for (int k = 0; k < 4; ++k) o[k].push_back(o[k].back() + cnt[k]);
         }

@@ -92,6 +92,7 @@ struct BatchGroup {
     const int *off;
     int count;
     int blocks[4];
+    AnlsParams single;   // host copy used when count == 1 (plain launches, no table lookup)
 };
 hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t s);
 
