@@ -200,6 +200,33 @@ def batching_section(count, sweeps):
             "speedup": plain_ms / batch_ms, "autotuned_waves": waves}
 
 
+def serving_section(seconds, rate=200.0, warm=1.0):
+    """64 streams (13 at n = 8000, k = 8, the rest n = 2000, k = 4), each
+    starting at m = 64; Poisson arrivals at `rate`/s, each appending 16 columns
+    to a uniformly chosen stream and re-solving stage 1 to the stop rule.  The
+    same trace runs through the continuous-batching server and through the
+    plain one-request-at-a-time method; latency counts from the scheduled
+    arrival, requests arriving in the first `warm` s are not counted."""
+    from paper_2101_08431_amd.serving import PlainServer, Request, Server, build_workload, summarize
+    specs, reqs = build_workload(streams=64, rate=rate, seconds=seconds)
+    res = {"streams": 64, "rate_per_s": rate, "seconds": seconds, "requests": len(reqs),
+           "m_final_max": max(s.m_capacity for s in specs), "warmup_s": warm,
+           "request": "append 16 columns, then stage-1 sweeps to the stop rule (eps_STOL 1e-6)"}
+    for name, cls in (("served", Server), ("plain", PlainServer)):
+        srv = cls(specs, sweeps_per_round=4)
+        srv.open_all()
+        t0 = time.perf_counter()
+        rr = srv.run([Request(r.rid, r.sid, r.cols, r.arrival) for r in reqs])
+        res[name] = summarize(rr, t_from=warm)
+        res[name]["wall_s"] = time.perf_counter() - t0
+        if name == "served":
+            res[name]["rounds"] = srv.rounds
+            res[name]["mean_batch"] = float(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)))
+        srv.close_all()
+    res["p99_speedup"] = res["plain"]["p99_ms"] / res["served"]["p99_ms"]
+    return res
+
+
 def cpu_baseline(M, X0, Y0, budget_s=15.0):
     import oracle
     n, m = M.shape
@@ -224,7 +251,20 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the full two-stage solves")
     ap.add_argument("--no-layers", action="store_true", help="skip the precision and batching sections")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving arrival trace")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 8, "copies": 10}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path in this library "
               "(the sharding design is written down, not built)", file=sys.stderr)
@@ -259,6 +299,8 @@ def main():
     if not args.no_layers:
         out["precision"] = precision_section(200)
         out["batching"] = batching_section(256, 10)
+    if not args.no_serve:
+        out["serving"] = serving_section(args.serve_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(M, X0, Y0)
     print(json.dumps(out), flush=True)

@@ -149,7 +149,8 @@ nmf_status nmf_solve(nmf_ctx *ctx, nmf_report *report);
 /* Streaming: appends mnew columns (n x mnew, column-major, leading dimension
  * ldm, host or device) to M.  The new columns of Y are solved at once by the
  * NNLS of the Y-half, warm-started from the last existing column, and the
- * context returns to stage 1 (the duals of the grown problem are not known).
+ * context returns to stage 1 (the duals of the grown problem are not known)
+ * with a fresh budget of max_anls_sweeps sweeps for its stop rule.
  * NMF_ECAPACITY beyond m_capacity. */
 nmf_status nmf_append_columns(nmf_ctx *ctx, const double *Mnew, int64_t mnew, int64_t ldm);
 
@@ -209,6 +210,13 @@ nmf_status nmf_batch_refresh(nmf_batch *b);
 /* Enqueues `sweeps` stage-1 sweeps of every problem.  use_graph = 1 captures
  * the sweeps into a HIP graph on first use (per sweep count) and replays it. */
 nmf_status nmf_batch_anls_step(nmf_batch *b, int32_t sweeps, int32_t use_graph);
+
+/* Waits for the batch's stream, then copies every context's stage-1 state
+ * out: converged[q] = 1 once context q's stop rule (Sec. IV) or its sweep
+ * budget holds, sweeps[q] = its sweep count (host arrays of the batch's
+ * count, in the order of nmf_batch_create's ctxs; either may be NULL).  Used
+ * by request loops that retire finished problems between sweeps. */
+nmf_status nmf_batch_poll(nmf_batch *b, int32_t *converged, int64_t *sweeps);
 
 /* Waits for the batch's stream. */
 nmf_status nmf_batch_sync(nmf_batch *b);

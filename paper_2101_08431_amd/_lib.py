@@ -23,7 +23,7 @@ EXPORTS = [
     "nmf_solve", "nmf_append_columns", "nmf_get_factors", "nmf_get_masks", "nmf_get_report",
     "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
     "nmf_get_duals", "nmf_set_launch_shape", "nmf_batch_workspace_bytes", "nmf_batch_create",
-    "nmf_batch_refresh", "nmf_batch_anls_step", "nmf_batch_sync", "nmf_batch_destroy",
+    "nmf_batch_refresh", "nmf_batch_anls_step", "nmf_batch_poll", "nmf_batch_sync", "nmf_batch_destroy",
 ]
 
 
@@ -103,6 +103,8 @@ def load():
         getattr(L, name).restype = ctypes.c_int
     L.nmf_batch_anls_step.argtypes = [vp, i32, i32]
     L.nmf_batch_anls_step.restype = ctypes.c_int
+    L.nmf_batch_poll.argtypes = [vp, vp, vp]
+    L.nmf_batch_poll.restype = ctypes.c_int
     L.nmf_get_shape.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.nmf_get_shape.restype = ctypes.c_int
     L.nmf_destroy.argtypes = [vp]
@@ -310,6 +312,18 @@ class Batch:
 
     def sync(self):
         load().nmf_batch_sync(self._b)
+
+    def poll(self):
+        """Waits for the batch, then returns (converged, sweeps): numpy arrays
+        over the contexts in the order given at construction."""
+        import numpy as np
+        n = len(self.contexts)
+        conv = np.zeros(n, dtype=np.int32)
+        sw = np.zeros(n, dtype=np.int64)
+        st = load().nmf_batch_poll(self._b, _ptr(conv), _ptr(sw))
+        if st != NMF_OK:
+            raise NMFError(st, "batch poll failed")
+        return conv.astype(bool), sw
 
     def close(self):
         if getattr(self, "_b", None):

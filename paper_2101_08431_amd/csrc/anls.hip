@@ -595,6 +595,21 @@ __global__ void k_copy_columns_warm(AnlsParams p, int64_t j_from, int64_t j0, in
     p.ymask[j] = p.ymask[j_from];
 }
 
+__global__ void k_rearm(DevStatus *st, int budget) {
+    if (threadIdx.x == 0) {
+        st->converged = 0;
+        st->max_sweeps = st->sweeps + budget;
+    }
+}
+
+__global__ void k_batch_poll(const AnlsParams *table, int count, long long *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const DevStatus *st = table[q].st;
+    out[2 * q] = st->converged;
+    out[2 * q + 1] = st->sweeps;
+}
+
 // ---------------------------------------------------------------- launchers
 #define NMF_K_SWITCH(K, CALL)                                                        \
     switch (K) {                                                                     \
@@ -735,6 +750,17 @@ hipError_t launch_factor_out(int K, const AnlsParams &p, double *dx, double *dy,
 hipError_t launch_make_lowprec(const AnlsParams &p, int64_t j0, int64_t j1, hipStream_t s) {
     if (p.prec == NMF_GRAM_FP64 || j1 <= j0) return hipSuccess;
     hipLaunchKernelGGL(k_make_lowprec, dim3(1024), dim3(NTHR), 0, s, p, j0, j1);
+    return hipGetLastError();
+}
+
+hipError_t launch_rearm(DevStatus *st, int budget, hipStream_t s) {
+    hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, s, st, budget);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_poll(const AnlsParams *table, int count, long long *out, hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_poll, dim3((unsigned)((count + NTHR - 1) / NTHR)), dim3(NTHR), 0, s, table, count, out);
     return hipGetLastError();
 }
 

@@ -581,9 +581,8 @@ nmf_status nmf_append_columns(nmf_ctx *c, const double *Mnew, int64_t mnew, int6
     AnlsParams p = c->p;
     p.mode = 2;
     HIPCHK(c, nmfk::launch_yhalf(c->K, p, s));
-    // the stop rule must be re-earned on the grown problem
-    const int zero = 0;
-    HIPCHK(c, hipMemcpyAsync(&c->p.st->converged, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    // the stop rule must be re-earned on the grown problem, with a fresh budget
+    HIPCHK(c, nmfk::launch_rearm(c->p.st, c->opt.max_anls_sweeps, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return NMF_OK;
 }
@@ -663,12 +662,14 @@ struct nmf_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_sweeps = 0;
+    std::vector<int> order;       // table position -> index in ctxs
+    long long *poll = nullptr;    // device: [count][2] converged, sweeps
     std::string err;
 };
 
 static size_t batch_bytes(int32_t count) {
     return align_up((size_t)count * sizeof(AnlsParams), 256) + align_up((size_t)4 * (count + 1) * sizeof(int), 256) +
-           256;
+           align_up((size_t)2 * count * sizeof(long long), 256) + 256;
 }
 
 static void drop_graph(nmf_batch *b) {
@@ -705,8 +706,12 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
     // tables: all groups' AnlsParams back to back, then their offsets
     std::vector<AnlsParams> tab;
     std::vector<int> offs;
+    const size_t count = b->ctxs.size();
     AnlsParams *dtab = (AnlsParams *)b->ws;
-    int *doff = (int *)(b->ws + align_up(b->ctxs.size() * sizeof(AnlsParams), 256));
+    int *doff = (int *)(b->ws + align_up(count * sizeof(AnlsParams), 256));
+    b->poll = (long long *)(b->ws + align_up(count * sizeof(AnlsParams), 256) +
+                            align_up((size_t)4 * (count + 1) * sizeof(int), 256));
+    b->order.clear();
     for (auto &g : b->groups) {
         const int np = (int)g.members.size();
         g.g.table = dtab + tab.size();
@@ -718,6 +723,7 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
             AnlsParams p = b->ctxs[q]->p;
             p.mode = 0;
             tab.push_back(p);
+            b->order.push_back(q);
             g.g.single = p;
             const int cnt[4] = {p.Tn * p.Sx, p.Bx, p.Tm * p.Sy, p.By};
             for (int k = 0; k < 4; ++k) o[k].push_back(o[k].back() + cnt[k]);
@@ -805,6 +811,25 @@ nmf_status nmf_batch_anls_step(nmf_batch *b, int32_t sweeps, int32_t use_graph) 
     if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) {
         b->err = "graph launch failed";
         return NMF_EDEVICE;
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_batch_poll(nmf_batch *b, int32_t *converged, int64_t *sweeps) {
+    if (!b) return NMF_EINVAL;
+    const int count = (int)b->ctxs.size();
+    std::vector<long long> h(2 * (size_t)count);
+    if (nmfk::launch_batch_poll((const AnlsParams *)b->ws, count, b->poll, b->stream) != hipSuccess ||
+        hipMemcpyAsync(h.data(), b->poll, h.size() * sizeof(long long), hipMemcpyDeviceToHost, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        b->err = "status poll failed";
+        return NMF_EDEVICE;
+    }
+    for (int t = 0; t < count; ++t) {
+        const int q = b->order[t];
+        if (converged) converged[q] = (int32_t)h[2 * (size_t)t];
+        if (sweeps) sweeps[q] = (int64_t)h[2 * (size_t)t + 1];
     }
     return NMF_OK;
 }

@@ -36,7 +36,8 @@ struct DevStatus {
     double eps_stol;
     long long sweeps;
     int converged;
-    int max_sweeps;
+    int pad_;
+    long long max_sweeps;         // the stop rule also holds once sweeps reaches this count
     double f_direct;              // 1/2 ||XY - M||^2 from the last direct pass
 };
 
@@ -81,6 +82,10 @@ hipError_t launch_factor_in(int K, const double *src_x, const double *src_y, con
                             unsigned *bad, hipStream_t s);
 hipError_t launch_factor_out(int K, const AnlsParams &p, double *dst_x, double *dst_y, hipStream_t s);
 hipError_t launch_make_lowprec(const AnlsParams &p, int64_t j0, int64_t j1, hipStream_t s);
+// Re-arms the stage-1 stop rule: converged = 0 and a budget of `budget` more sweeps.
+hipError_t launch_rearm(DevStatus *st, int budget, hipStream_t s);
+// out[2q] = converged, out[2q+1] = sweeps of the problem of table[q], q < count.
+hipError_t launch_batch_poll(const AnlsParams *table, int count, long long *out, hipStream_t s);
 hipError_t launch_copy_columns_warm(int K, const AnlsParams &p, int64_t j_from, int64_t j0,
                                     int64_t j1, hipStream_t s);
 

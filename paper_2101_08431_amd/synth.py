@@ -152,3 +152,37 @@ def make(name_or_spec, seed):
         raise ValueError(kind)
     x0, y0 = random_init(n, m, k, seed, float(np.linalg.norm(mm)))
     return mm, x0, y0
+
+
+# ------------------------------------------------------------------ serving
+def serving_streams(count=64, big_every=5, small=(2000, 4), big=(8000, 8)):
+    """(n, k) of each stream: every ``big_every``-th stream (index 0 mod
+    big_every) is ``big``, the others ``small``."""
+    return [big if (s % big_every == 0) else small for s in range(count)]
+
+
+def serving_trace(streams, rate, seconds, seed=7):
+    """Open-loop Poisson arrivals at ``rate`` requests/s in total over
+    ``seconds``; each request picks a stream uniformly.  Returns a list of
+    (arrival time in s, stream index), sorted by time."""
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        out.append((t, int(rng.integers(0, streams))))
+    return out
+
+
+def serving_stream_data(n, k, m0, add, requests, seed, sigma=1e-3):
+    """One stream's data: the first ``m0`` columns and ``requests`` blocks of
+    ``add`` new columns, all from one PDF-like stream whose time grid spans
+    m0 + add * requests instants.  Returns (M0, [blocks], X0, Y0), every block
+    (n, add) in Fortran order, X0, Y0 a random start for M0."""
+    mh = m0 + add * requests
+    mfull, _, _ = pdf_like(n, mh, k, seed, sigma=sigma, sigma_relative=True, m_horizon=mh)
+    M0 = np.asfortranarray(mfull[:, :m0])
+    blocks = [np.asfortranarray(mfull[:, m0 + add * q: m0 + add * (q + 1)]) for q in range(requests)]
+    x0, y0 = random_init(n, m0, k, seed, float(np.linalg.norm(M0)))
+    return M0, blocks, x0, y0

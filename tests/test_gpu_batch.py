@@ -90,3 +90,41 @@ def test_batch_after_relaunch_shape_change():
     torch.cuda.synchronize()
     for c, s in zip(ctxs, solo):
         assert np.array_equal(c.factors()[0], s.factors()[0])
+
+
+def test_batch_poll_reports_each_problem():
+    import torch
+    from paper_2101_08431_amd import Batch
+    probs = problems(7, seed0=10300)
+    print("case batch poll, 7 problems, stop rule 1e-6, budget 30", flush=True)
+    ctxs = contexts(probs, eps_stol=1e-6, max_anls_sweeps=30)
+    b = Batch(ctxs)
+    conv, sweeps = b.poll()
+    assert not conv.any() and (sweeps == 0).all()
+    b.step(5, graph=False)
+    conv, sweeps = b.poll()
+    for c, cv, sw in zip(ctxs, conv, sweeps):
+        st, rep = c.anls_step(0)
+        assert rep["sweeps"] == sw and (st == 1) == bool(cv)
+    b.step(40, graph=False)
+    conv, sweeps = b.poll()
+    assert conv.all() and (sweeps <= 30).all()
+    torch.cuda.synchronize()
+
+
+def test_append_rearms_the_sweep_budget():
+    # after nmf_append_columns the stop rule gets a fresh budget of
+    # max_anls_sweeps sweeps, counted from the sweeps done so far
+    from paper_2101_08431_amd import NMF, default_options
+    M, _, _ = synth.pdf_like(300, 60, 3, 5, sigma=1e-3, sigma_relative=True)
+    M = np.asarray(M)
+    X0, Y0 = synth.random_init(300, 40, 3, 5, float(np.linalg.norm(M[:, :40])))
+    ctx = NMF(np.asfortranarray(M[:, :40]), 3, X0, Y0, m_capacity=60,
+              options=default_options(eps_stol=0.0, max_anls_sweeps=7, with_ipm=0))
+    st, rep = ctx.anls_step(20)
+    assert st == 1 and rep["sweeps"] == 7
+    ctx.append_columns(np.asfortranarray(M[:, 40:]))
+    st, rep = ctx.anls_step(3)
+    assert st == 0 and rep["sweeps"] == 10
+    st, rep = ctx.anls_step(20)
+    assert st == 1 and rep["sweeps"] == 14
