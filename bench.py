@@ -52,6 +52,10 @@ def algorithmic_bytes(n, m, k):
             24 * k * m + 8 * m)
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def make_ctx(M, X0, Y0, k, **opt):
     import numpy as np
     import torch
@@ -121,6 +125,7 @@ def full_solve(name, seeds, tol, cap):
         t0 = time.perf_counter()
         st, rep = ctx.solve()
         torch.cuda.synchronize()
+        log(f"full solve seed {seed}: status {st}, E0 {rep['E0']:.2e}")
         out.append({"seed": seed, "ms": (time.perf_counter() - t0) * 1e3, "converged": st == 1,
                     "E0": rep["E0"], "f": rep["f"], "sweeps": rep["sweeps"], "ipm_iters": rep["ipm_iters"],
                     "ms_stage1": rep["ms_stage1"], "ms_stage2": rep["ms_stage2"]})
@@ -209,14 +214,18 @@ def serving_section(seconds, rate=200.0, warm=1.0):
     arrival, requests arriving in the first `warm` s are not counted."""
     from paper_2101_08431_amd.serving import PlainServer, Request, Server, build_workload, summarize
     specs, reqs = build_workload(streams=64, rate=rate, seconds=seconds)
+    log(f"serving: {len(reqs)} requests on 64 streams generated")
     res = {"streams": 64, "rate_per_s": rate, "seconds": seconds, "requests": len(reqs),
            "m_final_max": max(s.m_capacity for s in specs), "warmup_s": warm,
-           "request": "append 16 columns, then stage-1 sweeps to the stop rule (eps_STOL 1e-6)"}
+           "request": "append 16 columns, then warm-started stage-1 sweeps until the stop rule "
+                      "(eps_STOL 1e-4) holds or 64 sweeps are done"}
     for name, cls in (("served", Server), ("plain", PlainServer)):
-        srv = cls(specs, sweeps_per_round=4)
+        srv = cls(specs, sweeps_per_round=4, eps_stol=1e-4, request_sweeps=64)
         srv.open_all()
+        log(f"serving: {name} streams open")
         t0 = time.perf_counter()
         rr = srv.run([Request(r.rid, r.sid, r.cols, r.arrival) for r in reqs])
+        log(f"serving: {name} run done in {time.perf_counter() - t0:.1f} s")
         res[name] = summarize(rr, t_from=warm)
         res[name]["wall_s"] = time.perf_counter() - t0
         if name == "served":
@@ -294,14 +303,19 @@ def main():
         "nnls_solves_per_problem": rep["nnls_solves"] / max(1, rep["sweeps"] * (n + m)),
     }
     ctx.close()
+    log(f"headline done: {ms_graph * 1e3:.1f} us per sweep")
     if not args.no_solve:
         out["full_solve"] = full_solve(args.workload, [0, 1, 2, 3], 1e-8, 300)
     if not args.no_layers:
+        log("precision section")
         out["precision"] = precision_section(200)
+        log("batching section")
         out["batching"] = batching_section(256, 10)
     if not args.no_serve:
+        log("serving section")
         out["serving"] = serving_section(args.serve_seconds)
     if not args.no_cpu:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(M, X0, Y0)
     print(json.dumps(out), flush=True)
 

@@ -184,6 +184,14 @@ nmf_status nmf_anls_profile(nmf_ctx *ctx, int32_t sweeps, double *ms);
  * not change beyond the rounding of the split sums.  Used by the autotuner. */
 nmf_status nmf_set_launch_shape(nmf_ctx *ctx, int32_t x_splits, int32_t y_splits);
 
+/* Sets the stage-1 sweep budget (options.max_anls_sweeps, >= 1) used from now
+ * on, and re-arms the stop rule of Sec. IV: the next sweeps run until it holds
+ * again or `max_sweeps` more sweeps are done.  Every later
+ * nmf_append_columns() grants the same budget afresh.  For streaming callers
+ * that bound the work of each arriving block of columns.  Stage 1 only
+ * (NMF_ESTATE otherwise). */
+nmf_status nmf_set_anls_budget(nmf_ctx *ctx, int32_t max_sweeps);
+
 /* ------------------------------------------------------------------ batches
  * Many independent problems swept together (stage 1): the contexts of a batch
  * are grouped by (k, gram precision) and every group runs each of the four

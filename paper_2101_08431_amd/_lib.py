@@ -22,7 +22,7 @@ EXPORTS = [
     "nmf_default_options", "nmf_workspace_bytes", "nmf_create", "nmf_anls_step", "nmf_ipm_step",
     "nmf_solve", "nmf_append_columns", "nmf_get_factors", "nmf_get_masks", "nmf_get_report",
     "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
-    "nmf_get_duals", "nmf_set_launch_shape", "nmf_batch_workspace_bytes", "nmf_batch_create",
+    "nmf_get_duals", "nmf_set_launch_shape", "nmf_set_anls_budget", "nmf_batch_workspace_bytes", "nmf_batch_create",
     "nmf_batch_refresh", "nmf_batch_anls_step", "nmf_batch_poll", "nmf_batch_sync", "nmf_batch_destroy",
 ]
 
@@ -94,6 +94,8 @@ def load():
     L.nmf_anls_profile.restype = ctypes.c_int
     L.nmf_set_launch_shape.argtypes = [vp, i32, i32]
     L.nmf_set_launch_shape.restype = ctypes.c_int
+    L.nmf_set_anls_budget.argtypes = [vp, i32]
+    L.nmf_set_anls_budget.restype = ctypes.c_int
     L.nmf_batch_workspace_bytes.argtypes = [i32]
     L.nmf_batch_workspace_bytes.restype = ctypes.c_size_t
     L.nmf_batch_create.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
@@ -262,6 +264,10 @@ class NMF:
         ym = np.empty(self.m, dtype=np.uint32)
         self._check(load().nmf_get_masks(self._ctx, _ptr(xm), _ptr(ym)), ok=(NMF_OK,))
         return xm, ym
+
+    def set_anls_budget(self, max_sweeps):
+        """Stage-1 sweep budget from now on (re-arms the stop rule)."""
+        self._check(load().nmf_set_anls_budget(self._ctx, int(max_sweeps)), ok=(NMF_OK,))
 
     def set_launch_shape(self, x_splits, y_splits):
         self._check(load().nmf_set_launch_shape(self._ctx, int(x_splits), int(y_splits)), ok=(NMF_OK,))

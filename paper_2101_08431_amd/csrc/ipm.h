@@ -42,6 +42,7 @@ struct IpmState {
     double *Z = nullptr;                       // [n][K][ldY]: L_i^-1 Y
     double *S = nullptr;                       // [mK][ldS] column-major, lower triangle used
     double *vec = nullptr, *vec2 = nullptr;    // [ldS] right-hand side / solution
+    double *invd = nullptr;                    // [ldS] 1 / diagonal of the Cholesky factor of S
     double *part = nullptr;                    // [nblk][PARTW] block records
     double *fpart = nullptr;                   // [Tn * Sx] objective partials
     IpmScal *sc = nullptr;

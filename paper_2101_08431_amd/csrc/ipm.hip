@@ -752,68 +752,95 @@ __global__ __launch_bounds__(NTHR) void k_post_x(AnlsParams p, IpmArgs ia, doubl
 }
 
 // ---------------------------------------------------------------- dense Cholesky of S
-// Diagonal block [k0, k0 + nb) factored in LDS.  Sets sc->chol_fail on a
-// non-positive pivot (the factorisation then continues with pivot 1).
-__global__ __launch_bounds__(256) void k_chol_diag(double *S, int64_t ldS, int64_t N, int64_t k0, IpmScal *sc) {
-    __shared__ double A[CB][CB + 1];
-    const int nb = (int)min((int64_t)CB, N - k0);
-    for (int q = threadIdx.x; q < CB * CB; q += 256) {
-        const int r = q % CB, c = q / CB;
-        A[r][c] = (r < nb && c < nb && r >= c) ? S[(k0 + c) * ldS + k0 + r] : 0.0;
-    }
-    __syncthreads();
-    const int r = threadIdx.x & 63, part = threadIdx.x >> 6;
-    bool bad = false;
-    for (int c = 0; c < nb; ++c) {
-        if (threadIdx.x == 0) {
-            const double d = A[c][c];
-            if (!(d > 0.0)) bad = true;
-            A[c][c] = sqrt(d > 0.0 ? d : 1.0);
-        }
-        __syncthreads();
-        const double ip = 1.0 / A[c][c];
-        if (part == 0 && r > c && r < nb) A[r][c] *= ip;
-        __syncthreads();
-        if (r > c && r < nb) {
-            const double arc = A[r][c];
-            for (int c2 = c + 1 + part; c2 <= r; c2 += 4) A[r][c2] -= arc * A[c2][c];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && bad) sc->chol_fail = 1;
-    for (int q = threadIdx.x; q < CB * CB; q += 256) {
-        const int rr = q % CB, c = q / CB;
-        if (rr < nb && c < nb && rr >= c) S[(k0 + c) * ldS + k0 + rr] = A[rr][c];
-    }
+// S is column-major, element (r, c) at S[c * ldS + r]; only the lower
+// triangle is used.  Right-looking blocked factorisation with CB-wide block
+// columns: factor the diagonal block, solve the panel below it, update the
+// trailing lower triangle.  invd[r] = 1 / L[r][r] is kept for the panel and
+// the triangular solves.
+
+// Value of v in lane `lane` (a compile-time constant after unrolling).
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Panel below the diagonal block: L[r, k0:k0+CB] = S[r, k0:k0+CB] L_kk^-T, one row per thread.
-__global__ __launch_bounds__(256) void k_chol_trsm(double *S, int64_t ldS, int64_t N, int64_t k0) {
-    __shared__ double Lk[CB][CB + 1];
-    for (int q = threadIdx.x; q < CB * CB; q += 256) {
-        const int r = q % CB, c = q / CB;
-        Lk[r][c] = r >= c ? S[(k0 + c) * ldS + k0 + r] : 0.0;
-    }
-    __syncthreads();
-    const int64_t row = k0 + CB + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (row >= N) return;
-    double x[CB];
+// Diagonal block [k0, k0 + nb) by one wave: lane i keeps row i of the block
+// in registers.  Step c takes the pivot from lane c, scales column c, and
+// every lane applies the rank-one update to its row with the entries L[j][c]
+// read from lane j.  A pivot that is not positive sets sc->chol_fail and is
+// replaced by 1.
+__global__ __launch_bounds__(64) void k_chol_diag(double *S, int64_t ldS, int64_t N, int64_t k0, double *invd,
+                                                 IpmScal *sc) {
+    const int i = threadIdx.x;
+    const int nb = (int)min((int64_t)CB, N - k0);
+    double a[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+        a[j] = (j <= i && i < nb) ? S[(k0 + j) * ldS + k0 + i] : (j == i ? 1.0 : 0.0);
+    bool bad = false;
+    double mine = 1.0;
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-        double v = S[(k0 + c) * ldS + row];
+        const double d = lane_value(a[c], c);
+        const bool ok = d > 0.0;
+        bad = bad || !ok;
+        const double l = sqrt(ok ? d : 1.0);
+        const double il = 1.0 / l;
+        if (i == c) {
+            a[c] = l;
+            mine = il;
+        } else if (i > c) {
+            a[c] *= il;
+        }
+        const double lic = (i > c) ? a[c] : 0.0;
 #pragma unroll
-        for (int q = 0; q < c; ++q) v -= x[q] * Lk[c][q];
-        x[c] = v / Lk[c][c];
+        for (int j = c + 1; j < CB; ++j) a[j] = fma(-lic, lane_value(a[c], j), a[j]);
     }
+    if (i < nb) {
 #pragma unroll
-    for (int c = 0; c < CB; ++c) S[(k0 + c) * ldS + row] = x[c];
+        for (int j = 0; j < CB; ++j)
+            if (j <= i) S[(k0 + j) * ldS + k0 + i] = a[j];
+        invd[k0 + i] = mine;
+    }
+    if (i == 0 && bad) sc->chol_fail = 1;
 }
 
-// Trailing update of the lower triangle: S[r][c] -= sum_q P[r][q] P[c][q] over
-// 64 x 64 tiles (R >= C) of [k0 + CB, N)^2.
+// Panel below a full diagonal block: L[r, k0:k0+CB) = S[r, k0:k0+CB) L_kk^-T,
+// one row per thread, solved left to right with every later entry updated at
+// once (independent fused multiply-adds); L_kk is read from LDS.
+__global__ __launch_bounds__(256) void k_chol_panel(double *S, int64_t ldS, int64_t N, int64_t k0,
+                                                  const double *invd) {
+    __shared__ double Lk[CB * CB];   // Lk[q * CB + j] = L[k0 + j][k0 + q], j > q
+    __shared__ double id[CB];
+    for (int t = threadIdx.x; t < CB * CB; t += 256) {
+        const int j = t % CB, q = t / CB;
+        Lk[t] = (j > q) ? S[(k0 + q) * ldS + k0 + j] : 0.0;
+    }
+    if (threadIdx.x < CB) id[threadIdx.x] = invd[k0 + threadIdx.x];
+    __syncthreads();
+    const int64_t r = k0 + CB + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= N) return;
+    double x[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) x[q] = S[(k0 + q) * ldS + r];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+        x[q] *= id[q];
+#pragma unroll
+        for (int j = q + 1; j < CB; ++j) x[j] = fma(-x[q], Lk[q * CB + j], x[j]);
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) S[(k0 + q) * ldS + r] = x[q];
+}
+
+// Trailing update of the lower triangle: S[r][c] -= sum_q L[r][k0+q] L[c][k0+q]
+// over 64 x 64 tiles (R >= C) of [k0 + CB, N)^2.  Thread (tx, ty) owns rows
+// tx + 16a and columns ty + 16b of its tile (4 x 4 accumulators).
 __global__ __launch_bounds__(256) void k_chol_syrk(double *S, int64_t ldS, int64_t N, int64_t k0) {
-    __shared__ double PR[CB][CB + 1];
-    __shared__ double PC[CB][CB + 1];
+    __shared__ double PR[CB * CB];   // PR[q * CB + rr] = L[rb + rr][k0 + q]
+    __shared__ double PC[CB * CB];
     const int64_t T0 = k0 + CB;
     const int64_t tix = blockIdx.x;
     int64_t R = (int64_t)((sqrt(8.0 * (double)tix + 1.0) - 1.0) * 0.5);
@@ -821,24 +848,25 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double *S, int64_t ldS, int64
     while (R * (R + 1) / 2 > tix) --R;
     const int64_t C = tix - R * (R + 1) / 2;
     const int64_t rb = T0 + R * CB, cb = T0 + C * CB;
-    for (int q = threadIdx.x; q < CB * CB; q += 256) {
-        const int rr = q % CB, kk = q / CB;
-        PR[rr][kk] = (rb + rr < N) ? S[(k0 + kk) * ldS + rb + rr] : 0.0;
-        PC[rr][kk] = (cb + rr < N) ? S[(k0 + kk) * ldS + cb + rr] : 0.0;
+    for (int t = threadIdx.x; t < CB * CB; t += 256) {
+        const int rr = t % CB, q = t / CB;
+        PR[t] = (rb + rr < N) ? S[(k0 + q) * ldS + rb + rr] : 0.0;
+        PC[t] = (cb + rr < N) ? S[(k0 + q) * ldS + cb + rr] : 0.0;
     }
     __syncthreads();
-    const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     double acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int kk = 0; kk < CB; ++kk) {
+#pragma unroll 4
+    for (int q = 0; q < CB; ++q) {
         double pr[4], pc[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            pr[a] = PR[tr + a][kk];
-            pc[a] = PC[tc + a][kk];
+            pr[a] = PR[q * CB + tx + 16 * a];
+            pc[a] = PC[q * CB + ty + 16 * a];
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -846,79 +874,93 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double *S, int64_t ldS, int64
             for (int b = 0; b < 4; ++b) acc[a][b] = fma(pr[a], pc[b], acc[a][b]);
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int b = 0; b < 4; ++b) {
+        const int64_t colg = cb + ty + 16 * b;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int64_t row = rb + tr + a, col = cb + tc + b;
-            if (row < N && col < N && row >= col) S[col * ldS + row] -= acc[a][b];
+        for (int a = 0; a < 4; ++a) {
+            const int64_t row = rb + tx + 16 * a;
+            if (row < N && colg < N && row >= colg) S[colg * ldS + row] -= acc[a][b];
         }
     }
 }
 
-// Forward solve step: every block solves y_k = L_kk^-1 b_k (b_k read from
-// vec); block 0 stores y_k in out; the others update the rows below.
-__global__ __launch_bounds__(256) void k_trsv_fwd(const double *S, int64_t ldS, int64_t N, int64_t k0, double *vec,
-                                                  double *out) {
-    __shared__ double Lk[CB][CB + 1];
-    __shared__ double y[CB];
+// Forward solve step: wave 0 of every block solves x_k = L_kk^-1 vec_k (lane
+// i keeps row i of L_kk; step q takes x_q from lane q) into LDS; block 0
+// stores x_k in out; every block then subtracts L[r, k0:k0+nb) x_k from its
+// 256 rows r below the block.
+__global__ __launch_bounds__(256) void k_trsv_fwd(const double *S, int64_t ldS, int64_t N, int64_t k0,
+                                                  const double *invd, double *vec, double *out) {
+    __shared__ double xs[CB];
     const int nb = (int)min((int64_t)CB, N - k0);
-    for (int q = threadIdx.x; q < CB * CB; q += 256) {
-        const int r = q % CB, c = q / CB;
-        Lk[r][c] = (r < nb && c < nb && r >= c) ? S[(k0 + c) * ldS + k0 + r] : 0.0;
-    }
-    if ((int)threadIdx.x < CB) y[threadIdx.x] = (int)threadIdx.x < nb ? vec[k0 + threadIdx.x] : 0.0;
-    __syncthreads();
-    {
-        const int r = threadIdx.x;   // every thread reaches every barrier
-        for (int c = 0; c < nb; ++c) {
-            if (r == c) y[c] = y[c] / Lk[c][c];
-            __syncthreads();
-            if (r > c && r < nb) y[r] -= Lk[r][c] * y[c];
-            __syncthreads();
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x;
+        double l[CB];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) l[j] = (j < i && i < nb) ? S[(k0 + j) * ldS + k0 + i] : 0.0;
+        double b = i < nb ? vec[k0 + i] : 0.0;
+        const double di = i < nb ? invd[k0 + i] : 0.0;
+        double mine = 0.0;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            const double xq = lane_value(b, q) * lane_value(di, q);
+            if (i == q) mine = xq;
+            b = fma(-l[q], xq, b);
         }
+        xs[i] = mine;
+        if (blockIdx.x == 0 && i < nb) out[k0 + i] = mine;
     }
-    if (blockIdx.x == 0) {
-        if ((int)threadIdx.x < nb) out[k0 + threadIdx.x] = y[threadIdx.x];
-        return;
-    }
-    const int64_t row = k0 + nb + (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x;
+    __syncthreads();
+    const int64_t row = k0 + nb + (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (row >= N) return;
     double v = vec[row];
-    for (int q = 0; q < nb; ++q) v -= S[(k0 + q) * ldS + row] * y[q];
+#pragma unroll 8
+    for (int q = 0; q < nb; ++q) v = fma(-S[(k0 + q) * ldS + row], xs[q], v);
     vec[row] = v;
 }
 
-// Backward solve step with L^T: blocks solve L_kk^T x_k = vec_k; block 0
-// stores x_k; the others update the rows above: vec[r] -= sum_q L[k0+q][r] x_q.
-__global__ __launch_bounds__(256) void k_trsv_bwd(const double *S, int64_t ldS, int64_t N, int64_t k0, double *vec,
-                                                  double *out) {
-    __shared__ double Lk[CB][CB + 1];
-    __shared__ double x[CB];
+// Backward solve step with L^T: every block stages L_kk through LDS and its
+// wave 0 solves L_kk^T x_k = vec_k (lane j keeps column j of L_kk; steps run
+// from the last row up); block 0 stores x_k in out.  Then every wave takes 64
+// rows c < k0 and subtracts sum_q L[k0+q][c] x_q: lane q reads L's block row
+// coalesced and a transpose-reduce sums over the wave.
+__global__ __launch_bounds__(256) void k_trsv_bwd(const double *S, int64_t ldS, int64_t N, int64_t k0,
+                                                  const double *invd, double *vec, double *out) {
+    __shared__ double Lt[CB * (CB + 1)];   // Lt[j * (CB + 1) + q] = L[k0 + q][k0 + j], q > j
+    __shared__ double xs[CB];
     const int nb = (int)min((int64_t)CB, N - k0);
-    for (int q = threadIdx.x; q < CB * CB; q += 256) {
-        const int r = q % CB, c = q / CB;
-        Lk[r][c] = (r < nb && c < nb && r >= c) ? S[(k0 + c) * ldS + k0 + r] : 0.0;
+    for (int t = threadIdx.x; t < CB * CB; t += 256) {
+        const int q = t % CB, j = t / CB;
+        Lt[j * (CB + 1) + q] = (q > j && q < nb) ? S[(k0 + j) * ldS + k0 + q] : 0.0;
     }
-    if ((int)threadIdx.x < CB) x[threadIdx.x] = (int)threadIdx.x < nb ? vec[k0 + threadIdx.x] : 0.0;
     __syncthreads();
-    {
-        const int r = threadIdx.x;   // every thread reaches every barrier
-        for (int c = nb - 1; c >= 0; --c) {
-            if (r == c) x[c] = x[c] / Lk[c][c];
-            __syncthreads();
-            if (r < c) x[r] -= Lk[c][r] * x[c];
-            __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w == 0) {
+        const int j = lane;
+        double cl[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) cl[q] = Lt[j * (CB + 1) + q];
+        double y = j < nb ? vec[k0 + j] : 0.0;
+        const double dj = j < nb ? invd[k0 + j] : 0.0;
+        double mine = 0.0;
+#pragma unroll
+        for (int q = CB - 1; q >= 0; --q) {
+            const double xq = lane_value(y, q) * lane_value(dj, q);
+            if (j == q) mine = xq;
+            y = fma(-cl[q], xq, y);
         }
+        xs[j] = mine;
+        if (blockIdx.x == 0 && j < nb) out[k0 + j] = mine;
     }
-    if (blockIdx.x == 0) {
-        if ((int)threadIdx.x < nb) out[k0 + threadIdx.x] = x[threadIdx.x];
-        return;
-    }
-    const int64_t row = (int64_t)(blockIdx.x - 1) * 256 + threadIdx.x;
-    if (row >= k0) return;
-    double v = vec[row];
-    for (int q = 0; q < nb; ++q) v -= S[row * ldS + k0 + q] * x[q];
-    vec[row] = v;
+    __syncthreads();
+    const int64_t c0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+    if (c0 >= k0) return;   // k0 is a multiple of CB, so c0 + 63 < k0 otherwise
+    const double xq = xs[lane];
+    const bool on = lane < nb;
+    double v[YVALS];
+#pragma unroll
+    for (int jj = 0; jj < YVALS; ++jj) v[jj] = on ? S[(c0 + jj) * ldS + k0 + lane] * xq : 0.0;
+    const double sum = wave_transpose_reduce(v, lane);
+    vec[c0 + lane] -= sum;
 }
 
 // ---------------------------------------------------------------- line search
@@ -1119,7 +1161,7 @@ __global__ __launch_bounds__(NTHR) void k_duals_out(AnlsParams p, IpmArgs ia, do
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct IpmLayout {
-    size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Qi, Z, S, vec, vec2, part, fpart, sc, total;
+    size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Qi, Z, S, vec, vec2, invd, part, fpart, sc, total;
     int64_t ldX, ldY, ldS;
 };
 
@@ -1144,6 +1186,7 @@ static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     L.S = take((size_t)N * L.ldS * 8);
     L.vec = take((size_t)L.ldS * 8);
     L.vec2 = take((size_t)L.ldS * 8);
+    L.invd = take((size_t)L.ldS * 8);
     L.part = take((size_t)nblk * PRS * 8);
     L.fpart = take((size_t)Tn * 64 * 8 * sizeof(double));   // Tn * Sx records of 8 (Sx <= 64)
     L.sc = take(sizeof(IpmScal));
@@ -1163,6 +1206,7 @@ nmf_status ipm_bind(IpmState &s, uint8_t *base, int64_t n, int64_t m_cap, int K)
     s.V = (double *)(base + L.V); s.tX = (double *)(base + L.tX); s.tY = (double *)(base + L.tY);
     s.Lq = (double *)(base + L.Lq); s.Qi = (double *)(base + L.Qi); s.Z = (double *)(base + L.Z);
     s.S = (double *)(base + L.S); s.vec = (double *)(base + L.vec); s.vec2 = (double *)(base + L.vec2);
+    s.invd = (double *)(base + L.invd);
     s.part = (double *)(base + L.part); s.fpart = (double *)(base + L.fpart);
     s.sc = (IpmScal *)(base + L.sc);
     s.bound = true;
@@ -1248,10 +1292,11 @@ nmf_status cholesky(Ctx &c, int64_t N) {
     double *S = c.s.S;
     const int64_t ldS = c.s.ldS;
     for (int64_t k0 = 0; k0 < N; k0 += CB) {
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, c.st, S, ldS, N, k0, c.s.sc);
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, c.st, S, ldS, N, k0, c.s.invd, c.s.sc);
         const int64_t below = N - k0 - CB;
         if (below > 0) {
-            hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, c.st, S, ldS, N, k0);
+            hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, c.st, S, ldS, N,
+                               k0, (const double *)c.s.invd);
             const int64_t nt = (below + CB - 1) / CB;
             hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, c.st, S, ldS, N, k0);
         }
@@ -1262,18 +1307,21 @@ nmf_status cholesky(Ctx &c, int64_t N) {
 
 // vec2 = S^-1 vec (S = L L^T, factored in place); vec is overwritten.
 nmf_status solve_S(Ctx &c, int64_t N) {
-    double *S = c.s.S;
+    const double *S = c.s.S;
     const int64_t ldS = c.s.ldS;
     for (int64_t k0 = 0; k0 < N; k0 += CB) {
         const int64_t below = N - k0 - CB;
-        const unsigned nb = 1 + (below > 0 ? (unsigned)((below + 255) / 256) : 0u);
-        hipLaunchKernelGGL(k_trsv_fwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, c.s.vec, c.s.vec2);
+        const unsigned nb = below > 0 ? (unsigned)((below + 255) / 256) : 1u;
+        hipLaunchKernelGGL(k_trsv_fwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, (const double *)c.s.invd,
+                           c.s.vec, c.s.vec2);
     }
     // backward on vec2 (y) -> vec (x)
     const int64_t last = (N - 1) / CB * CB;
     for (int64_t k0 = last; k0 >= 0; k0 -= CB) {
-        const unsigned nb = 1 + (unsigned)((k0 + 255) / 256);
-        hipLaunchKernelGGL(k_trsv_bwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, c.s.vec2, c.s.vec);
+        const int64_t chunks = k0 / 64;
+        const unsigned nb = chunks > 0 ? (unsigned)((chunks + 3) / 4) : 1u;
+        hipLaunchKernelGGL(k_trsv_bwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, (const double *)c.s.invd,
+                           c.s.vec2, c.s.vec);
     }
     HCK(hipMemcpyAsync(c.s.vec2, c.s.vec, sizeof(double) * N, hipMemcpyDeviceToDevice, c.st));
     HCK(hipGetLastError());

@@ -529,6 +529,16 @@ nmf_status nmf_get_masks(nmf_ctx *c, uint32_t *xm, uint32_t *ym) {
     return NMF_OK;
 }
 
+nmf_status nmf_set_anls_budget(nmf_ctx *c, int32_t max_sweeps) {
+    if (!c) return NMF_EINVAL;
+    if (max_sweeps < 1) return fail(c, NMF_EINVAL, "max_sweeps < 1");
+    if (c->stage != 1) return fail(c, NMF_ESTATE, "stage 2 has started");
+    c->opt.max_anls_sweeps = max_sweeps;
+    HIPCHK(c, nmfk::launch_rearm(c->p.st, max_sweeps, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NMF_OK;
+}
+
 nmf_status nmf_set_launch_shape(nmf_ctx *c, int32_t xs, int32_t ys) {
     if (!c) return NMF_EINVAL;
     if (xs < 0 || xs > kSxMax || ys < 0 || ys > kSyMax) return fail(c, NMF_EINVAL, "splits out of range");

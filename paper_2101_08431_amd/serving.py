@@ -19,6 +19,9 @@ on the grown problem.  Requests of one stream run in arrival order.
   * a joining request's append runs on its stream's own HIP stream while the
     batch of the running requests executes.
 
+A request ends when the stop rule of Sec. IV holds on the grown problem or
+its sweep budget (``request_sweeps``) is spent, whichever comes first.
+
 ``PlainServer`` is the plain per-request method on the same kernels and the
 same resident state: one request at a time in arrival order, each with its
 own stage-1 sweeps (rounds of the same length).
@@ -86,13 +89,19 @@ def _options(eps_stol, max_sweeps):
 
 
 class _Base:
-    def __init__(self, specs: List[StreamSpec], eps_stol=1e-6, max_sweeps=5000, sweeps_per_round=4,
-                 hbm_budget=None, record=False):
+    """eps_stol: the stop rule of every solve; initial_sweeps: sweep budget of
+    the solve of a stream's first window; request_sweeps: sweep budget of each
+    request (a request ends when the stop rule holds or its budget is spent);
+    sweeps_per_round: sweeps between two status checks."""
+
+    def __init__(self, specs: List[StreamSpec], eps_stol=1e-4, initial_sweeps=2000, request_sweeps=64,
+                 sweeps_per_round=4, hbm_budget=None, record=False):
         import torch
         from ._lib import workspace_bytes
         self.torch = torch
         self.streams = {s.sid: _Stream(s) for s in specs}
-        self.opts = _options(eps_stol, max_sweeps)
+        self.opts = _options(eps_stol, initial_sweeps)
+        self.request_sweeps = int(request_sweeps)
         self.T = int(sweeps_per_round)
         self.record = record
         for st in self.streams.values():
@@ -108,28 +117,50 @@ class _Base:
     def _can_open(self, st):
         return self.in_use + st.nbytes <= self.budget
 
-    def _open(self, st):
-        """Allocate the stream's workspace and solve its first window (Alg. 1
-        from the given start until the stop rule holds)."""
+    def _create(self, st):
         from ._lib import NMF
-        torch = self.torch
-        st.hip_stream = torch.cuda.Stream()
+        st.hip_stream = self.torch.cuda.Stream()
         sp = st.spec
         st.ctx = NMF(sp.M0, sp.k, sp.X0, sp.Y0, m_capacity=sp.m_capacity, options=self.opts,
                      stream=st.hip_stream)
         self.in_use += st.nbytes
         self.peak_in_use = max(self.peak_in_use, self.in_use)
+
+    def _open(self, st):
+        """Allocate the stream's workspace and solve its first window (Alg. 1
+        from the given start until the stop rule holds or the initial budget
+        is spent), then set the per-request budget."""
+        self._create(st)
         while True:
             code, rep = st.ctx.anls_step(64)
             if code == 1:
                 break
         st.sweeps = rep["sweeps"]
+        st.ctx.set_anls_budget(self.request_sweeps)
 
     def open_all(self):
-        """Open every stream that fits the budget (before a timed run)."""
+        """Open every stream that fits the budget (before a timed run).  The
+        first windows are solved together in batched sweeps; each ends where
+        its own solve would."""
+        from ._lib import Batch
+        new = []
         for st in self.streams.values():
             if st.ctx is None and not st.closed and self._can_open(st):
-                self._open(st)
+                self._create(st)
+                new.append(st)
+        if not new:
+            return
+        self.torch.cuda.synchronize()
+        b = Batch([st.ctx for st in new])
+        while True:
+            b.step(32, graph=False)
+            conv, sweeps = b.poll()
+            if conv.all():
+                break
+        b.close()
+        for st, sw in zip(new, sweeps):
+            st.sweeps = int(sw)
+            st.ctx.set_anls_budget(self.request_sweeps)
 
     def close_all(self):
         for st in self.streams.values():
@@ -211,6 +242,7 @@ class Server(_Base):
         joined: List[_Stream] = []     # appended, join at the next round
         batch = None
         batch_members: List[_Stream] = []
+        dirty = False
         self.t0 = time.perf_counter()
         remaining = len(pending)
         while remaining > 0:
@@ -224,14 +256,18 @@ class Server(_Base):
                 if st.active is None and st not in ready:
                     ready.append(st)
             self._admit_streams()
-            # membership for this round
-            running.extend(joined)
-            joined = []
-            if running and [s.spec.sid for s in running] != [s.spec.sid for s in batch_members]:
+            # membership for this round: a batch holds each problem's shape as
+            # it was when the batch was built, so any join or leave rebuilds it
+            if joined:
+                running.extend(joined)
+                joined = []
+                dirty = True
+            if running and dirty:
                 if batch is not None:
                     batch.close()
                 batch = Batch([s.ctx for s in running], stream=self._batch_stream())
                 batch_members = list(running)
+                dirty = False
             if running:
                 batch.step(self.T, graph=self.use_graph)
                 self.rounds += 1
@@ -266,6 +302,8 @@ class Server(_Base):
                             ready.append(st)
                     else:
                         still.append(st)
+                if len(still) != len(running):
+                    dirty = True
                 running = still
             elif not joined:
                 # idle: wait for the next arrival (or for memory that never frees)

@@ -128,3 +128,7 @@ def test_append_rearms_the_sweep_budget():
     assert st == 0 and rep["sweeps"] == 10
     st, rep = ctx.anls_step(20)
     assert st == 1 and rep["sweeps"] == 14
+    # an explicit budget re-arms the stop rule and applies to later appends
+    ctx.set_anls_budget(5)
+    st, rep = ctx.anls_step(20)
+    assert st == 1 and rep["sweeps"] == 19
