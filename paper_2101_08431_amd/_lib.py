@@ -66,6 +66,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library missing: {LIB_PATH} (run paper_2101_08431_amd.build.build())")
+    # PyTorch ships its own HIP runtime.  Importing it first makes this
+    # library bind to that same runtime (the sonames match); loaded the other
+    # way round, the process would hold two HIP runtimes and the second one
+    # finds no device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     L.nmf_default_options.argtypes = [ctypes.POINTER(Options)]

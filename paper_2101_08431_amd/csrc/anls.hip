@@ -166,31 +166,51 @@ __device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int 
 
 template <int K>
 __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
-    if (p.mode == 0 && p.st->converged) return;
     __shared__ double G[K * K];
     __shared__ double lds[NTHR];
-    reduce_records(p.gy_part, p.By, K * K, G, lds);
     const int64_t i = (int64_t)bid * NTHR + threadIdx.x;
+    const bool live = i < p.n;
+    // the row's loads go out before anything waits on memory
+    double b[K], x[K];
+    uint32_t old_mask = 0u;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        b[a] = 0.0;
+        x[a] = live ? p.X[(int64_t)a * p.ldX + i] : 0.0;
+    }
+    if (live) {
+        old_mask = p.xmask[i];
+        int s = 0;
+        for (; s + 1 < p.Sx; s += 2) {
+            double t0[K], t1[K];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                t0[a] = p.bx_part[((int64_t)s * K + a) * p.ldX + i];
+                t1[a] = p.bx_part[((int64_t)(s + 1) * K + a) * p.ldX + i];
+            }
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                b[a] += t0[a];
+                b[a] += t1[a];
+            }
+        }
+        for (; s < p.Sx; ++s) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) b[a] += p.bx_part[((int64_t)s * K + a) * p.ldX + i];
+        }
+    }
+    if (p.mode == 0 && p.st->converged) return;
+    reduce_records(p.gy_part, p.By, K * K, G, lds);
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
     double xn[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) xn[a] = 0.0;
-    if (i < p.n) {
+    if (live) {
         double gmax = 0.0;
 #pragma unroll
         for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
-        double b[K], x[K];
-#pragma unroll
-        for (int a = 0; a < K; ++a) {
-            b[a] = 0.0;
-            x[a] = p.X[(int64_t)a * p.ldX + i];
-        }
-        for (int s = 0; s < p.Sx; ++s) {
-#pragma unroll
-            for (int a = 0; a < K; ++a) b[a] += p.bx_part[((int64_t)s * K + a) * p.ldX + i];
-        }
         // graX at the old point: (X Y Y^T - M Y^T)_i
 #pragma unroll
         for (int a = 0; a < K; ++a) {
@@ -201,7 +221,6 @@ __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
             else st[ST_EC2] += (g * x[a]) * (g * x[a]);
         }
         if (p.mode == 0) {
-            const uint32_t old_mask = p.xmask[i];
 #pragma unroll
             for (int a = 0; a < K; ++a) {
                 xn[a] = x[a];
@@ -266,35 +285,43 @@ __device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int sp
 
 template <int K>
 __device__ __forceinline__ void ynnls_body(const AnlsParams &p, int bid) {
-    if (p.mode == 0 && p.st->converged) return;
     __shared__ double G[K * K];
     __shared__ double lds[NTHR];
     __shared__ unsigned flag;
-    reduce_records(p.gx_part, p.Bx, K * K, G, lds);
     const int64_t j = (int64_t)bid * NTHR + threadIdx.x;
+    const bool live = j < p.m;
+    // the column's loads go out before anything waits on memory
+    double b[K], y[K];
+    uint32_t old_mask = 0u;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        b[a] = 0.0;
+        y[a] = live ? p.Y[(int64_t)a * p.ldY + j] : 0.0;
+    }
+    if (live) {
+        old_mask = p.ymask[j];
+        for (int s = 0; s < p.Sy; ++s) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) b[a] += p.by_part[((int64_t)s * K + a) * p.ldY + j];
+        }
+    }
+    if (p.mode == 0 && p.st->converged) return;
+    reduce_records(p.gx_part, p.Bx, K * K, G, lds);
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
     double yn[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) yn[a] = 0.0;
-    if (j < p.m) {
+    if (live) {
         double gmax = 0.0;
 #pragma unroll
         for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
-        double b[K], y[K];
 #pragma unroll
         for (int a = 0; a < K; ++a) {
-            b[a] = 0.0;
-            y[a] = p.Y[(int64_t)a * p.ldY + j];
             yn[a] = y[a];
             st[ST_NORM2] += y[a] * y[a];
         }
-        for (int s = 0; s < p.Sy; ++s) {
-#pragma unroll
-            for (int a = 0; a < K; ++a) b[a] += p.by_part[((int64_t)s * K + a) * p.ldY + j];
-        }
-        const uint32_t old_mask = p.ymask[j];
         const LhResult r = lh_warm<K>(G, gmax, b, yn);
 #pragma unroll
         for (int a = 0; a < K; ++a) {

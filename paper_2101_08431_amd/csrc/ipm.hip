@@ -38,7 +38,6 @@ namespace nmfk {
 constexpr int PRS = KMAX * KMAX;   // stride of block records in `part`
 constexpr int CB = 64;             // dense Cholesky / triangular-solve block
 constexpr int TJ = 16;             // Schur tile: 16 x 16 (j, l) pairs
-constexpr int SRB = 4;             // rows of X staged per Schur step
 constexpr int ZRB = 8;             // rows per block of the Z kernel
 
 struct IpmArgs {
@@ -501,13 +500,14 @@ __global__ __launch_bounds__(NTHR) void k_zmat(AnlsParams p, IpmArgs ia) {
 template <int K, bool EXACT>
 __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double rho) {
     constexpr int NL = K * (K + 1) / 2;
-    __shared__ double Zs[SRB][K][2 * TJ];
-    __shared__ double XX[SRB][K * K];
-    __shared__ double Xs[SRB][K];
-    __shared__ double Ws[EXACT ? SRB : 1][EXACT ? K : 1][2 * TJ];
-    __shared__ double Rs[EXACT ? SRB : 1][2 * TJ];
-    __shared__ double Qs[EXACT ? SRB : 1][EXACT ? K * K : 1];
-    __shared__ double Ls[EXACT ? SRB : 1][EXACT ? NL + K : 1];
+    constexpr int SR = (K <= 8 && !EXACT) ? 16 : 8;   // rows of X staged per step
+    __shared__ double Zs[SR][K][2 * TJ];
+    __shared__ double XX[SR][EXACT ? K * K : K * (K + 1) / 2];
+    __shared__ double Xs[SR][K];
+    __shared__ double Ws[EXACT ? SR : 1][EXACT ? K : 1][2 * TJ];
+    __shared__ double Rs[EXACT ? SR : 1][2 * TJ];
+    __shared__ double Qs[EXACT ? SR : 1][EXACT ? K * K : 1];
+    __shared__ double Ls[EXACT ? SR : 1][EXACT ? NL + K : 1];
     // tile index -> (jt, lt), jt >= lt
     const int64_t tix = blockIdx.x;
     int64_t jt = (int64_t)((sqrt(8.0 * (double)tix + 1.0) - 1.0) * 0.5);
@@ -517,30 +517,33 @@ __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double 
     const int jj = threadIdx.x / TJ, ll = threadIdx.x % TJ;
     const int64_t j = jt * TJ + jj, l = lt * TJ + ll;
 
-    double acc[K * K];
+    // The Gauss-Newton part of block (j, l) is symmetric in (a, b): without
+    // the exact terms only its lower triangle is accumulated.
+    constexpr int NACC = EXACT ? K * K : NL;
+    double acc[NACC];
 #pragma unroll
-    for (int q = 0; q < K * K; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
 
-    for (int64_t i0 = 0; i0 < p.n; i0 += SRB) {
+    for (int64_t i0 = 0; i0 < p.n; i0 += SR) {
         __syncthreads();
-        for (int q = threadIdx.x; q < SRB * K * 2 * TJ; q += 256) {
+        for (int q = threadIdx.x; q < SR * K * 2 * TJ; q += 256) {
             const int rr = q / (K * 2 * TJ), c = (q / (2 * TJ)) % K, col = q % (2 * TJ);
             const int64_t i = i0 + rr;
             const int64_t jc = col < TJ ? jt * TJ + col : lt * TJ + col - TJ;
             Zs[rr][c][col] = (i < p.n && jc < p.m) ? ia.Z[(i * K + c) * p.ldY + jc] : 0.0;
         }
-        for (int q = threadIdx.x; q < SRB * K; q += 256) {
+        for (int q = threadIdx.x; q < SR * K; q += 256) {
             const int rr = q / K, a = q % K;
             const int64_t i = i0 + rr;
             Xs[rr][a] = i < p.n ? p.X[(int64_t)a * p.ldX + i] : 0.0;
         }
         if (EXACT) {
-            for (int q = threadIdx.x; q < SRB * (NL + K); q += 256) {
+            for (int q = threadIdx.x; q < SR * (NL + K); q += 256) {
                 const int rr = q / (NL + K), c = q % (NL + K);
                 const int64_t i = i0 + rr;
                 Ls[rr][c] = i < p.n ? ia.Lq[(int64_t)c * p.ldX + i] : 1.0;
             }
-            for (int q = threadIdx.x; q < SRB * K * K; q += 256) {
+            for (int q = threadIdx.x; q < SR * K * K; q += 256) {
                 const int rr = q / (K * K), a = (q / K) % K, b = q % K;
                 const int64_t i = i0 + rr;
                 const int hi = a > b ? a : b, lo = a > b ? b : a;
@@ -548,13 +551,22 @@ __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double 
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < SRB * K * K; q += 256) {
-            const int rr = q / (K * K), a = (q / K) % K, b = q % K;
-            XX[rr][a * K + b] = Xs[rr][a] * Xs[rr][b];
+        for (int q = threadIdx.x; q < SR * NACC; q += 256) {
+            const int rr = q / NACC, t = q % NACC;
+            int a, b;
+            if (EXACT) {
+                a = t / K;
+                b = t % K;
+            } else {
+                a = 0;
+                while ((a + 1) * (a + 2) / 2 <= t) ++a;
+                b = t - a * (a + 1) / 2;
+            }
+            XX[rr][t] = Xs[rr][a] * Xs[rr][b];
         }
         if (EXACT) {
             // w = L^-T z for the 32 staged columns; R_ij = X_i . Y_j - M_ij
-            for (int q = threadIdx.x; q < SRB * 2 * TJ; q += 256) {
+            for (int q = threadIdx.x; q < SR * 2 * TJ; q += 256) {
                 const int rr = q / (2 * TJ), col = q % (2 * TJ);
                 const int64_t i = i0 + rr;
                 const int64_t jc = col < TJ ? jt * TJ + col : lt * TJ + col - TJ;
@@ -581,12 +593,12 @@ __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double 
         }
         __syncthreads();
 #pragma unroll
-        for (int rr = 0; rr < SRB; ++rr) {
+        for (int rr = 0; rr < SR; ++rr) {
             double c = 0.0;
 #pragma unroll
             for (int q = 0; q < K; ++q) c = fma(Zs[rr][q][jj], Zs[rr][q][TJ + ll], c);
 #pragma unroll
-            for (int q = 0; q < K * K; ++q) acc[q] = fma(c, XX[rr][q], acc[q]);
+            for (int q = 0; q < NACC; ++q) acc[q] = fma(c, XX[rr][q], acc[q]);
             if (EXACT) {
                 const double Rj = Rs[rr][jj], Rl = Rs[rr][TJ + ll];
                 const double RR = Rj * Rl;
@@ -596,11 +608,12 @@ __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double 
                     const double wla_rj = Ws[rr][a][TJ + ll] * Rj;
 #pragma unroll
                     for (int b = 0; b < K; ++b) {
-                        double v = acc[a * K + b];
+                        const int q = EXACT ? a * K + b : 0;
+                        double v = acc[q];
                         v = fma(xa_rl, Ws[rr][b][jj], v);
                         v = fma(wla_rj, Xs[rr][b], v);
                         v = fma(RR, Qs[rr][a * K + b], v);
-                        acc[a * K + b] = v;
+                        acc[q] = v;
                     }
                 }
             }
@@ -612,7 +625,8 @@ __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double 
         for (int a = 0; a < K; ++a) {
 #pragma unroll
             for (int b = 0; b < K; ++b) {
-                double v = -acc[a * K + b];
+                const int q = EXACT ? a * K + b : (a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a);
+                double v = -acc[q];
                 if (j == l) {
                     v += G[a * K + b];
                     if (a == b) v += rho + ia.s[(int64_t)a * p.ldY + j] / p.Y[(int64_t)a * p.ldY + j];
@@ -766,73 +780,123 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Diagonal block [k0, k0 + nb) by one wave: lane i keeps row i of the block
-// in registers.  Step c takes the pivot from lane c, scales column c, and
-// every lane applies the rank-one update to its row with the entries L[j][c]
-// read from lane j.  A pivot that is not positive sets sc->chol_fail and is
-// replaced by 1.
-__global__ __launch_bounds__(64) void k_chol_diag(double *S, int64_t ldS, int64_t N, int64_t k0, double *invd,
+// Diagonal block [k0, k0 + nb) by one block of 256 threads: thread (tx, ty)
+// keeps the 4 x 4 entries (tx + 16a, ty + 16b) in registers.  Step c: the
+// owner of (c, c) takes the square root of the pivot, the owners of column c
+// scale it and publish it in LDS, and every thread applies the rank-one update
+// to its entries of the trailing triangle.  A pivot that is not positive sets
+// sc->chol_fail and is replaced by 1.
+__global__ __launch_bounds__(256) void k_chol_diag(double *S, int64_t ldS, int64_t N, int64_t k0, double *invd,
                                                  IpmScal *sc) {
-    const int i = threadIdx.x;
+    __shared__ double colv[CB];
+    __shared__ double piv;
+    __shared__ int bad;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int nb = (int)min((int64_t)CB, N - k0);
-    double a[CB];
+    double a[4][4];
 #pragma unroll
-    for (int j = 0; j < CB; ++j)
-        a[j] = (j <= i && i < nb) ? S[(k0 + j) * ldS + k0 + i] : (j == i ? 1.0 : 0.0);
-    bool bad = false;
-    double mine = 1.0;
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = tx + 16 * u, j = ty + 16 * v;
+            a[u][v] = (i >= j && i < nb) ? S[(k0 + j) * ldS + k0 + i] : (i == j ? 1.0 : 0.0);
+        }
+    if (threadIdx.x == 0) bad = 0;
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-        const double d = lane_value(a[c], c);
-        const bool ok = d > 0.0;
-        bad = bad || !ok;
-        const double l = sqrt(ok ? d : 1.0);
-        const double il = 1.0 / l;
-        if (i == c) {
-            a[c] = l;
-            mine = il;
-        } else if (i > c) {
-            a[c] *= il;
+        const int cu = c >> 4, cr = c & 15;
+        if (tx == cr && ty == cr) {
+            const double d = a[cu][cu];
+            const bool ok = d > 0.0;
+            if (!ok) bad = 1;
+            const double l = sqrt(ok ? d : 1.0);
+            a[cu][cu] = l;
+            piv = 1.0 / l;
         }
-        const double lic = (i > c) ? a[c] : 0.0;
+        __syncthreads();
+        if (ty == cr) {
+            const double il = piv;
 #pragma unroll
-        for (int j = c + 1; j < CB; ++j) a[j] = fma(-lic, lane_value(a[c], j), a[j]);
-    }
-    if (i < nb) {
+            for (int u = 0; u < 4; ++u) {
+                const int i = tx + 16 * u;
+                if (i > c) {
+                    a[u][cu] *= il;
+                    colv[i] = a[u][cu];
+                }
+            }
+        }
+        __syncthreads();
+        double li[4], lj[4];
 #pragma unroll
-        for (int j = 0; j < CB; ++j)
-            if (j <= i) S[(k0 + j) * ldS + k0 + i] = a[j];
-        invd[k0 + i] = mine;
+        for (int u = 0; u < 4; ++u) {
+            li[u] = (tx + 16 * u > c) ? colv[tx + 16 * u] : 0.0;
+            lj[u] = (ty + 16 * u > c) ? colv[ty + 16 * u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[u][v] = fma(-li[u], lj[v], a[u][v]);
     }
-    if (i == 0 && bad) sc->chol_fail = 1;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = tx + 16 * u, j = ty + 16 * v;
+            if (i >= j && i < nb) S[(k0 + j) * ldS + k0 + i] = a[u][v];
+            if (i > j && i < nb) S[(k0 + i) * ldS + k0 + j] = a[u][v];   // transposed copy
+            if (i == j && i < nb) invd[k0 + i] = 1.0 / a[u][v];
+        }
+    if (threadIdx.x == 0 && bad) sc->chol_fail = 1;
 }
 
 // Panel below a full diagonal block: L[r, k0:k0+CB) = S[r, k0:k0+CB) L_kk^-T,
 // one row per thread, solved left to right with every later entry updated at
-// once (independent fused multiply-adds); L_kk is read from LDS.
+// once; L_kk and 1 / diag are read from LDS.  The block's rows are also
+// stored transposed into the upper triangle, S[r * ldS + k0 + q] =
+// L[r][k0 + q], staged through LDS so that each wave writes one contiguous
+// row; the backward triangular solve reads them there.
 __global__ __launch_bounds__(256) void k_chol_panel(double *S, int64_t ldS, int64_t N, int64_t k0,
                                                   const double *invd) {
     __shared__ double Lk[CB * CB];   // Lk[q * CB + j] = L[k0 + j][k0 + q], j > q
     __shared__ double id[CB];
+    __shared__ double T[CB * 129];   // T[q * 129 + t] = L[row of thread t][k0 + q], half a block at a time
     for (int t = threadIdx.x; t < CB * CB; t += 256) {
         const int j = t % CB, q = t / CB;
         Lk[t] = (j > q) ? S[(k0 + q) * ldS + k0 + j] : 0.0;
     }
     if (threadIdx.x < CB) id[threadIdx.x] = invd[k0 + threadIdx.x];
     __syncthreads();
-    const int64_t r = k0 + CB + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= N) return;
+    const int64_t base = k0 + CB + (int64_t)blockIdx.x * 256;
+    const int64_t r = base + threadIdx.x;
     double x[CB];
+    if (r < N) {
 #pragma unroll
-    for (int q = 0; q < CB; ++q) x[q] = S[(k0 + q) * ldS + r];
+        for (int q = 0; q < CB; ++q) x[q] = S[(k0 + q) * ldS + r];
 #pragma unroll
-    for (int q = 0; q < CB; ++q) {
-        x[q] *= id[q];
+        for (int q = 0; q < CB; ++q) {
+            x[q] *= id[q];
 #pragma unroll
-        for (int j = q + 1; j < CB; ++j) x[j] = fma(-x[q], Lk[q * CB + j], x[j]);
+            for (int j = q + 1; j < CB; ++j) x[j] = fma(-x[q], Lk[q * CB + j], x[j]);
+        }
+#pragma unroll
+        for (int q = 0; q < CB; ++q) S[(k0 + q) * ldS + r] = x[q];
     }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < CB; ++q) S[(k0 + q) * ldS + r] = x[q];
+    for (int half = 0; half < 2; ++half) {
+        __syncthreads();
+        const int t = (int)threadIdx.x - 128 * half;
+        if (t >= 0 && t < 128 && r < N) {
+#pragma unroll
+            for (int q = 0; q < CB; ++q) T[q * 129 + t] = x[q];
+        }
+        __syncthreads();
+        for (int rr = w; rr < 128; rr += 4) {
+            const int64_t r2 = base + 128 * half + rr;
+            if (r2 < N) S[r2 * ldS + k0 + lane] = T[lane * 129 + rr];
+        }
+    }
 }
 
 // Trailing update of the lower triangle: S[r][c] -= sum_q L[r][k0+q] L[c][k0+q]
@@ -918,27 +982,20 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const double *S, int64_t ldS, 
     vec[row] = v;
 }
 
-// Backward solve step with L^T: every block stages L_kk through LDS and its
-// wave 0 solves L_kk^T x_k = vec_k (lane j keeps column j of L_kk; steps run
-// from the last row up); block 0 stores x_k in out.  Then every wave takes 64
-// rows c < k0 and subtracts sum_q L[k0+q][c] x_q: lane q reads L's block row
-// coalesced and a transpose-reduce sums over the wave.
+// Backward solve step with L^T, reading the transposed copy of L kept in the
+// upper triangle (S[(k0 + q) * ldS + c] = L[k0 + q][c], c < k0 + q): wave 0
+// of every block solves L_kk^T x_k = vec_k (lane j keeps column j of L_kk;
+// steps run from the last row up) into LDS; block 0 stores x_k in out; every
+// block then subtracts sum_q L[k0+q][c] x_q from its 256 rows c < k0.
 __global__ __launch_bounds__(256) void k_trsv_bwd(const double *S, int64_t ldS, int64_t N, int64_t k0,
                                                   const double *invd, double *vec, double *out) {
-    __shared__ double Lt[CB * (CB + 1)];   // Lt[j * (CB + 1) + q] = L[k0 + q][k0 + j], q > j
     __shared__ double xs[CB];
     const int nb = (int)min((int64_t)CB, N - k0);
-    for (int t = threadIdx.x; t < CB * CB; t += 256) {
-        const int q = t % CB, j = t / CB;
-        Lt[j * (CB + 1) + q] = (q > j && q < nb) ? S[(k0 + j) * ldS + k0 + q] : 0.0;
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (w == 0) {
-        const int j = lane;
+    if (threadIdx.x < 64) {
+        const int j = threadIdx.x;
         double cl[CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) cl[q] = Lt[j * (CB + 1) + q];
+        for (int q = 0; q < CB; ++q) cl[q] = (q > j && q < nb) ? S[(k0 + q) * ldS + k0 + j] : 0.0;
         double y = j < nb ? vec[k0 + j] : 0.0;
         const double dj = j < nb ? invd[k0 + j] : 0.0;
         double mine = 0.0;
@@ -952,15 +1009,12 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(const double *S, int64_t ldS, 
         if (blockIdx.x == 0 && j < nb) out[k0 + j] = mine;
     }
     __syncthreads();
-    const int64_t c0 = ((int64_t)blockIdx.x * 4 + w) * 64;
-    if (c0 >= k0) return;   // k0 is a multiple of CB, so c0 + 63 < k0 otherwise
-    const double xq = xs[lane];
-    const bool on = lane < nb;
-    double v[YVALS];
-#pragma unroll
-    for (int jj = 0; jj < YVALS; ++jj) v[jj] = on ? S[(c0 + jj) * ldS + k0 + lane] * xq : 0.0;
-    const double sum = wave_transpose_reduce(v, lane);
-    vec[c0 + lane] -= sum;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= k0) return;
+    double v = vec[c];
+#pragma unroll 8
+    for (int q = 0; q < nb; ++q) v = fma(-S[(k0 + q) * ldS + c], xs[q], v);
+    vec[c] = v;
 }
 
 // ---------------------------------------------------------------- line search
@@ -1292,7 +1346,7 @@ nmf_status cholesky(Ctx &c, int64_t N) {
     double *S = c.s.S;
     const int64_t ldS = c.s.ldS;
     for (int64_t k0 = 0; k0 < N; k0 += CB) {
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, c.st, S, ldS, N, k0, c.s.invd, c.s.sc);
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, c.st, S, ldS, N, k0, c.s.invd, c.s.sc);
         const int64_t below = N - k0 - CB;
         if (below > 0) {
             hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, c.st, S, ldS, N,
@@ -1318,8 +1372,7 @@ nmf_status solve_S(Ctx &c, int64_t N) {
     // backward on vec2 (y) -> vec (x)
     const int64_t last = (N - 1) / CB * CB;
     for (int64_t k0 = last; k0 >= 0; k0 -= CB) {
-        const int64_t chunks = k0 / 64;
-        const unsigned nb = chunks > 0 ? (unsigned)((chunks + 3) / 4) : 1u;
+        const unsigned nb = k0 > 0 ? (unsigned)((k0 + 255) / 256) : 1u;
         hipLaunchKernelGGL(k_trsv_bwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, (const double *)c.s.invd,
                            c.s.vec2, c.s.vec);
     }
