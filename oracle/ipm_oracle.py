@@ -262,7 +262,9 @@ def ipm(M, X, Yt, r, s, mu, rho, opts: IPMOptions):
         mu_aff = (float(np.sum((X + a1a * dxa) * (r + a2a * dra)))
                   + float(np.sum((Yt + a1a * dya) * (s + a2a * dsa)))) / N
         avg = (float(np.sum(X * r)) + float(np.sum(Yt * s))) / N
-        sigma = min((mu_aff / avg) ** 3, 0.99)
+        # mu_aff >= 0 in exact arithmetic (points of the closed orthant); a
+        # rounding residue below 0 from the step to the boundary counts as 0
+        sigma = min((max(mu_aff, 0.0) / avg) ** 3, 0.99)
         mu = sigma * avg
         flag = 1 if sigma <= opts.sigma_c else 0
     return IPMResult(X=X, Yt=Yt, r=r, s=s, mu=mu, flag=flag, E0=E0, outer=outer, inner=inner,
