@@ -1562,7 +1562,10 @@ nmf_status mu_update(Ctx &c) {
     const double Nn = (double)(p.n + p.m) * c.K;
     const double avg = s.SR / Nn;   // current average complementarity
     const double mu_aff = h[0] / Nn;
-    double r = mu_aff / avg;
+    // mu_aff is a complementarity of points in the closed orthant, so it is
+    // >= 0; the step to the boundary (tau = 1) can leave a rounding residue
+    // below 0, which must not turn sigma (and mu) negative.
+    double r = mu_aff > 0.0 ? mu_aff / avg : 0.0;
     double sigma = r * r * r;
     if (sigma > 0.99) sigma = 0.99;
     s.sigma = sigma;
