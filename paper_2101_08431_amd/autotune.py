@@ -49,11 +49,11 @@ def splits_for_waves(n, m, k, waves):
     xs = max(1, min(math.ceil(waves / (SWAVES * tn)), 64, m))
     j = max(1, 64 // k)
     tm = math.ceil(m / j)
-    ys = max(1, min(math.ceil(waves / (SWAVES * tm)), max(1, n // (4 * STHR)), 64, n))
+    ys = max(1, min(math.ceil(waves / (SWAVES * tm)), max(1, n // STHR), 64, n))
     return xs, ys
 
 
-def tune_single(ctx, xs_cands=(1, 2, 4, 8, 16), ys_cands=(1, 2, 4), sweeps=30, use_cache=True):
+def tune_single(ctx, xs_cands=(1, 2, 4, 8, 11, 16), ys_cands=(1, 2, 3, 4, 6), sweeps=30, use_cache=True):
     """Pick (x_splits, y_splits) for one context; returns the choice and sets it."""
     key = f"single:{ctx.n}:{ctx.m}:{ctx.k}:{int(ctx.options.gram_precision)}"
     cache = _load() if use_cache else {}

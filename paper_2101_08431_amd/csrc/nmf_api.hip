@@ -34,7 +34,7 @@ struct Plan {
 
 // Stage-1 launch shape.  X stream: 64-row tiles, column splits so that about
 // 4096 waves stream M (8 per block).  Y stream: J = 64/K columns per tile, row
-// splits while every thread still covers >= 4 rows and the grid is short of
+// splits while every thread still covers >= 1 row and the grid is short of
 // ~4096 waves.  NNLS kernels: 256 problems per block.
 Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, int y_splits = 0) {
     Plan P;
@@ -49,7 +49,7 @@ Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, in
     P.Sx = (int)ceil_div(m, P.xcols);
     P.J = nmfk::yhalf_cols(K);
     P.Tm = (int)ceil_div(m, P.J);
-    int64_t sy = std::min<int64_t>(ceil_div(4096, (int64_t)P.Tm * nmfk::SWAVES), n / (4 * nmfk::STHR));
+    int64_t sy = std::min<int64_t>(ceil_div(4096, (int64_t)P.Tm * nmfk::SWAVES), n / nmfk::STHR);
     if (y_splits > 0) sy = y_splits;
     sy = std::max<int64_t>(1, std::min<int64_t>(sy, std::min<int64_t>(kSyMax, n)));
     P.yrows = (int)ceil_div(n, sy);
