@@ -180,8 +180,11 @@ nmf_status nmf_get_report(nmf_ctx *ctx, nmf_report *report);
 nmf_status nmf_anls_profile(nmf_ctx *ctx, int32_t sweeps, double *ms);
 
 /* Re-plans the stage-1 launch shape of a context: column splits of the X-half
- * and row splits of the Y-half (0 = automatic, at most 64 each).  Results do
- * not change beyond the rounding of the split sums.  Used by the autotuner. */
+ * and row splits of the Y-half (0 = automatic, at most 64 each).  A single
+ * split runs that half as one kernel that streams M and solves its tile.
+ * Results do not change beyond the rounding of the split sums.  Synchronises
+ * (the Gram partial sums are rebuilt for the new layout).  Used by the
+ * autotuner. */
 nmf_status nmf_set_launch_shape(nmf_ctx *ctx, int32_t x_splits, int32_t y_splits);
 
 /* Sets the stage-1 sweep budget (options.max_anls_sweeps, >= 1) used from now

@@ -17,6 +17,7 @@ import os
 import time
 
 XTILE, SWAVES, STHR = 64, 8, 512
+last_timings = {}   # ms per sweep of every shape the last tune_single call timed
 
 
 def _cache_path():
@@ -54,21 +55,33 @@ def splits_for_waves(n, m, k, waves):
 
 
 def tune_single(ctx, xs_cands=(1, 2, 4, 8, 11, 16), ys_cands=(1, 2, 3, 4, 6), sweeps=30, use_cache=True):
-    """Pick (x_splits, y_splits) for one context; returns the choice and sets it."""
+    """Pick (x_splits, y_splits) for one context by timing back-to-back sweeps
+    of each candidate shape (a single split makes that half one fused kernel);
+    returns the choice and sets it.  The sweeps advance the factorisation, so
+    tune a context whose stop rule cannot hold yet (or a copy of one)."""
     key = f"single:{ctx.n}:{ctx.m}:{ctx.k}:{int(ctx.options.gram_precision)}"
     cache = _load() if use_cache else {}
     if key in cache:
         xs, ys = cache[key]["choice"]
         ctx.set_launch_shape(xs, ys)
         return tuple(cache[key]["choice"])
+    import torch
     timings = {}
     for xs in xs_cands:
         for ys in ys_cands:
             ctx.set_launch_shape(xs, ys)
-            ctx.anls_profile(3)
-            timings[(xs, ys)] = sum(ctx.anls_profile(sweeps))
+            ctx.anls_step(3, report=False)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            ctx.anls_step(sweeps, report=False)
+            e1.record(ctx.stream)
+            e1.synchronize()
+            timings[(xs, ys)] = e0.elapsed_time(e1) / sweeps
     best = min(timings, key=timings.get)
     ctx.set_launch_shape(*best)
+    global last_timings
+    last_timings = {f"{a},{b}": v for (a, b), v in sorted(timings.items(), key=lambda kv: kv[1])}
     cache = _load()
     cache[key] = {"choice": list(best), "ms": timings[best],
                   "tried": {f"{a},{b}": v for (a, b), v in timings.items()}}

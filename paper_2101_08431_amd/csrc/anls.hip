@@ -106,18 +106,184 @@ struct MElem<NMF_GRAM_BF16X2> {
     }
 };
 
+// Row i of the X-half: the gradient statistics at the previous row x (E(.;0)
+// parts), and in mode 0 the warm-started solve, stored to X and the mask.
+// b is row i of B_X = M Y^T, G is G_Y in LDS.  xn receives the new row (zeros
+// in mode 1).
+template <int K>
+__device__ __forceinline__ void x_row(const AnlsParams &p, const double *G, int64_t i, const double (&x)[K],
+                                      const double (&b)[K], uint32_t old_mask, double (&st)[NST],
+                                      double (&xn)[K]) {
+    double gmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
+    // graX at the old point: (X Y Y^T - M Y^T)_i
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double g = -b[a];
+#pragma unroll
+        for (int c = 0; c < K; ++c) g = fma(G[a * K + c], x[c], g);
+        if (g < 0.0) st[ST_EG2] += g * g;
+        else st[ST_EC2] += (g * x[a]) * (g * x[a]);
+    }
+    if (p.mode == 0) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            xn[a] = x[a];
+            st[ST_NORM2] += x[a] * x[a];
+        }
+        const LhResult r = lh_warm<K>(G, gmax, b, xn);
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            const double d = xn[a] - x[a];
+            st[ST_STEP2] += d * d;
+            p.X[(int64_t)a * p.ldX + i] = xn[a];
+        }
+        p.xmask[i] = r.P;
+        st[ST_SOLVES] = r.solves;
+        st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
+        st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
+    }
+}
+
+// Column j of the Y-half: warm-started solve from the previous column y,
+// stored to Y and the mask, then the gradient statistics at the new column.
+// b is column j of B_Y = X^T M, G is G_X in LDS.
+template <int K>
+__device__ __forceinline__ void y_col(const AnlsParams &p, const double *G, int64_t j, const double (&y)[K],
+                                      const double (&b)[K], uint32_t old_mask, double (&st)[NST],
+                                      double (&yn)[K]) {
+    double gmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        yn[a] = y[a];
+        st[ST_NORM2] += y[a] * y[a];
+    }
+    const LhResult r = lh_warm<K>(G, gmax, b, yn);
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        const double d = yn[a] - y[a];
+        st[ST_STEP2] += d * d;
+        p.Y[(int64_t)a * p.ldY + j] = yn[a];
+    }
+    p.ymask[j] = r.P;
+    // graY at the new point: (X^T X Y - X^T M)_j, the Y part of E(.;0)
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double g = -b[a];
+#pragma unroll
+        for (int c = 0; c < K; ++c) g = fma(G[a * K + c], yn[c], g);
+        if (g < 0.0) st[ST_EG2] += g * g;
+        else st[ST_EC2] += (g * yn[a]) * (g * yn[a]);
+    }
+    st[ST_SOLVES] = r.solves;
+    st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
+    st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
+}
+
+// One wave's record: the sums over its 64 lanes of the statistics and of the
+// products xn_a xn_c (a >= c); lane q writes value q of each 64-value pass
+// (statistics to stat_out, the Gram matrix in both triangles to gram_out
+// unless it is null).  Called by all 64 lanes of the wave.
+// (a, c), a >= c, of entry idx of the packed lower triangle (row by row).
+__host__ __device__ constexpr int tri_row(int idx) {
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= idx) ++a;
+    return a;
+}
+__host__ __device__ constexpr int tri_col(int idx) { return idx - tri_row(idx) * (tri_row(idx) + 1) / 2; }
+
+template <int K>
+__device__ __forceinline__ void wave_stats_and_gram(const double (&st)[NST], const double (&xn)[K],
+                                                    double *stat_out, double *gram_out) {
+    constexpr int NG = K * (K + 1) / 2;
+    constexpr int V = NG + NST;
+    constexpr int NPASS = (V + YVALS - 1) / YVALS;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+        double v[YVALS];
+#pragma unroll
+        for (int q = 0; q < YVALS; ++q) {
+            const int idx = pass * YVALS + q;
+            if (idx < NG) v[q] = xn[tri_row(idx)] * xn[tri_col(idx)];
+            else if (idx < V) v[q] = st[idx - NG];
+            else v[q] = 0.0;
+        }
+        const double sum = wave_transpose_reduce(v, lane);
+        const int idx = pass * YVALS + lane;
+        if (idx < V) {
+            if (idx >= NG) {
+                stat_out[idx - NG] = sum;
+            } else if (gram_out) {
+                const int a = tri_row(idx), c = tri_col(idx);
+                gram_out[a * K + c] = sum;
+                gram_out[c * K + a] = sum;
+            }
+        }
+    }
+}
+
+// End of a sweep, in the block that finished last: the X and Y statistics
+// records, the E(.;0) parts and the stop rule of Sec. IV (mode 0), or only the
+// Y part for appended columns (mode 2).  All threads call it; scr holds
+// blockDim doubles of LDS.
+__device__ __forceinline__ void sweep_summary(const AnlsParams &p, double *scr) {
+    __shared__ double sx[NST], sy[NST];
+    reduce_records(p.xstat, p.Rx, NST, sx, scr);
+    reduce_records(p.ystat, p.Ry, NST, sy, scr);
+    if (threadIdx.x == 0 && p.mode == 2) {
+        // appended columns solved: Y part of E, counters; no sweep, no stop test
+        DevStatus *s = p.st;
+        s->ey_g2 = sy[ST_EG2];
+        s->ey_c2 = sy[ST_EC2];
+        s->E_cur = -1.0;
+        s->solves += sy[ST_SOLVES];
+        s->fails += sy[ST_FAILS];
+        s->changes += sy[ST_CHANGES];
+    } else if (threadIdx.x == 0) {
+        DevStatus *s = p.st;
+        const double step2 = sx[ST_STEP2] + sy[ST_STEP2];
+        const double norm2 = sx[ST_NORM2] + sy[ST_NORM2];
+        s->step2 = step2;
+        s->norm2 = norm2;
+        s->ex_g2 = sx[ST_EG2];
+        s->ex_c2 = sx[ST_EC2];
+        if (s->ey_g2 >= 0.0) {
+            const double eg = sqrt(sx[ST_EG2] + s->ey_g2);
+            const double ec = sqrt(sx[ST_EC2] + s->ey_c2);
+            s->E_prev = eg > ec ? eg : ec;
+        }
+        s->ey_g2_prev = s->ey_g2;
+        s->ey_c2_prev = s->ey_c2;
+        s->ey_g2 = sy[ST_EG2];
+        s->ey_c2 = sy[ST_EC2];
+        s->E_cur = -1.0;
+        s->solves += sx[ST_SOLVES] + sy[ST_SOLVES];
+        s->fails += sx[ST_FAILS] + sy[ST_FAILS];
+        s->changes += sx[ST_CHANGES] + sy[ST_CHANGES];
+        s->sweeps += 1;
+        if (sqrt(step2) <= s->eps_stol * (1.0 + sqrt(norm2)) || s->sweeps >= s->max_sweeps) s->converged = 1;
+    }
+}
+
+// LDS of the X stream: a chunk of Y while streaming, then the wave sums.
+template <int K>
+constexpr int xstream_lds() {
+    return (XCHUNK * K > SWAVES * K * XTILE) ? XCHUNK * K : SWAVES * K * XTILE;
+}
+
+// Streams the columns [j0, j1) of the tile's 64 rows of M against Y and
+// leaves each wave's partial sums of B_X in lds[(w * K + a) * XTILE + lane]
+// (ends with a barrier).  Every thread of the block calls it.
 template <int K, int P>
-__device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int split) {
-    if (p.mode == 0 && p.st->converged) return;
+__device__ __forceinline__ void xstream_sums(const AnlsParams &p, int tile, int64_t j0, int64_t j1, double *lds) {
     using T = typename MElem<P>::T;
-    constexpr int RED = SWAVES * K * XTILE;
-    constexpr int LDSN = (XCHUNK * K > RED) ? XCHUNK * K : RED;
-    __shared__ double lds[LDSN];   // Y chunk while streaming, then the wave sums
     T *ys = reinterpret_cast<T *>(lds);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = (int64_t)tile * XTILE + lane;
-    const int64_t j0 = (int64_t)split * p.xcols;
-    const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
     const bool row_ok = i < p.n;
 
     T acc[K];
@@ -153,7 +319,18 @@ __device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int 
 #pragma unroll
     for (int a = 0; a < K; ++a) lds[(w * K + a) * XTILE + lane] = (double)acc[a];
     __syncthreads();
-    if (w == 0 && row_ok) {
+}
+
+// X stream, one column split: partial sums of B_X for the split.
+template <int K, int P>
+__device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int split, double *lds) {
+    if (p.mode == 0 && p.st->converged) return;
+    const int64_t j0 = (int64_t)split * p.xcols;
+    const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
+    xstream_sums<K, P>(p, tile, j0, j1, lds);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)tile * XTILE + lane;
+    if (w == 0 && i < p.n) {
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             double v = lds[(0 * K + a) * XTILE + lane];
@@ -162,6 +339,42 @@ __device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int 
             p.bx_part[((int64_t)split * K + a) * p.ldX + i] = v;
         }
     }
+}
+
+// The whole X-half when the X stream has a single column split: the tile's 64
+// rows of B_X are complete after the stream, so the first wave solves them
+// (one row per lane) and writes the tile's statistics and G_X record (the
+// X-side records then number Rx = Tn).
+template <int K, int P>
+__device__ __forceinline__ void xfused_body(const AnlsParams &p, int tile, double *lds) {
+    if (p.mode == 0 && p.st->converged) return;
+    __shared__ double G[K * K];
+    __shared__ double scr[STHR];
+    reduce_records(p.gy_part, p.Ry, K * K, G, scr);
+    xstream_sums<K, P>(p, tile, 0, p.m, lds);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w != 0) return;
+    const int64_t i = (int64_t)tile * XTILE + lane;
+    const bool live = i < p.n;
+    double b[K], x[K], st[NST], xn[K];
+    uint32_t old_mask = 0u;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double v = lds[(0 * K + a) * XTILE + lane];
+#pragma unroll
+        for (int ww = 1; ww < SWAVES; ++ww) v += lds[(ww * K + a) * XTILE + lane];
+        b[a] = 0.0 + v;
+        x[a] = live ? p.X[(int64_t)a * p.ldX + i] : 0.0;
+        xn[a] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NST; ++q) st[q] = 0.0;
+    if (live) {
+        old_mask = p.xmask[i];
+        x_row<K>(p, G, i, x, b, old_mask, st, xn);
+    }
+    wave_stats_and_gram<K>(st, xn, p.xstat + (int64_t)tile * NST,
+                           p.mode == 0 ? p.gx_part + (int64_t)tile * K * K : nullptr);
 }
 
 template <int K>
@@ -200,61 +413,29 @@ __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
         }
     }
     if (p.mode == 0 && p.st->converged) return;
-    reduce_records(p.gy_part, p.By, K * K, G, lds);
+    reduce_records(p.gy_part, p.Ry, K * K, G, lds);
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
     double xn[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) xn[a] = 0.0;
-    if (live) {
-        double gmax = 0.0;
-#pragma unroll
-        for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
-        // graX at the old point: (X Y Y^T - M Y^T)_i
-#pragma unroll
-        for (int a = 0; a < K; ++a) {
-            double g = -b[a];
-#pragma unroll
-            for (int c = 0; c < K; ++c) g = fma(G[a * K + c], x[c], g);
-            if (g < 0.0) st[ST_EG2] += g * g;
-            else st[ST_EC2] += (g * x[a]) * (g * x[a]);
-        }
-        if (p.mode == 0) {
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                xn[a] = x[a];
-                st[ST_NORM2] += x[a] * x[a];
-            }
-            const LhResult r = lh_warm<K>(G, gmax, b, xn);
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                const double d = xn[a] - x[a];
-                st[ST_STEP2] += d * d;
-                p.X[(int64_t)a * p.ldX + i] = xn[a];
-            }
-            p.xmask[i] = r.P;
-            st[ST_SOLVES] = r.solves;
-            st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
-            st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
-        }
-    }
+    if (live) x_row<K>(p, G, i, x, b, old_mask, st, xn);
     block_stats_and_gram<K>(st, xn, p.xstat + (int64_t)bid * NST,
                             p.mode == 0 ? p.gx_part + (int64_t)bid * K * K : nullptr, lds);
 }
 
 // ---------------------------------------------------------------- Y-half
+// Streams the rows [r0, r1) of the tile's J = 64 / K columns of M against X
+// and leaves each wave's transpose-reduced sums in red[w * YVALS + lane]
+// (value jj * K + a is B_Y[a][jb + jj]); ends with a barrier.
 template <int K, int P>
-__device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int split) {
-    if (p.mode == 0 && p.st->converged) return;
+__device__ __forceinline__ void ystream_sums(const AnlsParams &p, int ct, int64_t r0, int64_t r1, double *red) {
     using T = typename MElem<P>::T;
     constexpr int J = YVALS / K;
-    __shared__ double red[SWAVES * YVALS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t jb = (int64_t)ct * J;
     const int nj = (int)min((int64_t)J, p.m - jb);
-    const int64_t r0 = (int64_t)split * p.yrows;
-    const int64_t r1 = min(r0 + (int64_t)p.yrows, p.n);
 
     T v[YVALS];
 #pragma unroll
@@ -274,6 +455,19 @@ __device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int sp
     }
     red[w * YVALS + lane] = (double)wave_transpose_reduce(v, lane);
     __syncthreads();
+}
+
+// Y stream, one row split: partial sums of B_Y for the split.
+template <int K, int P>
+__device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int split) {
+    if (p.mode == 0 && p.st->converged) return;
+    constexpr int J = YVALS / K;
+    __shared__ double red[SWAVES * YVALS];
+    const int64_t r0 = (int64_t)split * p.yrows;
+    const int64_t r1 = min(r0 + (int64_t)p.yrows, p.n);
+    ystream_sums<K, P>(p, ct, r0, r1, red);
+    const int64_t jb = (int64_t)ct * J;
+    const int nj = (int)min((int64_t)J, p.m - jb);
     if ((int)threadIdx.x < nj * K) {
         double s = red[threadIdx.x];
 #pragma unroll
@@ -281,6 +475,55 @@ __device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int sp
         const int jj = threadIdx.x / K, a = threadIdx.x - jj * K;
         p.by_part[((int64_t)split * K + a) * p.ldY + jb + jj] = s;
     }
+}
+
+// The whole Y-half when the Y stream has a single row split: the tile's J
+// columns of B_Y are complete after the stream, so the first wave solves them
+// (one column per lane), writes the tile's statistics and G_Y record (the
+// Y-side records then number Ry = Tm), and the tile that finishes last closes
+// the sweep.
+template <int K, int P>
+__device__ __forceinline__ void yfused_body(const AnlsParams &p, int ct) {
+    if (p.mode == 0 && p.st->converged) return;
+    constexpr int J = YVALS / K;
+    __shared__ double red[SWAVES * YVALS];
+    __shared__ double G[K * K];
+    __shared__ double scr[STHR];
+    __shared__ double bsum[YVALS];
+    __shared__ unsigned flag;
+    reduce_records(p.gx_part, p.Rx, K * K, G, scr);
+    ystream_sums<K, P>(p, ct, 0, p.n, red);
+    const int64_t jb = (int64_t)ct * J;
+    const int nj = (int)min((int64_t)J, p.m - jb);
+    if ((int)threadIdx.x < nj * K) {
+        double s = red[threadIdx.x];
+#pragma unroll
+        for (int ww = 1; ww < SWAVES; ++ww) s += red[ww * YVALS + threadIdx.x];
+        bsum[threadIdx.x] = s;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w == 0) {
+        const bool live = lane < nj;
+        const int64_t j = jb + lane;
+        double b[K], y[K], st[NST], yn[K];
+        uint32_t old_mask = 0u;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            b[a] = live ? 0.0 + bsum[lane * K + a] : 0.0;
+            y[a] = live ? p.Y[(int64_t)a * p.ldY + j] : 0.0;
+            yn[a] = 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NST; ++q) st[q] = 0.0;
+        if (live) {
+            old_mask = p.ymask[j];
+            y_col<K>(p, G, j, y, b, old_mask, st, yn);
+        }
+        wave_stats_and_gram<K>(st, yn, p.ystat + (int64_t)ct * NST, p.gy_part + (int64_t)ct * K * K);
+    }
+    if (!last_arrival(p.cnt_fin, (unsigned)p.Tm, &flag)) return;
+    sweep_summary(p, scr);
 }
 
 template <int K>
@@ -306,89 +549,33 @@ __device__ __forceinline__ void ynnls_body(const AnlsParams &p, int bid) {
         }
     }
     if (p.mode == 0 && p.st->converged) return;
-    reduce_records(p.gx_part, p.Bx, K * K, G, lds);
+    reduce_records(p.gx_part, p.Rx, K * K, G, lds);
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
     double yn[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) yn[a] = 0.0;
-    if (live) {
-        double gmax = 0.0;
-#pragma unroll
-        for (int a = 0; a < K; ++a) gmax = G[a * K + a] > gmax ? G[a * K + a] : gmax;
-#pragma unroll
-        for (int a = 0; a < K; ++a) {
-            yn[a] = y[a];
-            st[ST_NORM2] += y[a] * y[a];
-        }
-        const LhResult r = lh_warm<K>(G, gmax, b, yn);
-#pragma unroll
-        for (int a = 0; a < K; ++a) {
-            const double d = yn[a] - y[a];
-            st[ST_STEP2] += d * d;
-            p.Y[(int64_t)a * p.ldY + j] = yn[a];
-        }
-        p.ymask[j] = r.P;
-        // graY at the new point: (X^T X Y - X^T M)_j, the Y part of E(.;0)
-#pragma unroll
-        for (int a = 0; a < K; ++a) {
-            double g = -b[a];
-#pragma unroll
-            for (int c = 0; c < K; ++c) g = fma(G[a * K + c], yn[c], g);
-            if (g < 0.0) st[ST_EG2] += g * g;
-            else st[ST_EC2] += (g * yn[a]) * (g * yn[a]);
-        }
-        st[ST_SOLVES] = r.solves;
-        st[ST_FAILS] = r.status != 0 ? 1.0 : 0.0;
-        st[ST_CHANGES] = r.P != old_mask ? 1.0 : 0.0;
-    }
+    if (live) y_col<K>(p, G, j, y, b, old_mask, st, yn);
     block_stats_and_gram<K>(st, yn, p.ystat + (int64_t)bid * NST, p.gy_part + (int64_t)bid * K * K, lds);
     if (!last_arrival(p.cnt_fin, (unsigned)p.By, &flag)) return;
-
-    // ---- last block of the sweep: statistics and the Sec. IV stop rule
-    __shared__ double sx[NST], sy[NST];
-    reduce_records(p.xstat, p.Bx, NST, sx, lds);
-    reduce_records(p.ystat, p.By, NST, sy, lds);
-    if (threadIdx.x == 0 && p.mode == 2) {
-        // appended columns solved: Y part of E, counters; no sweep, no stop test
-        DevStatus *s = p.st;
-        s->ey_g2 = sy[ST_EG2];
-        s->ey_c2 = sy[ST_EC2];
-        s->E_cur = -1.0;
-        s->solves += sy[ST_SOLVES];
-        s->fails += sy[ST_FAILS];
-        s->changes += sy[ST_CHANGES];
-    } else if (threadIdx.x == 0) {
-        DevStatus *s = p.st;
-        const double step2 = sx[ST_STEP2] + sy[ST_STEP2];
-        const double norm2 = sx[ST_NORM2] + sy[ST_NORM2];
-        s->step2 = step2;
-        s->norm2 = norm2;
-        s->ex_g2 = sx[ST_EG2];
-        s->ex_c2 = sx[ST_EC2];
-        if (s->ey_g2 >= 0.0) {
-            const double eg = sqrt(sx[ST_EG2] + s->ey_g2);
-            const double ec = sqrt(sx[ST_EC2] + s->ey_c2);
-            s->E_prev = eg > ec ? eg : ec;
-        }
-        s->ey_g2_prev = s->ey_g2;
-        s->ey_c2_prev = s->ey_c2;
-        s->ey_g2 = sy[ST_EG2];
-        s->ey_c2 = sy[ST_EC2];
-        s->E_cur = -1.0;
-        s->solves += sx[ST_SOLVES] + sy[ST_SOLVES];
-        s->fails += sx[ST_FAILS] + sy[ST_FAILS];
-        s->changes += sx[ST_CHANGES] + sy[ST_CHANGES];
-        s->sweeps += 1;
-        if (sqrt(step2) <= s->eps_stol * (1.0 + sqrt(norm2)) || s->sweeps >= s->max_sweeps) s->converged = 1;
-    }
+    sweep_summary(p, lds);
 }
 
 // ---------------------------------------------------------------- kernels
 // One problem: the grid is the problem's own launch shape.
 template <int K, int P>
-__global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) { xstream_body<K, P>(p, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) {
+    __shared__ double lds[xstream_lds<K>()];
+    xstream_body<K, P>(p, blockIdx.x, blockIdx.y, lds);
+}
+template <int K, int P>
+__global__ __launch_bounds__(STHR) void k_xfused(AnlsParams p) {
+    __shared__ double lds[xstream_lds<K>()];
+    xfused_body<K, P>(p, blockIdx.x, lds);
+}
+template <int K, int P>
+__global__ __launch_bounds__(STHR) void k_yfused(AnlsParams p) { yfused_body<K, P>(p, blockIdx.x); }
 template <int K>
 __global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) { xnnls_body<K>(p, blockIdx.x); }
 template <int K, int P>
@@ -414,7 +601,9 @@ __global__ __launch_bounds__(STHR) void kb_xstream(const AnlsParams *tab, const 
     const int q = batch_problem(off, np, blockIdx.x);
     const AnlsParams p = tab[q];
     const int local = blockIdx.x - off[q];
-    xstream_body<K, P>(p, local % p.Tn, local / p.Tn);
+    __shared__ double lds[xstream_lds<K>()];
+    if (p.Sx == 1) xfused_body<K, P>(p, local, lds);
+    else xstream_body<K, P>(p, local % p.Tn, local / p.Tn, lds);
 }
 template <int K>
 __global__ __launch_bounds__(NTHR) void kb_xnnls(const AnlsParams *tab, const int *off, int np) {
@@ -427,7 +616,8 @@ __global__ __launch_bounds__(STHR) void kb_ystream(const AnlsParams *tab, const 
     const int q = batch_problem(off, np, blockIdx.x);
     const AnlsParams p = tab[q];
     const int local = blockIdx.x - off[q];
-    ystream_body<K, P>(p, local % p.Tm, local / p.Tm);
+    if (p.Sy == 1) yfused_body<K, P>(p, local);
+    else ystream_body<K, P>(p, local % p.Tm, local / p.Tm);
 }
 template <int K>
 __global__ __launch_bounds__(NTHR) void kb_ynnls(const AnlsParams *tab, const int *off, int np) {
@@ -442,7 +632,7 @@ template <int K>
 __global__ __launch_bounds__(NTHR) void k_measure_finish(AnlsParams p) {
     __shared__ double sx[NST];
     __shared__ double scr[NTHR];
-    reduce_records(p.xstat, p.Bx, NST, sx, scr);
+    reduce_records(p.xstat, p.Rx, NST, sx, scr);
     if (threadIdx.x == 0) {
         DevStatus *st = p.st;
         const double yg = st->ey_g2 >= 0.0 ? st->ey_g2 : 0.0;
@@ -453,13 +643,16 @@ __global__ __launch_bounds__(NTHR) void k_measure_finish(AnlsParams p) {
     }
 }
 
-// G_Y block partials from the current Y, in the k_ynnls block layout.
+// G_Y records from the current Y, Ry of them (block b covers ceil(m / Ry)
+// <= 256 columns), as the Y-half writes them.
 template <int K>
 __global__ __launch_bounds__(NTHR) void k_gram_y_init(AnlsParams p) {
     __shared__ double ys[NTHR * K];
-    const int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    const int64_t per = (p.m + p.Ry - 1) / p.Ry;
+    const int64_t j = (int64_t)blockIdx.x * per + threadIdx.x;
+    const bool on = threadIdx.x < per && j < p.m;
 #pragma unroll
-    for (int a = 0; a < K; ++a) ys[threadIdx.x * K + a] = j < p.m ? p.Y[(int64_t)a * p.ldY + j] : 0.0;
+    for (int a = 0; a < K; ++a) ys[threadIdx.x * K + a] = on ? p.Y[(int64_t)a * p.ldY + j] : 0.0;
     __syncthreads();
     for (int q = threadIdx.x; q < K * K; q += NTHR) {
         const int a = q / K, c = q - a * K;
@@ -469,13 +662,16 @@ __global__ __launch_bounds__(NTHR) void k_gram_y_init(AnlsParams p) {
     }
 }
 
-// G_X block partials from the current X, in the k_xnnls block layout.
+// G_X records from the current X, Rx of them (block b covers ceil(n / Rx)
+// <= 256 rows), as the X-half writes them.
 template <int K>
 __global__ __launch_bounds__(NTHR) void k_gram_x_init(AnlsParams p) {
     __shared__ double xs[NTHR * K];
-    const int64_t i = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    const int64_t per = (p.n + p.Rx - 1) / p.Rx;
+    const int64_t i = (int64_t)blockIdx.x * per + threadIdx.x;
+    const bool on = threadIdx.x < per && i < p.n;
 #pragma unroll
-    for (int a = 0; a < K; ++a) xs[threadIdx.x * K + a] = i < p.n ? p.X[(int64_t)a * p.ldX + i] : 0.0;
+    for (int a = 0; a < K; ++a) xs[threadIdx.x * K + a] = on ? p.X[(int64_t)a * p.ldX + i] : 0.0;
     __syncthreads();
     for (int q = threadIdx.x; q < K * K; q += NTHR) {
         const int a = q / K, c = q - a * K;
@@ -662,6 +858,17 @@ __global__ void k_batch_poll(const AnlsParams *table, int count, long long *out)
 int yhalf_cols(int K) { return K >= 1 && K <= KMAX ? YVALS / K : 0; }
 
 hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s) {
+    if (p.Sx == 1) {   // stream and solve in one kernel
+        const dim3 g(p.Tn);
+        if (p.prec == NMF_GRAM_FP32) {
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xfused<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
+        } else if (p.prec == NMF_GRAM_BF16X2) {
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xfused<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, p));
+        } else {
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xfused<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, p));
+        }
+        return hipGetLastError();
+    }
     const dim3 g(p.Tn, p.Sx);
     if (p.prec == NMF_GRAM_FP32) {
         NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xstream<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
@@ -674,11 +881,23 @@ hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s) {
 }
 
 hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s) {
+    if (p.Sx == 1) return hipSuccess;   // solved inside k_xfused
     NMF_K_SWITCH(K, hipLaunchKernelGGL(k_xnnls<KK>, dim3(p.Bx), dim3(NTHR), 0, s, p));
     return hipGetLastError();
 }
 
 hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s) {
+    if (p.Sy == 1) {   // stream and solve in one kernel
+        const dim3 g(p.Tm);
+        if (p.prec == NMF_GRAM_FP32) {
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_yfused<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
+        } else if (p.prec == NMF_GRAM_BF16X2) {
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_yfused<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, p));
+        } else {
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_yfused<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, p));
+        }
+        return hipGetLastError();
+    }
     const dim3 g(p.Tm, p.Sy);
     if (p.prec == NMF_GRAM_FP32) {
         NMF_K_SWITCH(K, hipLaunchKernelGGL((k_ystream<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
@@ -691,6 +910,7 @@ hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s) {
 }
 
 hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s) {
+    if (p.Sy == 1) return hipSuccess;   // solved inside k_yfused
     NMF_K_SWITCH(K, hipLaunchKernelGGL(k_ynnls<KK>, dim3(p.By), dim3(NTHR), 0, s, p));
     return hipGetLastError();
 }
@@ -720,7 +940,8 @@ hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t 
     } else {
         NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_xstream<KK, NMF_GRAM_FP64>), dim3(g.blocks[0]), dim3(STHR), 0, s, t, o, np));
     }
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_xnnls<KK>, dim3(g.blocks[1]), dim3(NTHR), 0, s, t, o + (np + 1), np));
+    if (g.blocks[1] > 0)
+        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_xnnls<KK>, dim3(g.blocks[1]), dim3(NTHR), 0, s, t, o + (np + 1), np));
     if (prec == NMF_GRAM_FP32) {
         NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_ystream<KK, NMF_GRAM_FP32>), dim3(g.blocks[2]), dim3(STHR), 0, s, t, o + 2 * (np + 1), np));
     } else if (prec == NMF_GRAM_BF16X2) {
@@ -728,7 +949,8 @@ hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t 
     } else {
         NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_ystream<KK, NMF_GRAM_FP64>), dim3(g.blocks[2]), dim3(STHR), 0, s, t, o + 2 * (np + 1), np));
     }
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_ynnls<KK>, dim3(g.blocks[3]), dim3(NTHR), 0, s, t, o + 3 * (np + 1), np));
+    if (g.blocks[3] > 0)
+        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_ynnls<KK>, dim3(g.blocks[3]), dim3(NTHR), 0, s, t, o + 3 * (np + 1), np));
     return hipGetLastError();
 }
 
@@ -738,12 +960,12 @@ hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s) {
 }
 
 hipError_t launch_gram_y_init(int K, const AnlsParams &p, hipStream_t s) {
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_y_init<KK>, dim3(p.By), dim3(NTHR), 0, s, p));
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_y_init<KK>, dim3(p.Ry), dim3(NTHR), 0, s, p));
     return hipGetLastError();
 }
 
 hipError_t launch_gram_x_init(int K, const AnlsParams &p, hipStream_t s) {
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_x_init<KK>, dim3(p.Bx), dim3(NTHR), 0, s, p));
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_gram_x_init<KK>, dim3(p.Rx), dim3(NTHR), 0, s, p));
     return hipGetLastError();
 }
 

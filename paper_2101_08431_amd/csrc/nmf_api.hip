@@ -35,7 +35,8 @@ struct Plan {
 // Stage-1 launch shape.  X stream: 64-row tiles, column splits so that about
 // 4096 waves stream M (8 per block).  Y stream: J = 64/K columns per tile, row
 // splits while every thread still covers >= 1 row and the grid is short of
-// ~4096 waves.  NNLS kernels: 256 problems per block.
+// ~4096 waves.  A single split makes the half one kernel that streams and
+// solves (chosen for matrices of at most 2^18 entries, or by the caller).  NNLS kernels: 256 problems per block.
 Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, int y_splits = 0) {
     Plan P;
     P.ldM = align_up((size_t)n, 32);
@@ -43,6 +44,7 @@ Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, in
     P.ldY = align_up((size_t)m_cap, 64);
     P.Tn = (int)ceil_div(n, nmfk::XTILE);
     int64_t sx = ceil_div(4096, (int64_t)P.Tn * nmfk::SWAVES);
+    if (n * m <= (int64_t)1 << 18) sx = 1;   // small: stream and solve in one kernel per half
     if (x_splits > 0) sx = x_splits;
     sx = std::max<int64_t>(1, std::min<int64_t>(sx, std::min<int64_t>(kSxMax, m)));
     P.xcols = (int)ceil_div(m, sx);
@@ -50,6 +52,7 @@ Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, in
     P.J = nmfk::yhalf_cols(K);
     P.Tm = (int)ceil_div(m, P.J);
     int64_t sy = std::min<int64_t>(ceil_div(4096, (int64_t)P.Tm * nmfk::SWAVES), n / nmfk::STHR);
+    if (n * m <= (int64_t)1 << 18) sy = 1;
     if (y_splits > 0) sy = y_splits;
     sy = std::max<int64_t>(1, std::min<int64_t>(sy, std::min<int64_t>(kSyMax, n)));
     P.yrows = (int)ceil_div(n, sy);
@@ -87,10 +90,14 @@ Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
     L.ymask = c.take<uint32_t>(P.ldY);
     L.bx = c.take<double>((size_t)kSxMax * K * P.ldX);
     L.by = c.take<double>((size_t)kSyMax * K * P.ldY);   // Sy varies with m; <= kSyMax
-    L.gx = c.take<double>((size_t)P.Bx * K * K);
-    L.gy = c.take<double>((size_t)ByMax * K * K);
-    L.xst = c.take<double>((size_t)P.Bx * nmfk::NST);
-    L.yst = c.take<double>((size_t)ByMax * nmfk::NST);
+    // statistics / Gram records: one per NNLS block, or one per stream tile
+    // when a half runs as one kernel (Tn >= Bx rows, Tm >= By columns)
+    const int64_t TmMax = ceil_div(m_cap, nmfk::yhalf_cols(K));
+    const int64_t RxMax = std::max<int64_t>(P.Bx, P.Tn), RyMax = std::max<int64_t>(ByMax, TmMax);
+    L.gx = c.take<double>((size_t)RxMax * K * K);
+    L.gy = c.take<double>((size_t)RyMax * K * K);
+    L.xst = c.take<double>((size_t)RxMax * nmfk::NST);
+    L.yst = c.take<double>((size_t)RyMax * nmfk::NST);
     L.cntf = c.take<unsigned>(4);
     L.status = c.take<DevStatus>(1);
     L.red = c.take<double>(2 * kRedBlocks);
@@ -154,6 +161,8 @@ static void refresh_shape(nmf_ctx *c) {
     p.yrows = c->plan.yrows;
     p.Bx = c->plan.Bx;
     p.By = c->plan.By;
+    p.Rx = p.Sx == 1 ? p.Tn : p.Bx;
+    p.Ry = p.Sy == 1 ? p.Tm : p.By;
 }
 
 extern "C" {
@@ -545,6 +554,13 @@ nmf_status nmf_set_launch_shape(nmf_ctx *c, int32_t xs, int32_t ys) {
     c->opt.x_splits = xs;
     c->opt.y_splits = ys;
     refresh_shape(c);
+    if (c->stage == 1) {
+        // the record layouts of the Gram partials follow the launch shape:
+        // rebuild them from the current factors
+        HIPCHK(c, nmfk::launch_gram_x_init(c->K, c->p, c->stream));
+        HIPCHK(c, nmfk::launch_gram_y_init(c->K, c->p, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     return NMF_OK;
 }
 
@@ -735,7 +751,7 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
             tab.push_back(p);
             b->order.push_back(q);
             g.g.single = p;
-            const int cnt[4] = {p.Tn * p.Sx, p.Bx, p.Tm * p.Sy, p.By};
+            const int cnt[4] = {p.Tn * p.Sx, p.Sx == 1 ? 0 : p.Bx, p.Tm * p.Sy, p.Sy == 1 ? 0 : p.By};
             for (int k = 0; k < 4; ++k) o[k].push_back(o[k].back() + cnt[k]);
         }
         for (int k = 0; k < 4; ++k) {

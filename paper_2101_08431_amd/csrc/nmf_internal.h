@@ -43,7 +43,9 @@ struct DevStatus {
 
 // Parameters of the stage-1 kernels.  One sweep = k_xstream, k_xnnls,
 // k_ystream, k_ynnls; every hand-over between blocks crosses a kernel
-// boundary except the sweep summary at the end of k_ynnls.
+// boundary except the sweep summary at the end of k_ynnls.  A half whose
+// stream has a single split (Sx == 1, Sy == 1) runs as one kernel instead
+// (k_xfused, k_yfused) that streams and solves its tile.
 struct AnlsParams {
     int64_t n, m, ldM, ldX, ldY;
     const double *M;
@@ -62,6 +64,8 @@ struct AnlsParams {
     int Sx, Tn, xcols; // X stream: Tn row tiles x Sx column splits of xcols columns
     int Sy, Tm, yrows; // Y stream: Tm column tiles x Sy row splits of yrows rows
     int Bx, By;        // NNLS blocks: ceil(n / 256), ceil(m / 256)
+    int Rx, Ry;        // statistics / Gram records of the X- and Y-half: Bx and By, or Tn
+                       // (Sx == 1) and Tm (Sy == 1) when the stream kernel also solves
     int mode;          // X: 0 = solve, 1 = measure E only; Y: 0 = sweep, 2 = appended columns
 };
 

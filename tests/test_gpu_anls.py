@@ -57,6 +57,26 @@ def test_ragged_shapes_match_oracle(orc, n, m, k):
     assert rel_err(X, Y, ref["X"], ref["Yt"]) <= REL
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (1, 3), (8, 1), (8, 3), (64, 64)])
+def test_launch_shapes_match_oracle(orc, shape):
+    # one kernel per half (a single split) or split stream + NNLS kernels, on a
+    # ragged size with several tiles; every shape reaches the oracle's iterates
+    n, m, k = 1100, 230, 5
+    print(f"case launch shape {shape} n={n} m={m} k={k}", flush=True)
+    M, X0, Y0 = synth.make(spec(n, m, k, 1e-3, True), 12)
+    ctx = gpu_ctx(M, k, X0, Y0, x_splits=shape[0], y_splits=shape[1])
+    ctx.anls_step(6)
+    X, Y = ctx.factors()
+    ref = orc.anls(M, X0, Y0.T.copy(), exact_sweeps=6)
+    assert rel_err(X, Y, ref["X"], ref["Yt"]) <= REL
+    # switching the shape in the middle of a run keeps the iterates
+    ctx.set_launch_shape(shape[1], shape[0])
+    ctx.anls_step(3)
+    X, Y = ctx.factors()
+    ref = orc.anls(M, X0, Y0.T.copy(), exact_sweeps=9)
+    assert rel_err(X, Y, ref["X"], ref["Yt"]) <= REL
+
+
 def test_full_size_3000x500x5(orc):
     print("case pdf_3000x500_k5 seed 0 sweeps 10", flush=True)
     M, X0, Y0 = synth.make("pdf_3000x500_k5", 0)
