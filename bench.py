@@ -100,7 +100,31 @@ def time_eager_sweeps(ctx, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def roofline(ctx, n, m, k, shape, sweeps=100):
+def measured_traffic(kernel, shape, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE and WRITE_SIZE scaled by a plain copy
+    of known size), or None when there is none for this launch shape or the
+    stage-1 kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    src = os.path.join(ROOT, "paper_2101_08431_amd", "csrc", "anls.hip")
+    try:
+        lines = open(path).read().splitlines()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    recorded = [ln.split()[2] for ln in lines if ln.startswith("source_sha256 anls.hip ")]
+    if not recorded or recorded[0] != digest:
+        return None
+    want = f"{shape[0]},{shape[1]}"
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 4 and f[0] == "traffic" and f[1] == kernel and f[2] == want:
+            return float(f[3])
+    return None
+
+
+def roofline(ctx, n, m, k, shape, workload, sweeps=100):
     """Per-kernel device times from the library's event profiler and the
     algorithmic bytes of each kernel; a half with a single split runs as one
     kernel (k_xfused / k_yfused) that moves the bytes of both of its steps."""
@@ -119,8 +143,8 @@ def roofline(ctx, n, m, k, shape, sweeps=100):
     dom = max(per, key=lambda q: per[q]["ms"])
     ach = per[dom]["GBs"]
     return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": per[dom]["bytes"],
-            "per_kernel": per}
+            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(dom, shape, workload),
+            "bytes_per_launch": per[dom]["bytes"], "launch_shape": list(shape), "per_kernel": per}
 
 
 def full_solve(name, seeds, tol, cap):
@@ -297,6 +321,8 @@ def main():
     ap.add_argument("--no-layers", action="store_true", help="skip the precision and batching sections")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving arrival trace")
+    ap.add_argument("--shape", default=None, metavar="XS,YS",
+                    help="fix the stage-1 launch shape (x splits, y splits) instead of autotuning it")
     ap.add_argument("--ipm-only", action="store_true",
                     help="only time stage-2 iterations on the headline workload (for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -327,15 +353,20 @@ def main():
     k = X0.shape[1]
     ctx = make_ctx(M, X0, Y0, k)
     from paper_2101_08431_amd import autotune
-    shape = autotune.tune_single(ctx, use_cache=False)
-    log(f"autotuned launch shape (x splits, y splits) = {shape}; fastest: "
-        + ", ".join(f"{kk}: {v * 1e3:.1f} us" for kk, v in list(autotune.last_timings.items())[:6]))
+    if args.shape:
+        shape = tuple(int(v) for v in args.shape.split(","))
+        ctx.set_launch_shape(*shape)
+        log(f"launch shape (x splits, y splits) = {shape}, fixed")
+    else:
+        shape = autotune.tune_single(ctx, use_cache=False)
+        log(f"autotuned launch shape (x splits, y splits) = {shape}; fastest: "
+            + ", ".join(f"{kk}: {v * 1e3:.1f} us" for kk, v in list(autotune.last_timings.items())[:6]))
     ms_graph, wall_ms = time_graph_sweeps(ctx, args.steps, args.warmup)
     ms_eager = time_eager_sweeps(ctx, args.steps, args.warmup)
     mode = "graph" if ms_graph <= ms_eager else "eager"
     ms_step = min(ms_graph, ms_eager)
     value = (n + m) / (ms_step * 1e-3)
-    rl = roofline(ctx, n, m, k, shape)
+    rl = roofline(ctx, n, m, k, shape, args.workload)
     _, rep = ctx.anls_step(0)
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,

@@ -171,12 +171,13 @@ nmf_status nmf_get_masks(nmf_ctx *ctx, uint32_t *xmask, uint32_t *ymask);
  * Synchronises. */
 nmf_status nmf_get_report(nmf_ctx *ctx, nmf_report *report);
 
-/* Profiling: enqueues `sweeps` stage-1 sweeps like nmf_anls_step() with a
- * pair of HIP events around every kernel, synchronises, and writes the mean
- * device time in milliseconds of the four stage-1 kernels to ms[0..3]: the
- * X-half stream (B_X = M Y^T), the row NNLS, the Y-half stream (B_Y = X^T M)
- * and the column NNLS.  Sweeps after the stop rule holds return at once and
- * are still counted. */
+/* Profiling: enqueues `sweeps` stage-1 sweeps like nmf_anls_step() with HIP
+ * events recorded by every kernel's own dispatch, synchronises, and writes
+ * the mean device time in milliseconds of the four stage-1 steps to
+ * ms[0..3]: the X-half stream (B_X = M Y^T), the row NNLS, the Y-half stream
+ * (B_Y = X^T M) and the column NNLS.  A half with a single split is one
+ * kernel: its time is in the stream entry and its NNLS entry is 0.  Sweeps
+ * after the stop rule holds return at once and are still counted. */
 nmf_status nmf_anls_profile(nmf_ctx *ctx, int32_t sweeps, double *ms);
 
 /* Re-plans the stage-1 launch shape of a context: column splits of the X-half

@@ -19,6 +19,7 @@
 // All hand-overs between blocks cross a kernel boundary, except the sweep
 // summary in k_ynnls (ceil(m/256) blocks).  Every sum runs in a fixed order,
 // so results are bitwise reproducible.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -298,15 +299,17 @@ __device__ __forceinline__ void xstream_sums(const AnlsParams &p, int tile, int6
         }
         __syncthreads();
         const int64_t base = c0 * p.ldM + (row_ok ? i : 0);
-        for (int jb = w; jb < nc; jb += 8 * SWAVES) {
-            T mv[8];
+        // loads in flight per lane: 8 columns of 8-byte, 16 of 4-byte elements
+        constexpr int NL = sizeof(T) == 8 && P == NMF_GRAM_FP64 ? 8 : 16;
+        for (int jb = w; jb < nc; jb += NL * SWAVES) {
+            T mv[NL];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < NL; ++t) {
                 const int jj = jb + t * SWAVES;
                 mv[t] = (jj < nc && row_ok) ? MElem<P>::load(p, base + (int64_t)jj * p.ldM) : T(0);
             }
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < NL; ++t) {
                 const int jj = jb + t * SWAVES;
                 if (jj < nc) {
 #pragma unroll
@@ -857,61 +860,61 @@ __global__ void k_batch_poll(const AnlsParams *table, int count, long long *out)
 
 int yhalf_cols(int K) { return K >= 1 && K <= KMAX ? YVALS / K : 0; }
 
-hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s) {
+hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (p.Sx == 1) {   // stream and solve in one kernel
         const dim3 g(p.Tn);
         if (p.prec == NMF_GRAM_FP32) {
-            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xfused<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
+            NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_xfused<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, e0, e1, 0, p));
         } else if (p.prec == NMF_GRAM_BF16X2) {
-            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xfused<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, p));
+            NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_xfused<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, e0, e1, 0, p));
         } else {
-            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xfused<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, p));
+            NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_xfused<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, e0, e1, 0, p));
         }
         return hipGetLastError();
     }
     const dim3 g(p.Tn, p.Sx);
     if (p.prec == NMF_GRAM_FP32) {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xstream<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
+        NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_xstream<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, e0, e1, 0, p));
     } else if (p.prec == NMF_GRAM_BF16X2) {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xstream<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, p));
+        NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_xstream<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, e0, e1, 0, p));
     } else {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_xstream<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, p));
+        NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_xstream<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, e0, e1, 0, p));
     }
     return hipGetLastError();
 }
 
-hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s) {
+hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (p.Sx == 1) return hipSuccess;   // solved inside k_xfused
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_xnnls<KK>, dim3(p.Bx), dim3(NTHR), 0, s, p));
+    NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_xnnls<KK>, dim3(p.Bx), dim3(NTHR), 0, s, e0, e1, 0, p));
     return hipGetLastError();
 }
 
-hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s) {
+hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (p.Sy == 1) {   // stream and solve in one kernel
         const dim3 g(p.Tm);
         if (p.prec == NMF_GRAM_FP32) {
-            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_yfused<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
+            NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_yfused<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, e0, e1, 0, p));
         } else if (p.prec == NMF_GRAM_BF16X2) {
-            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_yfused<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, p));
+            NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_yfused<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, e0, e1, 0, p));
         } else {
-            NMF_K_SWITCH(K, hipLaunchKernelGGL((k_yfused<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, p));
+            NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_yfused<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, e0, e1, 0, p));
         }
         return hipGetLastError();
     }
     const dim3 g(p.Tm, p.Sy);
     if (p.prec == NMF_GRAM_FP32) {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_ystream<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, p));
+        NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_ystream<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, e0, e1, 0, p));
     } else if (p.prec == NMF_GRAM_BF16X2) {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_ystream<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, p));
+        NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_ystream<KK, NMF_GRAM_BF16X2>), g, dim3(STHR), 0, s, e0, e1, 0, p));
     } else {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((k_ystream<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, p));
+        NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_ystream<KK, NMF_GRAM_FP64>), g, dim3(STHR), 0, s, e0, e1, 0, p));
     }
     return hipGetLastError();
 }
 
-hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s) {
+hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (p.Sy == 1) return hipSuccess;   // solved inside k_yfused
-    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_ynnls<KK>, dim3(p.By), dim3(NTHR), 0, s, p));
+    NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_ynnls<KK>, dim3(p.By), dim3(NTHR), 0, s, e0, e1, 0, p));
     return hipGetLastError();
 }
 

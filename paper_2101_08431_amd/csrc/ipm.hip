@@ -850,52 +850,54 @@ __global__ __launch_bounds__(256) void k_chol_diag(double *S, int64_t ldS, int64
     if (threadIdx.x == 0 && bad) sc->chol_fail = 1;
 }
 
-// Panel below a full diagonal block: L[r, k0:k0+CB) = S[r, k0:k0+CB) L_kk^-T,
-// one row per thread, solved left to right with every later entry updated at
-// once; L_kk and 1 / diag are read from LDS.  The block's rows are also
-// stored transposed into the upper triangle, S[r * ldS + k0 + q] =
-// L[r][k0 + q], staged through LDS so that each wave writes one contiguous
-// row; the backward triangular solve reads them there.
+// Panel below a full diagonal block: L[r, k0:k0+CB) = S[r, k0:k0+CB) L_kk^-T.
+// Four lanes share a row, each owning 16 of its 64 entries; step q: the owner
+// of entry q scales it by 1 / L_qq, the quad shares it, and every lane updates
+// its own later entries.  L_kk and 1 / diag are read from LDS.  The block's
+// rows are also stored transposed into the upper triangle, S[r * ldS + k0 +
+// q] = L[r][k0 + q], so that the backward triangular solve reads them
+// coalesced.
+constexpr int PROWS = 64;   // rows per panel block (4 lanes each)
 __global__ __launch_bounds__(256) void k_chol_panel(double *S, int64_t ldS, int64_t N, int64_t k0,
                                                   const double *invd) {
-    __shared__ double Lk[CB * CB];   // Lk[q * CB + j] = L[k0 + j][k0 + q], j > q
+    __shared__ double Lk[CB * CB];          // Lk[q * CB + j] = L[k0 + j][k0 + q], j > q
     __shared__ double id[CB];
-    __shared__ double T[CB * 129];   // T[q * 129 + t] = L[row of thread t][k0 + q], half a block at a time
+    __shared__ double T[CB * (PROWS + 1)];  // T[q * (PROWS + 1) + rr] = L[base + rr][k0 + q]
     for (int t = threadIdx.x; t < CB * CB; t += 256) {
         const int j = t % CB, q = t / CB;
         Lk[t] = (j > q) ? S[(k0 + q) * ldS + k0 + j] : 0.0;
     }
     if (threadIdx.x < CB) id[threadIdx.x] = invd[k0 + threadIdx.x];
     __syncthreads();
-    const int64_t base = k0 + CB + (int64_t)blockIdx.x * 256;
-    const int64_t r = base + threadIdx.x;
-    double x[CB];
-    if (r < N) {
+    const int rr = threadIdx.x >> 2, part = threadIdx.x & 3;
+    const int lane = threadIdx.x & 63;
+    const int64_t base = k0 + CB + (int64_t)blockIdx.x * PROWS;
+    const int64_t r = base + rr;
+    const bool live = r < N;
+    double x[16];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) x[q] = S[(k0 + q) * ldS + r];
+    for (int u = 0; u < 16; ++u) x[u] = live ? S[(k0 + 16 * part + u) * ldS + r] : 0.0;
 #pragma unroll
-        for (int q = 0; q < CB; ++q) {
-            x[q] *= id[q];
+    for (int q = 0; q < CB; ++q) {
+        const int owner = q >> 4, u = q & 15;
+        if (part == owner) x[u] *= id[q];
+        const double xq = __shfl(x[u], (lane & ~3) | owner, 64);
 #pragma unroll
-            for (int j = q + 1; j < CB; ++j) x[j] = fma(-x[q], Lk[q * CB + j], x[j]);
+        for (int v = 0; v < 16; ++v) {
+            const int j = 16 * part + v;
+            if (j > q) x[v] = fma(-xq, Lk[q * CB + j], x[v]);
         }
-#pragma unroll
-        for (int q = 0; q < CB; ++q) S[(k0 + q) * ldS + r] = x[q];
     }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        __syncthreads();
-        const int t = (int)threadIdx.x - 128 * half;
-        if (t >= 0 && t < 128 && r < N) {
-#pragma unroll
-            for (int q = 0; q < CB; ++q) T[q * 129 + t] = x[q];
-        }
-        __syncthreads();
-        for (int rr = w; rr < 128; rr += 4) {
-            const int64_t r2 = base + 128 * half + rr;
-            if (r2 < N) S[r2 * ldS + k0 + lane] = T[lane * 129 + rr];
-        }
+    for (int u = 0; u < 16; ++u) {
+        if (live) S[(k0 + 16 * part + u) * ldS + r] = x[u];
+        T[(16 * part + u) * (PROWS + 1) + rr] = x[u];
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    for (int r2 = w; r2 < PROWS; r2 += 4) {
+        const int64_t rg = base + r2;
+        if (rg < N) S[rg * ldS + k0 + lane] = T[lane * (PROWS + 1) + r2];
     }
 }
 
@@ -1349,8 +1351,8 @@ nmf_status cholesky(Ctx &c, int64_t N) {
         hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, c.st, S, ldS, N, k0, c.s.invd, c.s.sc);
         const int64_t below = N - k0 - CB;
         if (below > 0) {
-            hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((below + 255) / 256)), dim3(256), 0, c.st, S, ldS, N,
-                               k0, (const double *)c.s.invd);
+            hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((below + PROWS - 1) / PROWS)), dim3(256), 0, c.st, S,
+                               ldS, N, k0, (const double *)c.s.invd);
             const int64_t nt = (below + CB - 1) / CB;
             hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, c.st, S, ldS, N, k0);
         }

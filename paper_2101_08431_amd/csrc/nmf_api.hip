@@ -456,20 +456,21 @@ nmf_status nmf_anls_profile(nmf_ctx *c, int32_t sweeps, double *ms) {
     }
     AnlsParams p = c->p;
     p.mode = 0;
+    // the events are recorded by each kernel's own dispatch (no extra packets)
+    const bool live[4] = {true, p.Sx != 1, true, p.Sy != 1};
     for (int t = 0; st == NMF_OK && t < sweeps; ++t) {
         hipEvent_t *e = &ev[8 * (size_t)t];
-        bool ok = hipEventRecord(e[0], c->stream) == hipSuccess && nmfk::launch_xstream(c->K, p, c->stream) == hipSuccess &&
-                  hipEventRecord(e[1], c->stream) == hipSuccess && hipEventRecord(e[2], c->stream) == hipSuccess &&
-                  nmfk::launch_xnnls(c->K, p, c->stream) == hipSuccess && hipEventRecord(e[3], c->stream) == hipSuccess &&
-                  hipEventRecord(e[4], c->stream) == hipSuccess && nmfk::launch_ystream(c->K, p, c->stream) == hipSuccess &&
-                  hipEventRecord(e[5], c->stream) == hipSuccess && hipEventRecord(e[6], c->stream) == hipSuccess &&
-                  nmfk::launch_ynnls(c->K, p, c->stream) == hipSuccess && hipEventRecord(e[7], c->stream) == hipSuccess;
+        bool ok = nmfk::launch_xstream(c->K, p, c->stream, e[0], e[1]) == hipSuccess &&
+                  nmfk::launch_xnnls(c->K, p, c->stream, e[2], e[3]) == hipSuccess &&
+                  nmfk::launch_ystream(c->K, p, c->stream, e[4], e[5]) == hipSuccess &&
+                  nmfk::launch_ynnls(c->K, p, c->stream, e[6], e[7]) == hipSuccess;
         if (!ok) st = fail(c, NMF_EDEVICE, "launch failed");
     }
     double sum[4] = {0, 0, 0, 0};
     if (st == NMF_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, NMF_EDEVICE, "sync failed");
     for (int t = 0; st == NMF_OK && t < sweeps; ++t) {
         for (int k = 0; k < 4; ++k) {
+            if (!live[k]) continue;
             float a = 0.f;
             if (hipEventElapsedTime(&a, ev[8 * (size_t)t + 2 * k], ev[8 * (size_t)t + 2 * k + 1]) != hipSuccess) {
                 st = fail(c, NMF_EDEVICE, "hipEventElapsedTime failed");

@@ -72,10 +72,18 @@ struct AnlsParams {
 // Launchers (anls.hip).  All enqueue on `s` and return hipSuccess or an error.
 hipError_t launch_xhalf(int K, const AnlsParams &p, hipStream_t s);   // k_xstream + k_xnnls
 hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s);   // k_ystream + k_ynnls
-hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s);
-hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s);
-hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s);
-hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s);
+// The four stage-1 steps; e0 / e1 (may be null) are recorded by the dispatch
+// itself at the start and the end of the kernel.  A half with a single split
+// is one kernel, launched by its stream launcher; its NNLS launcher then does
+// nothing and records nothing.
+hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
+hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
+hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
+hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 hipError_t launch_measure_finish(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_gram_y_init(int K, const AnlsParams &p, hipStream_t s);
 hipError_t launch_gram_x_init(int K, const AnlsParams &p, hipStream_t s);
