@@ -163,10 +163,12 @@ def full_solve(name, seeds, tol, cap):
                     "E0": rep["E0"], "f": rep["f"], "sweeps": rep["sweeps"], "ipm_iters": rep["ipm_iters"],
                     "ms_stage1": rep["ms_stage1"], "ms_stage2": rep["ms_stage2"]})
         ctx.close()
+    import statistics
     conv = [r["ms"] for r in out if r["converged"]]
     return {"workload": name, "tol": tol, "ipm_cap": cap, "runs": out,
             "converged": f"{len(conv)}/{len(out)}",
-            "median_ms_converged": sorted(conv)[len(conv) // 2] if conv else None}
+            "median_ms_converged": statistics.median(conv) if conv else None,
+            "max_ms_converged": max(conv) if conv else None}
 
 
 def ipm_section(name="pdf_3000x500_k5", seed=1, iters=10):
@@ -264,7 +266,7 @@ def batching_section(count, sweeps):
             "speedup": plain_ms / batch_ms, "autotuned_waves": waves}
 
 
-def serving_section(seconds, rate=200.0, warm=1.0):
+def serving_section(seconds, rate=200.0, warm=1.0, plain=True):
     """64 streams (13 at n = 8000, k = 8, the rest n = 2000, k = 4), each
     starting at m = 64; Poisson arrivals at `rate`/s, each appending 16 columns
     to a uniformly chosen stream and re-solving stage 1 to the stop rule.  The
@@ -278,7 +280,7 @@ def serving_section(seconds, rate=200.0, warm=1.0):
            "m_final_max": max(s.m_capacity for s in specs), "warmup_s": warm,
            "request": "append 16 columns, then warm-started stage-1 sweeps until the stop rule "
                       "(eps_STOL 1e-4) holds or 64 sweeps are done"}
-    for name, cls in (("served", Server), ("plain", PlainServer)):
+    for name, cls in (("served", Server), ("plain", PlainServer)) if plain else (("served", Server),):
         srv = cls(specs, sweeps_per_round=4, eps_stol=1e-4, request_sweeps=64)
         srv.open_all()
         log(f"serving: {name} streams open")
@@ -291,7 +293,8 @@ def serving_section(seconds, rate=200.0, warm=1.0):
             res[name]["rounds"] = srv.rounds
             res[name]["mean_batch"] = float(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)))
         srv.close_all()
-    res["p99_speedup"] = res["plain"]["p99_ms"] / res["served"]["p99_ms"]
+    if plain:
+        res["p99_speedup"] = res["plain"]["p99_ms"] / res["served"]["p99_ms"]
     return res
 
 
@@ -385,7 +388,7 @@ def main():
     if not args.no_solve:
         log("stage-2 iteration timing")
         out["ipm_iteration"] = ipm_section(args.workload)
-        out["full_solve"] = full_solve(args.workload, [0, 1, 2, 3], 1e-8, 2000)
+        out["full_solve"] = full_solve(args.workload, [0, 1, 2, 3], 1e-8, 3000)
     if not args.no_layers:
         log("precision section")
         out["precision"] = precision_section(200)
@@ -394,6 +397,9 @@ def main():
     if not args.no_serve:
         log("serving section")
         out["serving"] = serving_section(args.serve_seconds)
+        # four times the arrival rate for a short trace: above what one request
+        # at a time can serve
+        out["serving_4x_load"] = serving_section(3.0, rate=800.0, warm=0.5)
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(M, X0, Y0)

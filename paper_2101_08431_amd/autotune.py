@@ -45,13 +45,17 @@ def _store(cache):
 
 
 def splits_for_waves(n, m, k, waves):
-    """Split counts that give about `waves` streaming waves per kernel."""
+    """Split counts that give about `waves` streaming waves per kernel.  A
+    single split (one kernel per half) is kept for matrices of at most 2^18
+    entries, as the library's automatic shape does; larger ones keep at least
+    two splits, so their NNLS runs in its own kernel."""
+    lo = 1 if n * m <= (1 << 18) else 2
     tn = math.ceil(n / XTILE)
-    xs = max(1, min(math.ceil(waves / (SWAVES * tn)), 64, m))
+    xs = max(lo, min(math.ceil(waves / (SWAVES * tn)), 64, m))
     j = max(1, 64 // k)
     tm = math.ceil(m / j)
-    ys = max(1, min(math.ceil(waves / (SWAVES * tm)), max(1, n // STHR), 64, n))
-    return xs, ys
+    ys = max(lo, min(math.ceil(waves / (SWAVES * tm)), max(1, n // STHR), 64, n))
+    return min(xs, m), min(ys, n)
 
 
 def tune_single(ctx, xs_cands=(1, 2, 4, 8, 11, 16), ys_cands=(1, 2, 3, 4, 6), sweeps=30, use_cache=True):

@@ -299,8 +299,7 @@ __device__ __forceinline__ void xstream_sums(const AnlsParams &p, int tile, int6
         }
         __syncthreads();
         const int64_t base = c0 * p.ldM + (row_ok ? i : 0);
-        // loads in flight per lane: 8 columns of 8-byte, 16 of 4-byte elements
-        constexpr int NL = sizeof(T) == 8 && P == NMF_GRAM_FP64 ? 8 : 16;
+        constexpr int NL = 8;   // loads in flight per lane
         for (int jb = w; jb < nc; jb += NL * SWAVES) {
             T mv[NL];
 #pragma unroll
