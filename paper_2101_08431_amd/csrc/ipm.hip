@@ -766,11 +766,12 @@ __global__ __launch_bounds__(NTHR) void k_post_x(AnlsParams p, IpmArgs ia, doubl
 }
 
 // ---------------------------------------------------------------- dense Cholesky of S
-// S is column-major, element (r, c) at S[c * ldS + r]; only the lower
-// triangle is used.  Right-looking blocked factorisation with CB-wide block
-// columns: factor the diagonal block, solve the panel below it, update the
-// trailing lower triangle.  invd[r] = 1 / L[r][r] is kept for the panel and
-// the triangular solves.
+// S is column-major, element (r, c) at S[c * ldS + r]; the Schur kernel fills
+// the lower triangle.  Right-looking blocked factorisation with CB-wide block
+// columns: factor the diagonal block and solve the panel below it (one
+// kernel), update the trailing lower triangle (a second).  The factor ends up
+// below the diagonal blocks (panels) and, transposed, in the whole upper
+// triangle (diagonal blocks included); invd[r] = 1 / L[r][r].
 
 // Value of v in lane `lane` (a compile-time constant after unrolling).
 __device__ __forceinline__ double lane_value(double v, int lane) {
@@ -780,17 +781,29 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Diagonal block [k0, k0 + nb) by one block of 256 threads: thread (tx, ty)
-// keeps the 4 x 4 entries (tx + 16a, ty + 16b) in registers.  Step c: the
-// owner of (c, c) takes the square root of the pivot, the owners of column c
-// scale it and publish it in LDS, and every thread applies the rank-one update
-// to its entries of the trailing triangle.  A pivot that is not positive sets
-// sc->chol_fail and is replaced by 1.
-__global__ __launch_bounds__(256) void k_chol_diag(double *S, int64_t ldS, int64_t N, int64_t k0, double *invd,
-                                                 IpmScal *sc) {
+// Block column [k0, k0 + CB) of the factorisation in one kernel.  Every block
+// first factors the diagonal block [k0, k0 + nb) in registers: thread (tx, ty)
+// keeps the 4 x 4 entries (tx + 16u, ty + 16v); step c takes the square root
+// of the pivot in its owner, scales column c, shares it in LDS and applies the
+// rank-one update (a pivot that is not positive sets sc->chol_fail and is
+// replaced by 1).  Block 0 stores L_kk transposed into the upper triangle
+// (S[(k0 + i) * ldS + k0 + j] = L[k0 + i][k0 + j], j < i) and 1 / diag; the
+// lower triangle of the diagonal block keeps its input, which the other
+// blocks read.  Then each block solves 64 rows of the panel below,
+// L[r, k0:k0+CB) = S[r, k0:k0+CB) L_kk^-T, four lanes per row each owning 16
+// entries: step q, the owner of entry q scales it by 1 / L_qq, the quad shares
+// it and every lane updates its own later entries.  The panel rows are also
+// stored transposed, S[r * ldS + k0 + q] = L[r][k0 + q], so that the backward
+// triangular solve reads them coalesced.
+constexpr int PROWS = 64;   // panel rows per block (4 lanes each)
+__global__ __launch_bounds__(256) void k_chol_col(double *S, int64_t ldS, int64_t N, int64_t k0, double *invd,
+                                                IpmScal *sc) {
     __shared__ double colv[CB];
     __shared__ double piv;
     __shared__ int bad;
+    __shared__ double Lk[CB * CB];          // Lk[q * CB + j] = L[k0 + j][k0 + q], j > q
+    __shared__ double id[CB];
+    __shared__ double T[CB * (PROWS + 1)];  // T[q * (PROWS + 1) + rr] = L[base + rr][k0 + q]
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int nb = (int)min((int64_t)CB, N - k0);
     double a[4][4];
@@ -837,37 +850,22 @@ __global__ __launch_bounds__(256) void k_chol_diag(double *S, int64_t ldS, int64
 #pragma unroll
             for (int v = 0; v < 4; ++v) a[u][v] = fma(-li[u], lj[v], a[u][v]);
     }
-    __syncthreads();
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = tx + 16 * u, j = ty + 16 * v;
-            if (i >= j && i < nb) S[(k0 + j) * ldS + k0 + i] = a[u][v];
-            if (i > j && i < nb) S[(k0 + i) * ldS + k0 + j] = a[u][v];   // transposed copy
-            if (i == j && i < nb) invd[k0 + i] = 1.0 / a[u][v];
+            if (i > j) Lk[j * CB + i] = a[u][v];
+            if (i == j) id[i] = 1.0 / a[u][v];
+            // block 0 keeps L_kk only in the upper triangle (transposed): the
+            // lower triangle still holds the input other blocks may be reading
+            if (blockIdx.x == 0 && i < nb) {
+                if (i > j) S[(k0 + i) * ldS + k0 + j] = a[u][v];
+                if (i == j) invd[k0 + i] = 1.0 / a[u][v];
+            }
         }
-    if (threadIdx.x == 0 && bad) sc->chol_fail = 1;
-}
-
-// Panel below a full diagonal block: L[r, k0:k0+CB) = S[r, k0:k0+CB) L_kk^-T.
-// Four lanes share a row, each owning 16 of its 64 entries; step q: the owner
-// of entry q scales it by 1 / L_qq, the quad shares it, and every lane updates
-// its own later entries.  L_kk and 1 / diag are read from LDS.  The block's
-// rows are also stored transposed into the upper triangle, S[r * ldS + k0 +
-// q] = L[r][k0 + q], so that the backward triangular solve reads them
-// coalesced.
-constexpr int PROWS = 64;   // rows per panel block (4 lanes each)
-__global__ __launch_bounds__(256) void k_chol_panel(double *S, int64_t ldS, int64_t N, int64_t k0,
-                                                  const double *invd) {
-    __shared__ double Lk[CB * CB];          // Lk[q * CB + j] = L[k0 + j][k0 + q], j > q
-    __shared__ double id[CB];
-    __shared__ double T[CB * (PROWS + 1)];  // T[q * (PROWS + 1) + rr] = L[base + rr][k0 + q]
-    for (int t = threadIdx.x; t < CB * CB; t += 256) {
-        const int j = t % CB, q = t / CB;
-        Lk[t] = (j > q) ? S[(k0 + q) * ldS + k0 + j] : 0.0;
-    }
-    if (threadIdx.x < CB) id[threadIdx.x] = invd[k0 + threadIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && bad) sc->chol_fail = 1;
+    if (N - k0 <= CB) return;   // no panel below the last block (uniform)
     __syncthreads();
     const int rr = threadIdx.x >> 2, part = threadIdx.x & 3;
     const int lane = threadIdx.x & 63;
@@ -951,7 +949,8 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double *S, int64_t ldS, int64
 }
 
 // Forward solve step: wave 0 of every block solves x_k = L_kk^-1 vec_k (lane
-// i keeps row i of L_kk; step q takes x_q from lane q) into LDS; block 0
+// i keeps row i of L_kk, read from the transposed copy in the upper triangle;
+// step q takes x_q from lane q) into LDS; block 0
 // stores x_k in out; every block then subtracts L[r, k0:k0+nb) x_k from its
 // 256 rows r below the block.
 __global__ __launch_bounds__(256) void k_trsv_fwd(const double *S, int64_t ldS, int64_t N, int64_t k0,
@@ -962,7 +961,7 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const double *S, int64_t ldS, 
         const int i = threadIdx.x;
         double l[CB];
 #pragma unroll
-        for (int j = 0; j < CB; ++j) l[j] = (j < i && i < nb) ? S[(k0 + j) * ldS + k0 + i] : 0.0;
+        for (int j = 0; j < CB; ++j) l[j] = (j < i && i < nb) ? S[(k0 + i) * ldS + k0 + j] : 0.0;
         double b = i < nb ? vec[k0 + i] : 0.0;
         const double di = i < nb ? invd[k0 + i] : 0.0;
         double mine = 0.0;
@@ -1348,11 +1347,10 @@ nmf_status cholesky(Ctx &c, int64_t N) {
     double *S = c.s.S;
     const int64_t ldS = c.s.ldS;
     for (int64_t k0 = 0; k0 < N; k0 += CB) {
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, c.st, S, ldS, N, k0, c.s.invd, c.s.sc);
         const int64_t below = N - k0 - CB;
+        const unsigned nb = below > 0 ? (unsigned)((below + PROWS - 1) / PROWS) : 1u;
+        hipLaunchKernelGGL(k_chol_col, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, c.s.invd, c.s.sc);
         if (below > 0) {
-            hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((below + PROWS - 1) / PROWS)), dim3(256), 0, c.st, S,
-                               ldS, N, k0, (const double *)c.s.invd);
             const int64_t nt = (below + CB - 1) / CB;
             hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, c.st, S, ldS, N, k0);
         }

@@ -49,3 +49,25 @@ def test_memory_admission_and_slots():
     ra = ref.run([Request(r.rid, r.sid, r.cols, r.arrival) for r in reqs])
     for a, b in zip(ra, out):
         assert a.sweeps == b.sweeps and np.array_equal(a.result[1], b.result[1])
+
+
+def test_mix_equals_alone_across_launch_shape_change():
+    # streams that start small (one kernel per half) and grow past 2^18
+    # entries (split kernels) while requests overlap: every request still ends
+    # where it ends alone
+    specs, reqs = build_workload(streams=5, rate=2000.0, seconds=0.02, m0=64, add=16, seed=5, big_every=5,
+                                 small=(2000, 4), big=(2600, 5))
+    print(f"case serving across shape change: {len(reqs)} requests on 5 streams", flush=True)
+    alone = PlainServer(specs, record=True)
+    alone.open_all()
+    ra = alone.run([Request(r.rid, r.sid, r.cols, r.arrival) for r in reqs])
+    alone.close_all()
+    mix = Server(specs, record=True, max_active=64)
+    mix.open_all()
+    rm = mix.run([Request(r.rid, r.sid, r.cols, r.arrival) for r in reqs])
+    mix.close_all()
+    assert max(mix.batch_sizes) > 1
+    for a, b in zip(ra, rm):
+        assert a.rid == b.rid
+        assert a.sweeps == b.sweeps, (a.rid, a.sid, a.sweeps, b.sweeps)
+        assert np.array_equal(a.result[0], b.result[0]) and np.array_equal(a.result[1], b.result[1]), (a.rid, a.sid)
