@@ -604,8 +604,14 @@ __global__ __launch_bounds__(STHR) void kb_xstream(const AnlsParams *tab, const 
     const AnlsParams p = tab[q];
     const int local = blockIdx.x - off[q];
     __shared__ double lds[xstream_lds<K>()];
-    if (p.Sx == 1) xfused_body<K, P>(p, local, lds);
-    else xstream_body<K, P>(p, local % p.Tn, local / p.Tn, lds);
+    xstream_body<K, P>(p, local % p.Tn, local / p.Tn, lds);
+}
+template <int K, int P>
+__global__ __launch_bounds__(STHR) void kb_xfused(const AnlsParams *tab, const int *off, int np) {
+    const int q = batch_problem(off, np, blockIdx.x);
+    const AnlsParams p = tab[q];
+    __shared__ double lds[xstream_lds<K>()];
+    xfused_body<K, P>(p, blockIdx.x - off[q], lds);
 }
 template <int K>
 __global__ __launch_bounds__(NTHR) void kb_xnnls(const AnlsParams *tab, const int *off, int np) {
@@ -618,8 +624,13 @@ __global__ __launch_bounds__(STHR) void kb_ystream(const AnlsParams *tab, const 
     const int q = batch_problem(off, np, blockIdx.x);
     const AnlsParams p = tab[q];
     const int local = blockIdx.x - off[q];
-    if (p.Sy == 1) yfused_body<K, P>(p, local);
-    else ystream_body<K, P>(p, local % p.Tm, local / p.Tm);
+    ystream_body<K, P>(p, local % p.Tm, local / p.Tm);
+}
+template <int K, int P>
+__global__ __launch_bounds__(STHR) void kb_yfused(const AnlsParams *tab, const int *off, int np) {
+    const int q = batch_problem(off, np, blockIdx.x);
+    const AnlsParams p = tab[q];
+    yfused_body<K, P>(p, blockIdx.x - off[q]);
 }
 template <int K>
 __global__ __launch_bounds__(NTHR) void kb_ynnls(const AnlsParams *tab, const int *off, int np) {
@@ -935,24 +946,29 @@ hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t 
     const AnlsParams *t = g.table;
     const int *o = g.off;
     const int np = g.count;
-    if (prec == NMF_GRAM_FP32) {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_xstream<KK, NMF_GRAM_FP32>), dim3(g.blocks[0]), dim3(STHR), 0, s, t, o, np));
-    } else if (prec == NMF_GRAM_BF16X2) {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_xstream<KK, NMF_GRAM_BF16X2>), dim3(g.blocks[0]), dim3(STHR), 0, s, t, o, np));
-    } else {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_xstream<KK, NMF_GRAM_FP64>), dim3(g.blocks[0]), dim3(STHR), 0, s, t, o, np));
+    const int *ox = o, *onx = o + (np + 1), *oy = o + 2 * (np + 1), *ony = o + 3 * (np + 1);
+    const int *ofx = o + 4 * (np + 1), *ofy = o + 5 * (np + 1);
+#define NMF_BATCH_STREAM(KERNEL, NB, OFF)                                                                      \
+    if ((NB) > 0) {                                                                                           \
+        if (prec == NMF_GRAM_FP32) {                                                                          \
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((KERNEL<KK, NMF_GRAM_FP32>), dim3(NB), dim3(STHR), 0, s, t, OFF, np)); \
+        } else if (prec == NMF_GRAM_BF16X2) {                                                                 \
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((KERNEL<KK, NMF_GRAM_BF16X2>), dim3(NB), dim3(STHR), 0, s, t, OFF, np)); \
+        } else {                                                                                              \
+            NMF_K_SWITCH(K, hipLaunchKernelGGL((KERNEL<KK, NMF_GRAM_FP64>), dim3(NB), dim3(STHR), 0, s, t, OFF, np)); \
+        }                                                                                                     \
     }
+    // X-half: split streams, fused halves, then the row NNLS of the split ones
+    NMF_BATCH_STREAM(kb_xstream, g.blocks[0], ox)
+    NMF_BATCH_STREAM(kb_xfused, g.blocks[4], ofx)
     if (g.blocks[1] > 0)
-        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_xnnls<KK>, dim3(g.blocks[1]), dim3(NTHR), 0, s, t, o + (np + 1), np));
-    if (prec == NMF_GRAM_FP32) {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_ystream<KK, NMF_GRAM_FP32>), dim3(g.blocks[2]), dim3(STHR), 0, s, t, o + 2 * (np + 1), np));
-    } else if (prec == NMF_GRAM_BF16X2) {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_ystream<KK, NMF_GRAM_BF16X2>), dim3(g.blocks[2]), dim3(STHR), 0, s, t, o + 2 * (np + 1), np));
-    } else {
-        NMF_K_SWITCH(K, hipLaunchKernelGGL((kb_ystream<KK, NMF_GRAM_FP64>), dim3(g.blocks[2]), dim3(STHR), 0, s, t, o + 2 * (np + 1), np));
-    }
+        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_xnnls<KK>, dim3(g.blocks[1]), dim3(NTHR), 0, s, t, onx, np));
+    // Y-half
+    NMF_BATCH_STREAM(kb_ystream, g.blocks[2], oy)
+    NMF_BATCH_STREAM(kb_yfused, g.blocks[5], ofy)
     if (g.blocks[3] > 0)
-        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_ynnls<KK>, dim3(g.blocks[3]), dim3(NTHR), 0, s, t, o + 3 * (np + 1), np));
+        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_ynnls<KK>, dim3(g.blocks[3]), dim3(NTHR), 0, s, t, ony, np));
+#undef NMF_BATCH_STREAM
     return hipGetLastError();
 }
 

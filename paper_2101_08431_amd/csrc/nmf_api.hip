@@ -694,8 +694,12 @@ struct nmf_batch {
     std::string err;
 };
 
+// Offset tables: NBK arrays of (members + 1) entries per group, at most
+// NBK * 2 * count entries over all groups (a group has at least one member).
+static size_t offsets_bytes(size_t count) { return align_up((size_t)nmfk::NBK * 2 * count * sizeof(int), 256); }
+
 static size_t batch_bytes(int32_t count) {
-    return align_up((size_t)count * sizeof(AnlsParams), 256) + align_up((size_t)4 * (count + 1) * sizeof(int), 256) +
+    return align_up((size_t)count * sizeof(AnlsParams), 256) + offsets_bytes((size_t)count) +
            align_up((size_t)2 * count * sizeof(long long), 256) + 256;
 }
 
@@ -736,15 +740,14 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
     const size_t count = b->ctxs.size();
     AnlsParams *dtab = (AnlsParams *)b->ws;
     int *doff = (int *)(b->ws + align_up(count * sizeof(AnlsParams), 256));
-    b->poll = (long long *)(b->ws + align_up(count * sizeof(AnlsParams), 256) +
-                            align_up((size_t)4 * (count + 1) * sizeof(int), 256));
+    b->poll = (long long *)(b->ws + align_up(count * sizeof(AnlsParams), 256) + offsets_bytes(count));
     b->order.clear();
     for (auto &g : b->groups) {
         const int np = (int)g.members.size();
         g.g.table = dtab + tab.size();
         g.g.off = doff + offs.size();
         g.g.count = np;
-        std::vector<int> o[4];
+        std::vector<int> o[nmfk::NBK];
         for (auto &v : o) v.assign(1, 0);
         for (int q : g.members) {
             AnlsParams p = b->ctxs[q]->p;
@@ -752,13 +755,19 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
             tab.push_back(p);
             b->order.push_back(q);
             g.g.single = p;
-            const int cnt[4] = {p.Tn * p.Sx, p.Sx == 1 ? 0 : p.Bx, p.Tm * p.Sy, p.Sy == 1 ? 0 : p.By};
-            for (int k = 0; k < 4; ++k) o[k].push_back(o[k].back() + cnt[k]);
+            const bool fx = p.Sx == 1, fy = p.Sy == 1;
+            const int cnt[nmfk::NBK] = {fx ? 0 : p.Tn * p.Sx, fx ? 0 : p.Bx, fy ? 0 : p.Tm * p.Sy,
+                                        fy ? 0 : p.By,     fx ? p.Tn : 0,   fy ? p.Tm : 0};
+            for (int k = 0; k < nmfk::NBK; ++k) o[k].push_back(o[k].back() + cnt[k]);
         }
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < nmfk::NBK; ++k) {
             g.g.blocks[k] = o[k].back();
             offs.insert(offs.end(), o[k].begin(), o[k].end());
         }
+    }
+    if (offs.size() * sizeof(int) > offsets_bytes(count)) {
+        b->err = "batch offset tables exceed their workspace region";
+        return NMF_ENOMEM;
     }
     if (hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(AnlsParams), hipMemcpyHostToDevice, b->stream) !=
             hipSuccess ||

@@ -102,13 +102,16 @@ hipError_t launch_copy_columns_warm(int K, const AnlsParams &p, int64_t j_from, 
                                     int64_t j1, hipStream_t s);
 
 // A group of problems sharing K and precision, launched as one flattened grid
-// per stage-1 kernel.  Device arrays: table[count] and off[4][count + 1]
-// (block prefix sums of k_xstream, k_xnnls, k_ystream, k_ynnls).
+// per stage-1 kernel.  Device arrays: table[count] and off[NBK][count + 1]
+// (block prefix sums of the split X stream, row NNLS, split Y stream, column
+// NNLS, fused X half and fused Y half; a problem has blocks in either the
+// split or the fused kernels of a half).
+constexpr int NBK = 6;   // flattened kernels per batched sweep
 struct BatchGroup {
     const AnlsParams *table;
     const int *off;
     int count;
-    int blocks[4];
+    int blocks[6];
     AnlsParams single;   // host copy used when count == 1 (plain launches, no table lookup)
 };
 hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t s);
