@@ -227,46 +227,80 @@ __device__ __forceinline__ void wave_stats_and_gram(const double (&st)[NST], con
     }
 }
 
+// The stage-1 stop flag of a sweep kernel (mode 0 only).  It is read with a
+// vector load issued before the kernel's other loads: waiting for a scalar
+// load would also wait for every kernel argument still in flight, and the
+// flag would then cost a memory round trip of its own before any data moves.
+__device__ __forceinline__ bool sweep_stopped(const AnlsParams &p) {
+    const int conv = __hip_atomic_load(&p.st->converged, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (p.mode == 0) & (conv != 0);
+}
+
 // End of a sweep, in the block that finished last: the X and Y statistics
 // records, the E(.;0) parts and the stop rule of Sec. IV (mode 0), or only the
 // Y part for appended columns (mode 2).  All threads call it; scr holds
 // blockDim doubles of LDS.
 __device__ __forceinline__ void sweep_summary(const AnlsParams &p, double *scr) {
     __shared__ double sx[NST], sy[NST];
-    reduce_records(p.xstat, p.Rx, NST, sx, scr);
-    reduce_records(p.ystat, p.Ry, NST, sy, scr);
+    DevStatus *s = p.st;
+    // the status fields and both record sets are loaded together: the first
+    // half of the block sums the X records, the second half the Y records
+    double ey_g2 = 0.0, ey_c2 = 0.0, solves = 0.0, fails = 0.0, changes = 0.0, eps = 0.0;
+    long long sweeps = 0, max_sweeps = 0;
+    if (threadIdx.x == 0) {
+        ey_g2 = s->ey_g2;
+        ey_c2 = s->ey_c2;
+        solves = s->solves;
+        fails = s->fails;
+        changes = s->changes;
+        eps = s->eps_stol;
+        sweeps = s->sweeps;
+        max_sweeps = s->max_sweeps;
+    }
+    const int half = (int)blockDim.x / 2;
+    const bool yside = (int)threadIdx.x >= half;
+    const int tid = yside ? (int)threadIdx.x - half : (int)threadIdx.x;
+    const double acc = yside ? records_partial(p.ystat, p.Ry, NST, tid, half)
+                             : records_partial(p.xstat, p.Rx, NST, tid, half);
+    scr[threadIdx.x] = acc;
+    __syncthreads();
+    if (tid < NST) {
+        const int G = half / NST;
+        double v = 0.0;
+        for (int gg = 0; gg < G; ++gg) v += scr[(yside ? half : 0) + gg * NST + tid];
+        (yside ? sy : sx)[tid] = v;
+    }
+    __syncthreads();
     if (threadIdx.x == 0 && p.mode == 2) {
         // appended columns solved: Y part of E, counters; no sweep, no stop test
-        DevStatus *s = p.st;
         s->ey_g2 = sy[ST_EG2];
         s->ey_c2 = sy[ST_EC2];
         s->E_cur = -1.0;
-        s->solves += sy[ST_SOLVES];
-        s->fails += sy[ST_FAILS];
-        s->changes += sy[ST_CHANGES];
+        s->solves = solves + sy[ST_SOLVES];
+        s->fails = fails + sy[ST_FAILS];
+        s->changes = changes + sy[ST_CHANGES];
     } else if (threadIdx.x == 0) {
-        DevStatus *s = p.st;
         const double step2 = sx[ST_STEP2] + sy[ST_STEP2];
         const double norm2 = sx[ST_NORM2] + sy[ST_NORM2];
         s->step2 = step2;
         s->norm2 = norm2;
         s->ex_g2 = sx[ST_EG2];
         s->ex_c2 = sx[ST_EC2];
-        if (s->ey_g2 >= 0.0) {
-            const double eg = sqrt(sx[ST_EG2] + s->ey_g2);
-            const double ec = sqrt(sx[ST_EC2] + s->ey_c2);
+        if (ey_g2 >= 0.0) {
+            const double eg = sqrt(sx[ST_EG2] + ey_g2);
+            const double ec = sqrt(sx[ST_EC2] + ey_c2);
             s->E_prev = eg > ec ? eg : ec;
         }
-        s->ey_g2_prev = s->ey_g2;
-        s->ey_c2_prev = s->ey_c2;
+        s->ey_g2_prev = ey_g2;
+        s->ey_c2_prev = ey_c2;
         s->ey_g2 = sy[ST_EG2];
         s->ey_c2 = sy[ST_EC2];
         s->E_cur = -1.0;
-        s->solves += sx[ST_SOLVES] + sy[ST_SOLVES];
-        s->fails += sx[ST_FAILS] + sy[ST_FAILS];
-        s->changes += sx[ST_CHANGES] + sy[ST_CHANGES];
-        s->sweeps += 1;
-        if (sqrt(step2) <= s->eps_stol * (1.0 + sqrt(norm2)) || s->sweeps >= s->max_sweeps) s->converged = 1;
+        s->solves = solves + (sx[ST_SOLVES] + sy[ST_SOLVES]);
+        s->fails = fails + (sx[ST_FAILS] + sy[ST_FAILS]);
+        s->changes = changes + (sx[ST_CHANGES] + sy[ST_CHANGES]);
+        s->sweeps = sweeps + 1;
+        if (sqrt(step2) <= eps * (1.0 + sqrt(norm2)) || sweeps + 1 >= max_sweeps) s->converged = 1;
     }
 }
 
@@ -278,35 +312,52 @@ constexpr int xstream_lds() {
 
 // Streams the columns [j0, j1) of the tile's 64 rows of M against Y and
 // leaves each wave's partial sums of B_X in lds[(w * K + a) * XTILE + lane]
-// (ends with a barrier).  Every thread of the block calls it.
+// (ends with a barrier).  The first chunk of Y and the first eight columns of
+// each wave go out together with the caller's stop flag (a scalar load); with
+// `stop` set the block returns false before touching LDS.  Every thread of the
+// block calls it.
 template <int K, int P>
-__device__ __forceinline__ void xstream_sums(const AnlsParams &p, int tile, int64_t j0, int64_t j1, double *lds) {
+__device__ __forceinline__ bool xstream_sums(const AnlsParams &p, int tile, int64_t j0, int64_t j1, double *lds,
+                                             bool stop) {
     using T = typename MElem<P>::T;
+    constexpr int NL = 8;   // loads in flight per lane
+    constexpr int YPER = (XCHUNK * K + STHR - 1) / STHR;
     T *ys = reinterpret_cast<T *>(lds);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = (int64_t)tile * XTILE + lane;
     const bool row_ok = i < p.n;
+    // lanes past the last row stream row n - 1; their sums are never used
+    const int64_t ic = row_ok ? i : p.n - 1;
 
     T acc[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) acc[a] = T(0);
     for (int64_t c0 = j0; c0 < j1; c0 += XCHUNK) {
         const int nc = (int)min((int64_t)XCHUNK, j1 - c0);
-        __syncthreads();
-        for (int q = threadIdx.x; q < nc * K; q += STHR) {
+        const int64_t base = c0 * p.ldM + ic;
+        // all first loads of the chunk are issued without a branch between
+        // them (indices clamped into the chunk; surplus values are not used)
+        T yv[YPER], mv[NL];
+#pragma unroll
+        for (int u = 0; u < YPER; ++u) {
+            const int q = min((int)threadIdx.x + u * STHR, nc * K - 1);
             const int jj = q / K, a = q - jj * K;
-            ys[q] = (T)p.Y[(int64_t)a * p.ldY + c0 + jj];
+            yv[u] = (T)p.Y[(int64_t)a * p.ldY + c0 + jj];
+        }
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int jj = min(w + t * SWAVES, nc - 1);
+            mv[t] = MElem<P>::load(p, base + (int64_t)jj * p.ldM);
+        }
+        if (c0 == j0 && stop) return false;
+        __syncthreads();   // the previous chunk's reads of ys are done
+#pragma unroll
+        for (int u = 0; u < YPER; ++u) {
+            const int q = (int)threadIdx.x + u * STHR;
+            if (q < nc * K) ys[q] = yv[u];
         }
         __syncthreads();
-        const int64_t base = c0 * p.ldM + (row_ok ? i : 0);
-        constexpr int NL = 8;   // loads in flight per lane
         for (int jb = w; jb < nc; jb += NL * SWAVES) {
-            T mv[NL];
-#pragma unroll
-            for (int t = 0; t < NL; ++t) {
-                const int jj = jb + t * SWAVES;
-                mv[t] = (jj < nc && row_ok) ? MElem<P>::load(p, base + (int64_t)jj * p.ldM) : T(0);
-            }
 #pragma unroll
             for (int t = 0; t < NL; ++t) {
                 const int jj = jb + t * SWAVES;
@@ -315,21 +366,30 @@ __device__ __forceinline__ void xstream_sums(const AnlsParams &p, int tile, int6
                     for (int a = 0; a < K; ++a) acc[a] = fma(mv[t], ys[jj * K + a], acc[a]);
                 }
             }
+            const int jn = jb + NL * SWAVES;
+            if (jn < nc) {
+#pragma unroll
+                for (int t = 0; t < NL; ++t) {
+                    const int jj = min(jn + t * SWAVES, nc - 1);
+                    mv[t] = MElem<P>::load(p, base + (int64_t)jj * p.ldM);
+                }
+            }
         }
     }
     __syncthreads();
 #pragma unroll
     for (int a = 0; a < K; ++a) lds[(w * K + a) * XTILE + lane] = (double)acc[a];
     __syncthreads();
+    return true;
 }
 
 // X stream, one column split: partial sums of B_X for the split.
 template <int K, int P>
 __device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int split, double *lds) {
-    if (p.mode == 0 && p.st->converged) return;
+    const bool stop = sweep_stopped(p);
     const int64_t j0 = (int64_t)split * p.xcols;
     const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
-    xstream_sums<K, P>(p, tile, j0, j1, lds);
+    if (!xstream_sums<K, P>(p, tile, j0, j1, lds, stop)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = (int64_t)tile * XTILE + lane;
     if (w == 0 && i < p.n) {
@@ -349,11 +409,12 @@ __device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int 
 // X-side records then number Rx = Tn).
 template <int K, int P>
 __device__ __forceinline__ void xfused_body(const AnlsParams &p, int tile, double *lds) {
-    if (p.mode == 0 && p.st->converged) return;
+    const bool stop = sweep_stopped(p);
     __shared__ double G[K * K];
     __shared__ double scr[STHR];
-    reduce_records(p.gy_part, p.Ry, K * K, G, scr);
-    xstream_sums<K, P>(p, tile, 0, p.m, lds);
+    const double gacc = records_partial(p.gy_part, p.Ry, K * K, (int)threadIdx.x, STHR);
+    if (!xstream_sums<K, P>(p, tile, 0, p.m, lds, stop)) return;
+    records_finish(gacc, K * K, 0, STHR, G, scr);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (w != 0) return;
     const int64_t i = (int64_t)tile * XTILE + lane;
@@ -379,43 +440,55 @@ __device__ __forceinline__ void xfused_body(const AnlsParams &p, int tile, doubl
                            p.mode == 0 ? p.gx_part + (int64_t)tile * K * K : nullptr);
 }
 
+// Splits of the B partials summed per row (column), in split order; SB splits
+// (SB * K loads) are in flight at a time and splits past S read as zero.
+template <int K>
+constexpr int partial_batch() {
+    return (48 / K) < 1 ? 1 : ((48 / K) > 16 ? 16 : 48 / K);
+}
+template <int K>
+__device__ __forceinline__ void sum_split_partials(const double *part, int64_t ld, int64_t i, int S,
+                                                   double (&b)[K]) {
+    constexpr int SB = partial_batch<K>();
+    for (int s0 = 0; s0 < S; s0 += SB) {
+        double t[SB][K];
+        // every load is issued (splits past S re-read split S - 1) and the
+        // surplus ones are dropped afterwards: no branch between the loads
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int su = s0 + u < S ? s0 + u : S - 1;
+#pragma unroll
+            for (int a = 0; a < K; ++a) t[u][a] = part[((int64_t)su * K + a) * ld + i];
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) b[a] += (s0 + u < S) ? t[u][a] : 0.0;
+        }
+    }
+}
+
 template <int K>
 __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
     __shared__ double G[K * K];
     __shared__ double lds[NTHR];
+    const bool stop = sweep_stopped(p);
     const int64_t i = (int64_t)bid * NTHR + threadIdx.x;
     const bool live = i < p.n;
-    // the row's loads go out before anything waits on memory
+    // the row's loads and the G_Y records go out before anything waits on
+    // memory; lanes past the last row load row n - 1 and solve nothing
+    const int64_t ic = live ? i : p.n - 1;
     double b[K], x[K];
-    uint32_t old_mask = 0u;
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         b[a] = 0.0;
-        x[a] = live ? p.X[(int64_t)a * p.ldX + i] : 0.0;
+        x[a] = p.X[(int64_t)a * p.ldX + ic];
     }
-    if (live) {
-        old_mask = p.xmask[i];
-        int s = 0;
-        for (; s + 1 < p.Sx; s += 2) {
-            double t0[K], t1[K];
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                t0[a] = p.bx_part[((int64_t)s * K + a) * p.ldX + i];
-                t1[a] = p.bx_part[((int64_t)(s + 1) * K + a) * p.ldX + i];
-            }
-#pragma unroll
-            for (int a = 0; a < K; ++a) {
-                b[a] += t0[a];
-                b[a] += t1[a];
-            }
-        }
-        for (; s < p.Sx; ++s) {
-#pragma unroll
-            for (int a = 0; a < K; ++a) b[a] += p.bx_part[((int64_t)s * K + a) * p.ldX + i];
-        }
-    }
-    if (p.mode == 0 && p.st->converged) return;
-    reduce_records(p.gy_part, p.Ry, K * K, G, lds);
+    const uint32_t old_mask = p.xmask[ic];
+    sum_split_partials<K>(p.bx_part, p.ldX, ic, p.Sx, b);
+    const double gacc = records_partial(p.gy_part, p.Ry, K * K, (int)threadIdx.x, NTHR);
+    if (stop) return;
+    records_finish(gacc, K * K, 0, NTHR, G, lds);
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
@@ -430,44 +503,82 @@ __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
 // ---------------------------------------------------------------- Y-half
 // Streams the rows [r0, r1) of the tile's J = 64 / K columns of M against X
 // and leaves each wave's transpose-reduced sums in red[w * YVALS + lane]
-// (value jj * K + a is B_Y[a][jb + jj]); ends with a barrier.
+// (value jj * K + a is B_Y[a][jb + jj]); ends with a barrier.  With `stop`
+// set the block returns false before any arithmetic.  When registers allow
+// (K + J <= 17) the loads of each row run one row ahead of the arithmetic and
+// the first row's loads go out together with the caller's stop flag.
 template <int K, int P>
-__device__ __forceinline__ void ystream_sums(const AnlsParams &p, int ct, int64_t r0, int64_t r1, double *red) {
+__device__ __forceinline__ bool ystream_sums(const AnlsParams &p, int ct, int64_t r0, int64_t r1, double *red,
+                                             bool stop) {
     using T = typename MElem<P>::T;
     constexpr int J = YVALS / K;
+    constexpr bool AHEAD = K + J <= 17;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t jb = (int64_t)ct * J;
     const int nj = (int)min((int64_t)J, p.m - jb);
 
+    // a row's loads, with no branch between them: rows past r1 load row
+    // r1 - 1 (never accumulated) and columns past the tile's last load its
+    // last column and are zeroed
+    auto load_row = [&](int64_t i, T (&x)[K], T (&mv)[J]) {
+        const int64_t ic = i < r1 ? i : r1 - 1;
+        const int64_t base = jb * p.ldM + ic;
+#pragma unroll
+        for (int a = 0; a < K; ++a) x[a] = (T)p.X[(int64_t)a * p.ldX + ic];
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) {
+            const T v = MElem<P>::load(p, base + (int64_t)min(jj, nj - 1) * p.ldM);
+            mv[jj] = jj < nj ? v : T(0);
+        }
+    };
+
     T v[YVALS];
 #pragma unroll
     for (int q = 0; q < YVALS; ++q) v[q] = T(0);
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += STHR) {
+    const int64_t i0 = r0 + threadIdx.x;
+    if constexpr (AHEAD) {
         T x[K], mv[J];
+        load_row(i0, x, mv);
+        if (stop) return false;
+        for (int64_t i = i0; i < r1; i += STHR) {
+            T xn[K], mn[J];
+            load_row(i + STHR, xn, mn);
 #pragma unroll
-        for (int a = 0; a < K; ++a) x[a] = (T)p.X[(int64_t)a * p.ldX + i];
-        const int64_t base = jb * p.ldM + i;
+            for (int jj = 0; jj < J; ++jj) {
 #pragma unroll
-        for (int jj = 0; jj < J; ++jj) mv[jj] = (jj < nj) ? MElem<P>::load(p, base + (int64_t)jj * p.ldM) : T(0);
+                for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
+            }
 #pragma unroll
-        for (int jj = 0; jj < J; ++jj) {
+            for (int a = 0; a < K; ++a) x[a] = xn[a];
 #pragma unroll
-            for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
+            for (int jj = 0; jj < J; ++jj) mv[jj] = mn[jj];
+        }
+    } else {
+        if (stop) return false;
+        for (int64_t i = i0; i < r1; i += STHR) {
+            T x[K], mv[J];
+            load_row(i, x, mv);
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) {
+#pragma unroll
+                for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
+            }
         }
     }
     red[w * YVALS + lane] = (double)wave_transpose_reduce(v, lane);
     __syncthreads();
+    return true;
 }
 
 // Y stream, one row split: partial sums of B_Y for the split.
 template <int K, int P>
 __device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int split) {
-    if (p.mode == 0 && p.st->converged) return;
+    const bool stop = sweep_stopped(p);
     constexpr int J = YVALS / K;
     __shared__ double red[SWAVES * YVALS];
     const int64_t r0 = (int64_t)split * p.yrows;
     const int64_t r1 = min(r0 + (int64_t)p.yrows, p.n);
-    ystream_sums<K, P>(p, ct, r0, r1, red);
+    if (!ystream_sums<K, P>(p, ct, r0, r1, red, stop)) return;
     const int64_t jb = (int64_t)ct * J;
     const int nj = (int)min((int64_t)J, p.m - jb);
     if ((int)threadIdx.x < nj * K) {
@@ -486,15 +597,16 @@ __device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int sp
 // the sweep.
 template <int K, int P>
 __device__ __forceinline__ void yfused_body(const AnlsParams &p, int ct) {
-    if (p.mode == 0 && p.st->converged) return;
+    const bool stop = sweep_stopped(p);
     constexpr int J = YVALS / K;
     __shared__ double red[SWAVES * YVALS];
     __shared__ double G[K * K];
     __shared__ double scr[STHR];
     __shared__ double bsum[YVALS];
     __shared__ unsigned flag;
-    reduce_records(p.gx_part, p.Rx, K * K, G, scr);
-    ystream_sums<K, P>(p, ct, 0, p.n, red);
+    const double gacc = records_partial(p.gx_part, p.Rx, K * K, (int)threadIdx.x, STHR);
+    if (!ystream_sums<K, P>(p, ct, 0, p.n, red, stop)) return;
+    records_finish(gacc, K * K, 0, STHR, G, scr);
     const int64_t jb = (int64_t)ct * J;
     const int nj = (int)min((int64_t)J, p.m - jb);
     if ((int)threadIdx.x < nj * K) {
@@ -533,25 +645,23 @@ __device__ __forceinline__ void ynnls_body(const AnlsParams &p, int bid) {
     __shared__ double G[K * K];
     __shared__ double lds[NTHR];
     __shared__ unsigned flag;
+    const bool stop = sweep_stopped(p);
     const int64_t j = (int64_t)bid * NTHR + threadIdx.x;
     const bool live = j < p.m;
-    // the column's loads go out before anything waits on memory
+    // the column's loads and the G_X records go out before anything waits on
+    // memory; lanes past the last column load column m - 1 and solve nothing
+    const int64_t jc = live ? j : p.m - 1;
     double b[K], y[K];
-    uint32_t old_mask = 0u;
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         b[a] = 0.0;
-        y[a] = live ? p.Y[(int64_t)a * p.ldY + j] : 0.0;
+        y[a] = p.Y[(int64_t)a * p.ldY + jc];
     }
-    if (live) {
-        old_mask = p.ymask[j];
-        for (int s = 0; s < p.Sy; ++s) {
-#pragma unroll
-            for (int a = 0; a < K; ++a) b[a] += p.by_part[((int64_t)s * K + a) * p.ldY + j];
-        }
-    }
-    if (p.mode == 0 && p.st->converged) return;
-    reduce_records(p.gx_part, p.Rx, K * K, G, lds);
+    const uint32_t old_mask = p.ymask[jc];
+    sum_split_partials<K>(p.by_part, p.ldY, jc, p.Sy, b);
+    const double gacc = records_partial(p.gx_part, p.Rx, K * K, (int)threadIdx.x, NTHR);
+    if (stop) return;
+    records_finish(gacc, K * K, 0, NTHR, G, lds);
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;

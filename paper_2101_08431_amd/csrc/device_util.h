@@ -8,19 +8,16 @@
 
 namespace nmfk {
 
-// Increments a counter; returns true in the block that arrives last (and
-// resets the counter).  All threads of the block call it.
+// Counts the block in; returns true in the block that arrives last.  The
+// counter wraps to zero at `expected` in the same atomic (atomicInc), so it is
+// ready for the next launch without another write.  All threads of the block
+// call it.
 __device__ __forceinline__ bool last_arrival(unsigned *cnt, unsigned expected, unsigned *flag_lds) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        const unsigned old = atomicAdd(cnt, 1u);
-        const bool last = (old == expected - 1u);
-        if (last) {
-            atomicExch(cnt, 0u);
-            __threadfence();
-        }
-        *flag_lds = last ? 1u : 0u;
+        const unsigned old = atomicInc(cnt, expected - 1u);
+        *flag_lds = (old == expected - 1u) ? 1u : 0u;
     }
     __syncthreads();
     const bool last = (*flag_lds != 0u);
@@ -57,34 +54,53 @@ __device__ __forceinline__ T wave_transpose_reduce(T (&v)[YVALS], int lane) {
 // out[0..len) (LDS), using the whole block: thread (q, g) sums the records
 // g, g + G, g + 2G, ... of entry q (G = blockDim / len groups), then the G
 // group sums are added in order.  `scratch` holds blockDim doubles of LDS.
-// Ends with a barrier.  len <= blockDim.
+// Ends with a barrier.  len <= blockDim.  It is split in two so that a kernel
+// can issue the loads (records_partial: thread tid of nthr threads returns its
+// group sum, no barrier) together with its other loads and add them up later
+// (records_finish).
+__device__ __forceinline__ double records_partial(const double *src, int cnt, int len, int tid, int nthr) {
+    const int G = nthr / len;
+    if (G <= 0) return 0.0;   // len > nthr: not a supported call
+    const int q = tid % len, g = tid / len;
+    // threads past the G groups, and records past the end, load record 0 or
+    // cnt - 1 and drop it: four loads in flight per step, no branch between
+    // them
+    const int gc = g < G ? g : 0;
+    double acc = 0.0;
+    for (int t = gc; t < cnt; t += 4 * G) {
+        const double a0 = src[(size_t)t * len + q];
+        const double a1 = src[(size_t)min(t + G, cnt - 1) * len + q];
+        const double a2 = src[(size_t)min(t + 2 * G, cnt - 1) * len + q];
+        const double a3 = src[(size_t)min(t + 3 * G, cnt - 1) * len + q];
+        acc += a0;
+        acc += t + G < cnt ? a1 : 0.0;
+        acc += t + 2 * G < cnt ? a2 : 0.0;
+        acc += t + 3 * G < cnt ? a3 : 0.0;
+    }
+    return g < G ? acc : 0.0;
+}
+
+// Second half of reduce_records: the partials of threads [base, base + nthr)
+// go through scratch[base ..) and thread base + q < base + len adds its entry's
+// G group sums in order into out[q].  Ends with a barrier.
+__device__ __forceinline__ void records_finish(double acc, int len, int base, int nthr, double *out,
+                                               double *scratch) {
+    const int G = nthr / len;
+    scratch[threadIdx.x] = acc;
+    __syncthreads();
+    const int tid = (int)threadIdx.x - base;
+    if (tid >= 0 && tid < len) {
+        double s = 0.0;
+        for (int gg = 0; gg < G; ++gg) s += scratch[base + gg * len + tid];
+        out[tid] = s;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ void reduce_records(const double *src, int cnt, int len, double *out,
                                                double *scratch) {
-    const int G = (int)blockDim.x / len;
-    const int q = threadIdx.x % len, g = threadIdx.x / len;
-    if (g < G) {
-        double acc = 0.0;
-        int t = g;
-        for (; t + 3 * G < cnt; t += 4 * G) {
-            const double a0 = src[(size_t)t * len + q];
-            const double a1 = src[(size_t)(t + G) * len + q];
-            const double a2 = src[(size_t)(t + 2 * G) * len + q];
-            const double a3 = src[(size_t)(t + 3 * G) * len + q];
-            acc += a0;
-            acc += a1;
-            acc += a2;
-            acc += a3;
-        }
-        for (; t < cnt; t += G) acc += src[(size_t)t * len + q];
-        scratch[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < len) {
-        double acc = 0.0;
-        for (int gg = 0; gg < G; ++gg) acc += scratch[gg * len + threadIdx.x];
-        out[threadIdx.x] = acc;
-    }
-    __syncthreads();
+    const double acc = records_partial(src, cnt, len, (int)threadIdx.x, (int)blockDim.x);
+    records_finish(acc, len, 0, (int)blockDim.x, out, scratch);
 }
 
 // Sums V values per thread over a block of NTHR threads: wave transpose-reduce

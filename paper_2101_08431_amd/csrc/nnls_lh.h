@@ -46,13 +46,27 @@ __device__ __forceinline__ void put(double (&v)[K], int idx, double val) {
         if (a == idx) v[a] = val;
 }
 
+// 1/sqrt(v) for a normal v > 0: the hardware estimate (v_rsq_f64) refined by
+// two Newton steps y <- y + (y/2)(1 - v y^2), each of which squares the
+// relative error, so the result is within a few ulp.  Its dependent chain is
+// about a third of a correctly rounded sqrt followed by a division.
+__device__ __forceinline__ double rsqrt_newton(double v) {
+    double y = __builtin_amdgcn_rsq(v);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-v * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 // z = (G masked to P)^-1 (b masked to P).  Returns false if a pivot on P is
-// not positive.  The factor keeps the reciprocals of its diagonal, so a solve
-// costs K divisions.
+// not positive.  The factor keeps only the reciprocals of its diagonal (the
+// solves multiply by them), taken as reciprocal square roots of the pivots.
 template <int K>
 __device__ __forceinline__ bool masked_solve(const double *G, const double (&b)[K], uint32_t P,
                                              double (&z)[K]) {
-    double L[K * (K + 1) / 2];
+    double L[K * (K + 1) / 2];   // off-diagonal entries only are read
     double inv[K];
     bool ok = true;
 #pragma unroll
@@ -66,9 +80,7 @@ __device__ __forceinline__ bool masked_solve(const double *G, const double (&b)[
             for (int q = 0; q < c; ++q) v -= L[r * (r + 1) / 2 + q] * L[c * (c + 1) / 2 + q];
             if (r == c) {
                 ok = ok && (v > 0.0);
-                const double d = sqrt(v > 0.0 ? v : 1.0);
-                L[r * (r + 1) / 2 + r] = d;
-                inv[r] = 1.0 / d;
+                inv[r] = rsqrt_newton(v > 0.0 ? v : 1.0);
             } else {
                 L[r * (r + 1) / 2 + c] = v * inv[c];
             }

@@ -132,3 +132,45 @@ def test_append_rearms_the_sweep_budget():
     ctx.set_anls_budget(5)
     st, rep = ctx.anls_step(20)
     assert st == 1 and rep["sweeps"] == 19
+
+
+def test_batch_many_groups_mixed_halves_with_polls():
+    # seven K groups in one batch (their offset tables together exceed one
+    # entry per problem), problems whose halves run split, fused or mixed,
+    # and a poll between every step: each problem still ends bitwise where
+    # its standalone sweeps end
+    import torch
+    from paper_2101_08431_amd import Batch
+    rng = np.random.default_rng(10400)
+    probs, shapes = [], []
+    for q in range(9):
+        k = 2 + q % 7
+        n, m = (1500, 300) if q % 3 == 0 else (int(rng.integers(100, 600)), int(rng.integers(20, 120)))
+        M, X0, Y0 = synth.make(dict(kind="pdf", n=n, m=m, k=k, sigma=1e-3, sigma_relative=True), 10400 + q)
+        probs.append((M, X0, Y0, k))
+        shapes.append([None, (1, 2), (2, 1)][q % 3])
+    print("case batch of 9 problems over 7 K groups, split / fused / mixed halves", flush=True)
+
+    def make():
+        cs = contexts(probs)
+        for c, sh in zip(cs, shapes):
+            if sh is not None:
+                c.set_launch_shape(*sh)
+        return cs
+
+    solo = make()
+    for c in solo:
+        c.anls_step(9, report=False)
+    torch.cuda.synchronize()
+    ctxs = make()
+    b = Batch(ctxs)
+    for _ in range(3):
+        b.step(3, graph=False)
+        conv, sweeps = b.poll()
+        assert not conv.any()
+    assert (sweeps == 9).all()
+    torch.cuda.synchronize()
+    for c, s in zip(ctxs, solo):
+        assert np.array_equal(c.factors()[0], s.factors()[0])
+        assert np.array_equal(c.factors()[1], s.factors()[1])
+    b.close()
