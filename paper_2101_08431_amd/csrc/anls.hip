@@ -57,10 +57,17 @@ __device__ __forceinline__ void block_stats_and_gram(const double (&st)[NST], co
     }
 #pragma unroll
     for (int pass = 0; pass < NPASS; ++pass) {
-        double v[YVALS];
+        if constexpr (V <= 32) {
+            double v[32];
 #pragma unroll
-        for (int q = 0; q < YVALS; ++q) v[q] = vals[pass * YVALS + q];
-        lds[w * YVALS + lane] = wave_transpose_reduce(v, lane);
+            for (int q = 0; q < 32; ++q) v[q] = vals[q];
+            lds[w * YVALS + lane] = wave_transpose_reduce32(v, lane);
+        } else {
+            double v[YVALS];
+#pragma unroll
+            for (int q = 0; q < YVALS; ++q) v[q] = vals[pass * YVALS + q];
+            lds[w * YVALS + lane] = wave_transpose_reduce(v, lane);
+        }
         __syncthreads();
         const int idx = pass * YVALS + (int)threadIdx.x;
         if ((int)threadIdx.x < YVALS && idx < V) {
@@ -205,15 +212,18 @@ __device__ __forceinline__ void wave_stats_and_gram(const double (&st)[NST], con
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int pass = 0; pass < NPASS; ++pass) {
-        double v[YVALS];
+        constexpr int W = V <= 32 ? 32 : YVALS;
+        double v[W];
 #pragma unroll
-        for (int q = 0; q < YVALS; ++q) {
+        for (int q = 0; q < W; ++q) {
             const int idx = pass * YVALS + q;
             if (idx < NG) v[q] = xn[tri_row(idx)] * xn[tri_col(idx)];
             else if (idx < V) v[q] = st[idx - NG];
             else v[q] = 0.0;
         }
-        const double sum = wave_transpose_reduce(v, lane);
+        double sum;
+        if constexpr (W == 32) sum = wave_transpose_reduce32(v, lane);
+        else sum = wave_transpose_reduce(v, lane);
         const int idx = pass * YVALS + lane;
         if (idx < V) {
             if (idx >= NG) {
@@ -504,22 +514,20 @@ __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
 // Streams the rows [r0, r1) of the tile's J = 64 / K columns of M against X
 // and leaves each wave's transpose-reduced sums in red[w * YVALS + lane]
 // (value jj * K + a is B_Y[a][jb + jj]); ends with a barrier.  With `stop`
-// set the block returns false before any arithmetic.  When registers allow
-// (K + J <= 17) the loads of each row run one row ahead of the arithmetic and
-// the first row's loads go out together with the caller's stop flag.
+// set the block returns false before any load.  (Loading the next row ahead
+// of the arithmetic, or the first row before the stop test, measured slower:
+// the extra registers cost more than the overlap gains.)
 template <int K, int P>
 __device__ __forceinline__ bool ystream_sums(const AnlsParams &p, int ct, int64_t r0, int64_t r1, double *red,
                                              bool stop) {
     using T = typename MElem<P>::T;
     constexpr int J = YVALS / K;
-    constexpr bool AHEAD = K + J <= 17;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t jb = (int64_t)ct * J;
     const int nj = (int)min((int64_t)J, p.m - jb);
 
-    // a row's loads, with no branch between them: rows past r1 load row
-    // r1 - 1 (never accumulated) and columns past the tile's last load its
-    // last column and are zeroed
+    // a row's loads, with no branch between them: columns past the tile's
+    // last load its last column and are zeroed
     auto load_row = [&](int64_t i, T (&x)[K], T (&mv)[J]) {
         const int64_t ic = i < r1 ? i : r1 - 1;
         const int64_t base = jb * p.ldM + ic;
@@ -535,34 +543,14 @@ __device__ __forceinline__ bool ystream_sums(const AnlsParams &p, int ct, int64_
     T v[YVALS];
 #pragma unroll
     for (int q = 0; q < YVALS; ++q) v[q] = T(0);
-    const int64_t i0 = r0 + threadIdx.x;
-    if constexpr (AHEAD) {
+    if (stop) return false;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += STHR) {
         T x[K], mv[J];
-        load_row(i0, x, mv);
-        if (stop) return false;
-        for (int64_t i = i0; i < r1; i += STHR) {
-            T xn[K], mn[J];
-            load_row(i + STHR, xn, mn);
+        load_row(i, x, mv);
 #pragma unroll
-            for (int jj = 0; jj < J; ++jj) {
+        for (int jj = 0; jj < J; ++jj) {
 #pragma unroll
-                for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
-            }
-#pragma unroll
-            for (int a = 0; a < K; ++a) x[a] = xn[a];
-#pragma unroll
-            for (int jj = 0; jj < J; ++jj) mv[jj] = mn[jj];
-        }
-    } else {
-        if (stop) return false;
-        for (int64_t i = i0; i < r1; i += STHR) {
-            T x[K], mv[J];
-            load_row(i, x, mv);
-#pragma unroll
-            for (int jj = 0; jj < J; ++jj) {
-#pragma unroll
-                for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
-            }
+            for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
         }
     }
     red[w * YVALS + lane] = (double)wave_transpose_reduce(v, lane);
@@ -697,13 +685,23 @@ __global__ __launch_bounds__(NTHR) void k_ynnls(AnlsParams p) { ynnls_body<K>(p,
 
 // A batch of problems with the same K and precision: one flattened grid, block
 // b belongs to the problem q with off[q] <= b < off[q + 1] and runs that
-// problem's block b - off[q] of its own launch shape.
+// problem's block b - off[q] of its own launch shape.  off is non-decreasing
+// with off[0] = 0, so q is the last index with off[q] <= b (problems without
+// blocks in this kernel are skipped).  Each wave finds it on its own: 64 lanes
+// probe 64 evenly spaced entries of the remaining range and a ballot keeps
+// the last probe that is <= b, so np <= 64 takes one load per lane and
+// np <= 4096 two, where a binary search would chain log2(np) loads.
 __device__ __forceinline__ int batch_problem(const int *off, int np, int b) {
-    int lo = 0, hi = np - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= b) lo = mid;
-        else hi = mid - 1;
+    const int lane = threadIdx.x & 63;
+    int lo = 0, span = np;   // the answer is in [lo, lo + span); off[lo] <= b
+    while (span > 1) {
+        const int step = (span + 63) / 64;
+        const int idx = lo + lane * step;
+        const bool ok = idx < lo + span && off[idx < np ? idx : np - 1] <= b;
+        const unsigned long long mask = __ballot(ok);
+        const int last = 63 - __clzll((long long)mask);   // lane 0 always probes off[lo] <= b
+        lo += last * step;
+        span = min(step, span - last * step);
     }
     return lo;
 }

@@ -27,8 +27,9 @@ __device__ __forceinline__ bool last_arrival(unsigned *cnt, unsigned expected, u
 
 // One butterfly step: lanes that differ in bit H swap halves of v[0..2H) and
 // keep the sum of the half named by their bit.
-template <int H, class T>
-__device__ __forceinline__ void transpose_step(T (&v)[YVALS], int lane) {
+template <int H, int N, class T>
+__device__ __forceinline__ void transpose_step(T (&v)[N], int lane) {
+    static_assert(2 * H <= N, "step wider than the vector");
     const bool up = (lane & H) != 0;
 #pragma unroll
     for (int q = 0; q < H; ++q) {
@@ -48,6 +49,19 @@ __device__ __forceinline__ T wave_transpose_reduce(T (&v)[YVALS], int lane) {
     transpose_step<2>(v, lane);
     transpose_step<1>(v, lane);
     return v[0];
+}
+
+// The same for 32 values: lanes l and l + 32 end up with the sum over the 64
+// lanes of v[l mod 32] (31 exchanges within each half of the wave and one
+// across, instead of 63).
+template <class T>
+__device__ __forceinline__ T wave_transpose_reduce32(T (&v)[32], int lane) {
+    transpose_step<16>(v, lane);
+    transpose_step<8>(v, lane);
+    transpose_step<4>(v, lane);
+    transpose_step<2>(v, lane);
+    transpose_step<1>(v, lane);
+    return v[0] + __shfl_xor((double)v[0], 32, 64);
 }
 
 // Fixed-order sum of `cnt` records of `len` doubles (stride `len`) into
