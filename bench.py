@@ -126,16 +126,17 @@ def measured_traffic(kernel, shape, workload):
 
 def roofline(ctx, n, m, k, shape, workload, sweeps=100):
     """Per-kernel device times from the library's event profiler and the
-    algorithmic bytes of each kernel; a half with a single split runs as one
-    kernel (k_xfused / k_yfused) that moves the bytes of both of its steps."""
+    algorithmic bytes of each kernel; shape is the launch plan (x splits,
+    y splits, X one kernel, Y one kernel).  A half run as one kernel
+    (k_xfused / k_yfused) moves the bytes of both of its steps."""
     ms = ctx.anls_profile(sweeps)
     by = algorithmic_bytes(n, m, k)
     per = {}
-    if shape[0] == 1:
+    if shape[2]:
         per["k_xfused"] = (ms[0] + ms[1], by[0] + by[1])
     else:
         per["k_xstream"], per["k_xnnls"] = (ms[0], by[0]), (ms[1], by[1])
-    if shape[1] == 1:
+    if shape[3]:
         per["k_yfused"] = (ms[2] + ms[3], by[2] + by[3])
     else:
         per["k_ystream"], per["k_ynnls"] = (ms[2], by[2]), (ms[3], by[3])
@@ -144,7 +145,7 @@ def roofline(ctx, n, m, k, shape, workload, sweeps=100):
     ach = per[dom]["GBs"]
     return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(dom, shape, workload),
-            "bytes_per_launch": per[dom]["bytes"], "launch_shape": list(shape), "per_kernel": per}
+            "bytes_per_launch": per[dom]["bytes"], "launch_plan": list(shape), "per_kernel": per}
 
 
 def full_solve(name, seeds, tol, cap):
@@ -324,10 +325,13 @@ def main():
     ap.add_argument("--no-layers", action="store_true", help="skip the precision and batching sections")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the serving arrival trace")
-    ap.add_argument("--shape", default=None, metavar="XS,YS",
-                    help="fix the stage-1 launch shape (x splits, y splits) instead of autotuning it")
+    ap.add_argument("--shape", default=None, metavar="XS,YS[,FX,FY]",
+                    help="fix the stage-1 launch plan (x splits, y splits[, X-half one kernel, Y-half one "
+                         "kernel: 1, 0 or -1 = automatic]) instead of autotuning it")
     ap.add_argument("--ipm-only", action="store_true",
                     help="only time stage-2 iterations on the headline workload (for profiling)")
+    ap.add_argument("--batching-only", action="store_true",
+                    help="only run the batching section (256 problems, for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -351,19 +355,25 @@ def main():
     if args.ipm_only:
         print(json.dumps(ipm_section(args.workload)), flush=True)
         return
+    if args.batching_only:
+        print(json.dumps(batching_section(256, 20)), flush=True)
+        return
     M, X0, Y0 = synth.make(args.workload, 0)
     n, m = M.shape
     k = X0.shape[1]
     ctx = make_ctx(M, X0, Y0, k)
     from paper_2101_08431_amd import autotune
     if args.shape:
-        shape = tuple(int(v) for v in args.shape.split(","))
-        ctx.set_launch_shape(*shape)
-        log(f"launch shape (x splits, y splits) = {shape}, fixed")
+        vals = [int(v) for v in args.shape.split(",")]
+        ctx.set_launch_shape(vals[0], vals[1])
+        if len(vals) == 4:
+            ctx.set_launch_fusion(vals[2], vals[3])
+        log(f"launch plan (x splits, y splits, X one kernel, Y one kernel) = {ctx.launch_plan()}, fixed")
     else:
-        shape = autotune.tune_single(ctx, use_cache=False)
-        log(f"autotuned launch shape (x splits, y splits) = {shape}; fastest: "
-            + ", ".join(f"{kk}: {v * 1e3:.1f} us" for kk, v in list(autotune.last_timings.items())[:6]))
+        autotune.tune_single(ctx, use_cache=False)
+        log(f"autotuned launch plan (x splits, y splits, X one kernel, Y one kernel) = {ctx.launch_plan()}; "
+            "fastest: " + ", ".join(f"{kk}: {v * 1e3:.1f} us" for kk, v in list(autotune.last_timings.items())[:6]))
+    shape = ctx.launch_plan()
     ms_graph, wall_ms = time_graph_sweeps(ctx, args.steps, args.warmup)
     ms_eager = time_eager_sweeps(ctx, args.steps, args.warmup)
     mode = "graph" if ms_graph <= ms_eager else "eager"
@@ -376,10 +386,12 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "k": k,
-                   "step": "one ANLS sweep (4 kernels: X stream, row NNLS, Y stream, column NNLS), "
-                           "n + m NNLS solves",
+                   "step": "one ANLS sweep (X stream + row NNLS, then Y stream + column NNLS, each half "
+                           "two kernels or one), n + m NNLS solves",
                    "launch": mode, "graph_ms_per_step": ms_graph, "eager_ms_per_step": ms_eager,
-                   "graph_wall_ms_timed": wall_ms, "launch_shape": list(shape)},
+                   "graph_wall_ms_timed": wall_ms,
+                   "launch_plan": {"x_splits": shape[0], "y_splits": shape[1], "x_one_kernel": shape[2],
+                                   "y_one_kernel": shape[3]}},
         "roofline": rl,
         "nnls_solves_per_problem": rep["nnls_solves"] / max(1, rep["sweeps"] * (n + m)),
     }

@@ -188,6 +188,21 @@ nmf_status nmf_anls_profile(nmf_ctx *ctx, int32_t sweeps, double *ms);
  * autotuner. */
 nmf_status nmf_set_launch_shape(nmf_ctx *ctx, int32_t x_splits, int32_t y_splits);
 
+/* Chooses how each stage-1 half is launched (Alg. 1 runs the X-half, then the
+ * Y-half): 1 = one kernel (every split of a tile streams its share of M; the
+ * last split of the tile to finish, found by a per-tile counter, sums the
+ * partials in split order and solves the tile's rows or columns), 0 = a
+ * streaming kernel followed by an NNLS kernel, -1 = automatic (one kernel
+ * exactly when the half has a single split; the default).  Results do not
+ * change beyond the rounding of the sums.  Synchronises (the Gram partial
+ * sums are rebuilt).  NMF_EINVAL for other values.  Used by the autotuner. */
+nmf_status nmf_set_launch_fusion(nmf_ctx *ctx, int32_t fuse_x, int32_t fuse_y);
+
+/* The stage-1 launch plan in effect: out4 = {x splits, y splits, X-half is one
+ * kernel (0/1), Y-half is one kernel (0/1)}.  out4 is host memory owned by the
+ * caller. */
+nmf_status nmf_get_launch_shape(const nmf_ctx *ctx, int32_t *out4);
+
 /* Sets the stage-1 sweep budget (options.max_anls_sweeps, >= 1) used from now
  * on, and re-arms the stop rule of Sec. IV: the next sweeps run until it holds
  * again or `max_sweeps` more sweeps are done.  Every later

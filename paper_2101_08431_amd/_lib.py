@@ -22,7 +22,7 @@ EXPORTS = [
     "nmf_default_options", "nmf_workspace_bytes", "nmf_create", "nmf_anls_step", "nmf_ipm_step",
     "nmf_solve", "nmf_append_columns", "nmf_get_factors", "nmf_get_masks", "nmf_get_report",
     "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
-    "nmf_get_duals", "nmf_set_launch_shape", "nmf_set_anls_budget", "nmf_batch_workspace_bytes", "nmf_batch_create",
+    "nmf_get_duals", "nmf_set_launch_shape", "nmf_set_launch_fusion", "nmf_get_launch_shape", "nmf_set_anls_budget", "nmf_batch_workspace_bytes", "nmf_batch_create",
     "nmf_batch_refresh", "nmf_batch_anls_step", "nmf_batch_poll", "nmf_batch_sync", "nmf_batch_destroy",
 ]
 
@@ -99,6 +99,10 @@ def load():
     L.nmf_anls_profile.restype = ctypes.c_int
     L.nmf_set_launch_shape.argtypes = [vp, i32, i32]
     L.nmf_set_launch_shape.restype = ctypes.c_int
+    L.nmf_set_launch_fusion.argtypes = [vp, i32, i32]
+    L.nmf_set_launch_fusion.restype = ctypes.c_int
+    L.nmf_get_launch_shape.argtypes = [vp, vp]
+    L.nmf_get_launch_shape.restype = ctypes.c_int
     L.nmf_set_anls_budget.argtypes = [vp, i32]
     L.nmf_set_anls_budget.restype = ctypes.c_int
     L.nmf_batch_workspace_bytes.argtypes = [i32]
@@ -276,6 +280,17 @@ class NMF:
 
     def set_launch_shape(self, x_splits, y_splits):
         self._check(load().nmf_set_launch_shape(self._ctx, int(x_splits), int(y_splits)), ok=(NMF_OK,))
+
+    def set_launch_fusion(self, fuse_x, fuse_y):
+        """1: the half is one kernel (the tile's last split solves), 0: stream +
+        NNLS kernels, -1: one kernel exactly when the half has a single split."""
+        self._check(load().nmf_set_launch_fusion(self._ctx, int(fuse_x), int(fuse_y)), ok=(NMF_OK,))
+
+    def launch_plan(self):
+        """(x splits, y splits, X-half one kernel, Y-half one kernel) in effect."""
+        out = (ctypes.c_int32 * 4)()
+        self._check(load().nmf_get_launch_shape(self._ctx, out), ok=(NMF_OK,))
+        return int(out[0]), int(out[1]), bool(out[2]), bool(out[3])
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -58,39 +58,62 @@ def splits_for_waves(n, m, k, waves):
     return min(xs, m), min(ys, n)
 
 
+FUSE_KMAX = 7   # above this rank the one-kernel halves spill registers
+
+
+def _apply_single(ctx, xs, ys, fx, fy):
+    ctx.set_launch_shape(xs, ys)
+    ctx.set_launch_fusion(fx, fy)
+
+
 def tune_single(ctx, xs_cands=(1, 2, 4, 8, 11, 16), ys_cands=(1, 2, 3, 4, 6), sweeps=30, use_cache=True):
-    """Pick (x_splits, y_splits) for one context by timing back-to-back sweeps
-    of each candidate shape (a single split makes that half one fused kernel);
-    returns the choice and sets it.  The sweeps advance the factorisation, so
-    tune a context whose stop rule cannot hold yet (or a copy of one)."""
-    key = f"single:{ctx.n}:{ctx.m}:{ctx.k}:{int(ctx.options.gram_precision)}"
+    """Pick the stage-1 launch plan of one context, (x_splits, y_splits,
+    fuse_x, fuse_y), by timing back-to-back sweeps of each candidate: every
+    split pair with the automatic kernel split (one kernel per half exactly at
+    a single split) and, for ranks up to FUSE_KMAX, with each half forced into
+    one kernel.  Returns the choice and sets it.  The sweeps advance the
+    factorisation, so tune a context whose stop rule cannot hold yet (or a
+    copy of one)."""
+    key = f"single2:{ctx.n}:{ctx.m}:{ctx.k}:{int(ctx.options.gram_precision)}"
     cache = _load() if use_cache else {}
     if key in cache:
-        xs, ys = cache[key]["choice"]
-        ctx.set_launch_shape(xs, ys)
-        return tuple(cache[key]["choice"])
+        choice = tuple(cache[key]["choice"])
+        _apply_single(ctx, *choice)
+        return choice
     import torch
+    fusions = [(-1, -1)] + ([(1, -1), (-1, 1), (1, 1)] if ctx.k <= FUSE_KMAX else [])
     timings = {}
     for xs in xs_cands:
         for ys in ys_cands:
-            ctx.set_launch_shape(xs, ys)
-            ctx.anls_step(3, report=False)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(ctx.stream)
-            ctx.anls_step(sweeps, report=False)
-            e1.record(ctx.stream)
-            e1.synchronize()
-            timings[(xs, ys)] = e0.elapsed_time(e1) / sweeps
-    best = min(timings, key=timings.get)
-    ctx.set_launch_shape(*best)
+            for fx, fy in fusions:
+                _apply_single(ctx, xs, ys, fx, fy)
+                plan = ctx.launch_plan()
+                if any(plan == ctx_plan for ctx_plan, _ in timings.values()):
+                    continue   # the same launch plan as an earlier candidate
+                ctx.anls_step(3, report=False)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(ctx.stream)
+                ctx.anls_step(sweeps, report=False)
+                e1.record(ctx.stream)
+                e1.synchronize()
+                timings[(xs, ys, fx, fy)] = (plan, e0.elapsed_time(e1) / sweeps)
+    best = min(timings, key=lambda c: timings[c][1])
+    _apply_single(ctx, *best)
     global last_timings
-    last_timings = {f"{a},{b}": v for (a, b), v in sorted(timings.items(), key=lambda kv: kv[1])}
+    last_timings = {_label(timings[c][0]): timings[c][1] for c in sorted(timings, key=lambda c: timings[c][1])}
     cache = _load()
-    cache[key] = {"choice": list(best), "ms": timings[best],
-                  "tried": {f"{a},{b}": v for (a, b), v in timings.items()}}
+    cache[key] = {"choice": list(best), "ms": timings[best][1],
+                  "tried": {_label(p): t for p, t in timings.values()}}
     _store(cache)
     return best
+
+
+def _label(plan):
+    """'xs,ys' plus the halves that run as one kernel, e.g. '8,3 fused x'."""
+    xs, ys, fx, fy = plan
+    tag = {(False, False): "", (True, False): " fused x", (False, True): " fused y", (True, True): " fused x,y"}
+    return f"{xs},{ys}{tag[(fx, fy)]}"
 
 
 def tune_batch(batch, waves_cands=(256, 512, 1024, 2048, 4096), sweeps=10, use_cache=True):

@@ -413,43 +413,6 @@ __device__ __forceinline__ void xstream_body(const AnlsParams &p, int tile, int 
     }
 }
 
-// The whole X-half when the X stream has a single column split: the tile's 64
-// rows of B_X are complete after the stream, so the first wave solves them
-// (one row per lane) and writes the tile's statistics and G_X record (the
-// X-side records then number Rx = Tn).
-template <int K, int P>
-__device__ __forceinline__ void xfused_body(const AnlsParams &p, int tile, double *lds) {
-    const bool stop = sweep_stopped(p);
-    __shared__ double G[K * K];
-    __shared__ double scr[STHR];
-    const double gacc = records_partial(p.gy_part, p.Ry, K * K, (int)threadIdx.x, STHR);
-    if (!xstream_sums<K, P>(p, tile, 0, p.m, lds, stop)) return;
-    records_finish(gacc, K * K, 0, STHR, G, scr);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (w != 0) return;
-    const int64_t i = (int64_t)tile * XTILE + lane;
-    const bool live = i < p.n;
-    double b[K], x[K], st[NST], xn[K];
-    uint32_t old_mask = 0u;
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-        double v = lds[(0 * K + a) * XTILE + lane];
-#pragma unroll
-        for (int ww = 1; ww < SWAVES; ++ww) v += lds[(ww * K + a) * XTILE + lane];
-        b[a] = 0.0 + v;
-        x[a] = live ? p.X[(int64_t)a * p.ldX + i] : 0.0;
-        xn[a] = 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < NST; ++q) st[q] = 0.0;
-    if (live) {
-        old_mask = p.xmask[i];
-        x_row<K>(p, G, i, x, b, old_mask, st, xn);
-    }
-    wave_stats_and_gram<K>(st, xn, p.xstat + (int64_t)tile * NST,
-                           p.mode == 0 ? p.gx_part + (int64_t)tile * K * K : nullptr);
-}
-
 // Splits of the B partials summed per row (column), in split order; SB splits
 // (SB * K loads) are in flight at a time and splits past S read as zero.
 template <int K>
@@ -476,6 +439,82 @@ __device__ __forceinline__ void sum_split_partials(const double *part, int64_t l
             for (int a = 0; a < K; ++a) b[a] += (s0 + u < S) ? t[u][a] : 0.0;
         }
     }
+}
+
+// Sum over the S splits of part[s * stride], in split order, with up to 16
+// loads in flight (splits past S re-read split S - 1 and are dropped).
+__device__ __forceinline__ double sum_strided(const double *part, int64_t stride, int S) {
+    constexpr int SB = 16;
+    double acc = 0.0;
+    for (int s0 = 0; s0 < S; s0 += SB) {
+        double t[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) t[u] = part[(int64_t)(s0 + u < S ? s0 + u : S - 1) * stride];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) acc += (s0 + u < S) ? t[u] : 0.0;
+    }
+    return acc;
+}
+
+// The whole X-half in one kernel (grid Tn tiles x Sx column splits): every
+// block streams its split of the tile's 64 rows.  With one split the tile's
+// rows of B_X are complete after the stream; with several, each block stores
+// its partial and the tile's last block to arrive (per-tile counter) sums the
+// partials in split order.  That block's first wave then solves the rows (one
+// per lane) and writes the tile's statistics and G_X record (the X-side
+// records number Rx = Tn).
+template <int K, int P>
+__device__ __forceinline__ void xfused_body(const AnlsParams &p, int tile, int split, double *lds) {
+    const bool stop = sweep_stopped(p);
+    __shared__ double G[K * K];
+    __shared__ double scr[STHR];
+    __shared__ unsigned flag;
+    const double gacc = records_partial(p.gy_part, p.Ry, K * K, (int)threadIdx.x, STHR);
+    const int64_t j0 = (int64_t)split * p.xcols;
+    const int64_t j1 = min(j0 + (int64_t)p.xcols, p.m);
+    if (!xstream_sums<K, P>(p, tile, j0, j1, lds, stop)) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)tile * XTILE + lane;
+    const bool live = i < p.n;
+    const int64_t ic = live ? i : p.n - 1;
+    double b[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) b[a] = 0.0;
+    if (p.Sx > 1) {
+        if (w == 0 && live) {
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                double v = lds[(0 * K + a) * XTILE + lane];
+#pragma unroll
+                for (int ww = 1; ww < SWAVES; ++ww) v += lds[(ww * K + a) * XTILE + lane];
+                p.bx_part[((int64_t)split * K + a) * p.ldX + i] = v;
+            }
+        }
+        if (!last_arrival(p.tile_cnt + tile, (unsigned)p.Sx, &flag)) return;
+        if (w == 0) sum_split_partials<K>(p.bx_part, p.ldX, ic, p.Sx, b);
+    } else if (w == 0) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            double v = lds[(0 * K + a) * XTILE + lane];
+#pragma unroll
+            for (int ww = 1; ww < SWAVES; ++ww) v += lds[(ww * K + a) * XTILE + lane];
+            b[a] = 0.0 + v;
+        }
+    }
+    records_finish(gacc, K * K, 0, STHR, G, scr);
+    if (w != 0) return;
+    double x[K], st[NST], xn[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        x[a] = p.X[(int64_t)a * p.ldX + ic];
+        xn[a] = 0.0;
+    }
+    const uint32_t old_mask = p.xmask[ic];
+#pragma unroll
+    for (int q = 0; q < NST; ++q) st[q] = 0.0;
+    if (live) x_row<K>(p, G, i, x, b, old_mask, st, xn);
+    wave_stats_and_gram<K>(st, xn, p.xstat + (int64_t)tile * NST,
+                           p.mode == 0 ? p.gx_part + (int64_t)tile * K * K : nullptr);
 }
 
 template <int K>
@@ -578,13 +617,16 @@ __device__ __forceinline__ void ystream_body(const AnlsParams &p, int ct, int sp
     }
 }
 
-// The whole Y-half when the Y stream has a single row split: the tile's J
-// columns of B_Y are complete after the stream, so the first wave solves them
-// (one column per lane), writes the tile's statistics and G_Y record (the
-// Y-side records then number Ry = Tm), and the tile that finishes last closes
-// the sweep.
+// The whole Y-half in one kernel (grid Tm tiles x Sy row splits): every block
+// streams its split of the tile's J columns.  With one split the tile's
+// columns of B_Y are complete after the stream; with several, each block
+// stores its partial and the tile's last block to arrive (per-tile counter)
+// sums the partials in split order.  That block's first wave then solves the
+// columns (one per lane), writes the tile's statistics and G_Y record (the
+// Y-side records number Ry = Tm), and the tile that finishes last closes the
+// sweep.
 template <int K, int P>
-__device__ __forceinline__ void yfused_body(const AnlsParams &p, int ct) {
+__device__ __forceinline__ void yfused_body(const AnlsParams &p, int ct, int split) {
     const bool stop = sweep_stopped(p);
     constexpr int J = YVALS / K;
     __shared__ double red[SWAVES * YVALS];
@@ -593,17 +635,32 @@ __device__ __forceinline__ void yfused_body(const AnlsParams &p, int ct) {
     __shared__ double bsum[YVALS];
     __shared__ unsigned flag;
     const double gacc = records_partial(p.gx_part, p.Rx, K * K, (int)threadIdx.x, STHR);
-    if (!ystream_sums<K, P>(p, ct, 0, p.n, red, stop)) return;
-    records_finish(gacc, K * K, 0, STHR, G, scr);
+    const int64_t r0 = (int64_t)split * p.yrows;
+    const int64_t r1 = min(r0 + (int64_t)p.yrows, p.n);
+    if (!ystream_sums<K, P>(p, ct, r0, r1, red, stop)) return;
     const int64_t jb = (int64_t)ct * J;
     const int nj = (int)min((int64_t)J, p.m - jb);
-    if ((int)threadIdx.x < nj * K) {
-        double s = red[threadIdx.x];
+    const int t = (int)threadIdx.x;
+    if (p.Sy > 1) {
+        if (t < nj * K) {
+            double s = red[t];
 #pragma unroll
-        for (int ww = 1; ww < SWAVES; ++ww) s += red[ww * YVALS + threadIdx.x];
-        bsum[threadIdx.x] = s;
+            for (int ww = 1; ww < SWAVES; ++ww) s += red[ww * YVALS + t];
+            const int jj = t / K, a = t - jj * K;
+            p.by_part[((int64_t)split * K + a) * p.ldY + jb + jj] = s;
+        }
+        if (!last_arrival(p.tile_cnt + p.Tn + ct, (unsigned)p.Sy, &flag)) return;
+        if (t < nj * K) {
+            const int jj = t / K, a = t - jj * K;
+            bsum[t] = sum_strided(p.by_part + (int64_t)a * p.ldY + jb + jj, (int64_t)K * p.ldY, p.Sy);
+        }
+    } else if (t < nj * K) {
+        double s = red[t];
+#pragma unroll
+        for (int ww = 1; ww < SWAVES; ++ww) s += red[ww * YVALS + t];
+        bsum[t] = 0.0 + s;
     }
-    __syncthreads();
+    records_finish(gacc, K * K, 0, STHR, G, scr);   // its barriers also publish bsum
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (w == 0) {
         const bool live = lane < nj;
@@ -612,7 +669,7 @@ __device__ __forceinline__ void yfused_body(const AnlsParams &p, int ct) {
         uint32_t old_mask = 0u;
 #pragma unroll
         for (int a = 0; a < K; ++a) {
-            b[a] = live ? 0.0 + bsum[lane * K + a] : 0.0;
+            b[a] = live ? bsum[lane * K + a] : 0.0;
             y[a] = live ? p.Y[(int64_t)a * p.ldY + j] : 0.0;
             yn[a] = 0.0;
         }
@@ -672,10 +729,10 @@ __global__ __launch_bounds__(STHR) void k_xstream(AnlsParams p) {
 template <int K, int P>
 __global__ __launch_bounds__(STHR) void k_xfused(AnlsParams p) {
     __shared__ double lds[xstream_lds<K>()];
-    xfused_body<K, P>(p, blockIdx.x, lds);
+    xfused_body<K, P>(p, blockIdx.x, blockIdx.y, lds);
 }
 template <int K, int P>
-__global__ __launch_bounds__(STHR) void k_yfused(AnlsParams p) { yfused_body<K, P>(p, blockIdx.x); }
+__global__ __launch_bounds__(STHR) void k_yfused(AnlsParams p) { yfused_body<K, P>(p, blockIdx.x, blockIdx.y); }
 template <int K>
 __global__ __launch_bounds__(NTHR) void k_xnnls(AnlsParams p) { xnnls_body<K>(p, blockIdx.x); }
 template <int K, int P>
@@ -719,7 +776,8 @@ __global__ __launch_bounds__(STHR) void kb_xfused(const AnlsParams *tab, const i
     const int q = batch_problem(off, np, blockIdx.x);
     const AnlsParams p = tab[q];
     __shared__ double lds[xstream_lds<K>()];
-    xfused_body<K, P>(p, blockIdx.x - off[q], lds);
+    const int local = blockIdx.x - off[q];
+    xfused_body<K, P>(p, local % p.Tn, local / p.Tn, lds);
 }
 template <int K>
 __global__ __launch_bounds__(NTHR) void kb_xnnls(const AnlsParams *tab, const int *off, int np) {
@@ -738,7 +796,8 @@ template <int K, int P>
 __global__ __launch_bounds__(STHR) void kb_yfused(const AnlsParams *tab, const int *off, int np) {
     const int q = batch_problem(off, np, blockIdx.x);
     const AnlsParams p = tab[q];
-    yfused_body<K, P>(p, blockIdx.x - off[q]);
+    const int local = blockIdx.x - off[q];
+    yfused_body<K, P>(p, local % p.Tm, local / p.Tm);
 }
 template <int K>
 __global__ __launch_bounds__(NTHR) void kb_ynnls(const AnlsParams *tab, const int *off, int np) {
@@ -979,8 +1038,8 @@ __global__ void k_batch_poll(const AnlsParams *table, int count, long long *out)
 int yhalf_cols(int K) { return K >= 1 && K <= KMAX ? YVALS / K : 0; }
 
 hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (p.Sx == 1) {   // stream and solve in one kernel
-        const dim3 g(p.Tn);
+    if (p.fx) {   // stream and solve in one kernel
+        const dim3 g(p.Tn, p.Sx);
         if (p.prec == NMF_GRAM_FP32) {
             NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_xfused<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, e0, e1, 0, p));
         } else if (p.prec == NMF_GRAM_BF16X2) {
@@ -1002,14 +1061,14 @@ hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t 
 }
 
 hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (p.Sx == 1) return hipSuccess;   // solved inside k_xfused
+    if (p.fx) return hipSuccess;   // solved inside k_xfused
     NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_xnnls<KK>, dim3(p.Bx), dim3(NTHR), 0, s, e0, e1, 0, p));
     return hipGetLastError();
 }
 
 hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (p.Sy == 1) {   // stream and solve in one kernel
-        const dim3 g(p.Tm);
+    if (p.fy) {   // stream and solve in one kernel
+        const dim3 g(p.Tm, p.Sy);
         if (p.prec == NMF_GRAM_FP32) {
             NMF_K_SWITCH(K, hipExtLaunchKernelGGL((k_yfused<KK, NMF_GRAM_FP32>), g, dim3(STHR), 0, s, e0, e1, 0, p));
         } else if (p.prec == NMF_GRAM_BF16X2) {
@@ -1031,7 +1090,7 @@ hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t 
 }
 
 hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    if (p.Sy == 1) return hipSuccess;   // solved inside k_yfused
+    if (p.fy) return hipSuccess;   // solved inside k_yfused
     NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_ynnls<KK>, dim3(p.By), dim3(NTHR), 0, s, e0, e1, 0, p));
     return hipGetLastError();
 }

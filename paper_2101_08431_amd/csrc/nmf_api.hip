@@ -30,6 +30,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Plan {
     int64_t ldM, ldX, ldY;
     int Tn, Sx, xcols, Sy, yrows, Tm, J, Bx, By;
+    bool FX, FY;   // the half runs as one kernel
 };
 
 // Stage-1 launch shape.  X stream: 64-row tiles, column splits so that about
@@ -37,7 +38,10 @@ struct Plan {
 // splits while every thread still covers >= 1 row and the grid is short of
 // ~4096 waves.  A single split makes the half one kernel that streams and
 // solves (chosen for matrices of at most 2^18 entries, or by the caller).  NNLS kernels: 256 problems per block.
-Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, int y_splits = 0) {
+// fuse_x / fuse_y: 1 runs the half as one kernel whatever its splits, 0 as two
+// kernels, -1 (automatic) as one kernel exactly when it has a single split.
+Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, int y_splits = 0, int fuse_x = -1,
+                int fuse_y = -1) {
     Plan P;
     P.ldM = align_up((size_t)n, 32);
     P.ldX = align_up((size_t)n, 64);
@@ -59,6 +63,8 @@ Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, in
     P.Sy = (int)ceil_div(n, P.yrows);
     P.Bx = (int)ceil_div(n, nmfk::NTHR);
     P.By = (int)ceil_div(m, nmfk::NTHR);
+    P.FX = fuse_x < 0 ? P.Sx == 1 : fuse_x != 0;
+    P.FY = fuse_y < 0 ? P.Sy == 1 : fuse_y != 0;
     return P;
 }
 
@@ -73,7 +79,7 @@ struct Carve {
 };
 
 struct Offsets {
-    size_t M, Mlo, X, Y, xmask, ymask, bx, by, gx, gy, xst, yst, cntf, status, red, io, bad;
+    size_t M, Mlo, X, Y, xmask, ymask, bx, by, gx, gy, xst, yst, cntf, tcnt, status, red, io, bad;
     size_t ipm_base, total;
 };
 
@@ -99,6 +105,7 @@ Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
     L.xst = c.take<double>((size_t)RxMax * nmfk::NST);
     L.yst = c.take<double>((size_t)RyMax * nmfk::NST);
     L.cntf = c.take<unsigned>(4);
+    L.tcnt = c.take<unsigned>((size_t)P.Tn + TmMax);   // tile arrivals of the one-kernel halves
     L.status = c.take<DevStatus>(1);
     L.red = c.take<double>(2 * kRedBlocks);
     L.io = c.take<double>((size_t)K * (n + m_cap));
@@ -124,6 +131,7 @@ struct nmf_ctx {
     double *red = nullptr, *io = nullptr;
     unsigned *bad = nullptr;
     int stage = 1;
+    int fuse_x = -1, fuse_y = -1;   // nmf_set_launch_fusion
     double mnorm2 = 0.0;
     double ms1 = 0.0, ms2 = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -149,7 +157,7 @@ static nmf_status hip_fail(nmf_ctx *c, hipError_t e, const char *what) {
     } while (0)
 
 static void refresh_shape(nmf_ctx *c) {
-    c->plan = plan_shape(c->n, c->m, c->m_cap, c->K, c->opt.x_splits, c->opt.y_splits);
+    c->plan = plan_shape(c->n, c->m, c->m_cap, c->K, c->opt.x_splits, c->opt.y_splits, c->fuse_x, c->fuse_y);
     AnlsParams &p = c->p;
     p.n = c->n;
     p.m = c->m;
@@ -161,8 +169,10 @@ static void refresh_shape(nmf_ctx *c) {
     p.yrows = c->plan.yrows;
     p.Bx = c->plan.Bx;
     p.By = c->plan.By;
-    p.Rx = p.Sx == 1 ? p.Tn : p.Bx;
-    p.Ry = p.Sy == 1 ? p.Tm : p.By;
+    p.fx = c->plan.FX ? 1 : 0;
+    p.fy = c->plan.FY ? 1 : 0;
+    p.Rx = p.fx ? p.Tn : p.Bx;
+    p.Ry = p.fy ? p.Tm : p.By;
 }
 
 extern "C" {
@@ -285,6 +295,7 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
     p.xstat = (double *)(w + L.xst);
     p.ystat = (double *)(w + L.yst);
     p.cnt_fin = (unsigned *)(w + L.cntf);
+    p.tile_cnt = (unsigned *)(w + L.tcnt);
     p.st = (DevStatus *)(w + L.status);
     c->red = (double *)(w + L.red);
     c->io = (double *)(w + L.io);
@@ -457,7 +468,7 @@ nmf_status nmf_anls_profile(nmf_ctx *c, int32_t sweeps, double *ms) {
     AnlsParams p = c->p;
     p.mode = 0;
     // the events are recorded by each kernel's own dispatch (no extra packets)
-    const bool live[4] = {true, p.Sx != 1, true, p.Sy != 1};
+    const bool live[4] = {true, p.fx == 0, true, p.fy == 0};
     for (int t = 0; st == NMF_OK && t < sweeps; ++t) {
         hipEvent_t *e = &ev[8 * (size_t)t];
         bool ok = nmfk::launch_xstream(c->K, p, c->stream, e[0], e[1]) == hipSuccess &&
@@ -562,6 +573,30 @@ nmf_status nmf_set_launch_shape(nmf_ctx *c, int32_t xs, int32_t ys) {
         HIPCHK(c, nmfk::launch_gram_y_init(c->K, c->p, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    return NMF_OK;
+}
+
+nmf_status nmf_set_launch_fusion(nmf_ctx *c, int32_t fuse_x, int32_t fuse_y) {
+    if (!c) return NMF_EINVAL;
+    if (fuse_x < -1 || fuse_x > 1 || fuse_y < -1 || fuse_y > 1) return fail(c, NMF_EINVAL, "fusion mode not -1, 0 or 1");
+    c->fuse_x = fuse_x;
+    c->fuse_y = fuse_y;
+    refresh_shape(c);
+    if (c->stage == 1) {
+        // the Gram records follow the kernel split of each half: rebuild them
+        HIPCHK(c, nmfk::launch_gram_x_init(c->K, c->p, c->stream));
+        HIPCHK(c, nmfk::launch_gram_y_init(c->K, c->p, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_get_launch_shape(const nmf_ctx *c, int32_t *out4) {
+    if (!c || !out4) return NMF_EINVAL;
+    out4[0] = c->p.Sx;
+    out4[1] = c->p.Sy;
+    out4[2] = c->p.fx;
+    out4[3] = c->p.fy;
     return NMF_OK;
 }
 
@@ -755,9 +790,9 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
             tab.push_back(p);
             b->order.push_back(q);
             g.g.single = p;
-            const bool fx = p.Sx == 1, fy = p.Sy == 1;
+            const bool fx = p.fx != 0, fy = p.fy != 0;
             const int cnt[nmfk::NBK] = {fx ? 0 : p.Tn * p.Sx, fx ? 0 : p.Bx, fy ? 0 : p.Tm * p.Sy,
-                                        fy ? 0 : p.By,     fx ? p.Tn : 0,   fy ? p.Tm : 0};
+                                        fy ? 0 : p.By,     fx ? p.Tn * p.Sx : 0, fy ? p.Tm * p.Sy : 0};
             for (int k = 0; k < nmfk::NBK; ++k) o[k].push_back(o[k].back() + cnt[k]);
         }
         for (int k = 0; k < nmfk::NBK; ++k) {

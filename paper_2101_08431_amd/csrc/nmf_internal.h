@@ -43,9 +43,9 @@ struct DevStatus {
 
 // Parameters of the stage-1 kernels.  One sweep = k_xstream, k_xnnls,
 // k_ystream, k_ynnls; every hand-over between blocks crosses a kernel
-// boundary except the sweep summary at the end of k_ynnls.  A half whose
-// stream has a single split (Sx == 1, Sy == 1) runs as one kernel instead
-// (k_xfused, k_yfused) that streams and solves its tile.
+// boundary except the sweep summary at the end of k_ynnls.  A half may run as
+// one kernel instead (k_xfused, k_yfused; fx, fy): each tile's splits stream
+// as before and the last of them to finish solves the tile.
 struct AnlsParams {
     int64_t n, m, ldM, ldX, ldY;
     const double *M;
@@ -64,8 +64,11 @@ struct AnlsParams {
     int Sx, Tn, xcols; // X stream: Tn row tiles x Sx column splits of xcols columns
     int Sy, Tm, yrows; // Y stream: Tm column tiles x Sy row splits of yrows rows
     int Bx, By;        // NNLS blocks: ceil(n / 256), ceil(m / 256)
+    int fx, fy;        // 1: the half is one kernel (k_xfused / k_yfused) whose tile's last
+                       // split to finish solves the tile; 0: stream kernel + NNLS kernel
     int Rx, Ry;        // statistics / Gram records of the X- and Y-half: Bx and By, or Tn
-                       // (Sx == 1) and Tm (Sy == 1) when the stream kernel also solves
+                       // and Tm when the half is one kernel
+    unsigned *tile_cnt; // [Tn + Tm_max] arrival counters of the one-kernel halves' tiles
     int mode;          // X: 0 = solve, 1 = measure E only; Y: 0 = sweep, 2 = appended columns
 };
 
@@ -73,8 +76,8 @@ struct AnlsParams {
 hipError_t launch_xhalf(int K, const AnlsParams &p, hipStream_t s);   // k_xstream + k_xnnls
 hipError_t launch_yhalf(int K, const AnlsParams &p, hipStream_t s);   // k_ystream + k_ynnls
 // The four stage-1 steps; e0 / e1 (may be null) are recorded by the dispatch
-// itself at the start and the end of the kernel.  A half with a single split
-// is one kernel, launched by its stream launcher; its NNLS launcher then does
+// itself at the start and the end of the kernel.  A half run as one kernel
+// (fx / fy) is launched by its stream launcher; its NNLS launcher then does
 // nothing and records nothing.
 hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0 = nullptr,
                           hipEvent_t e1 = nullptr);

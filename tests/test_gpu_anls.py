@@ -57,20 +57,28 @@ def test_ragged_shapes_match_oracle(orc, n, m, k):
     assert rel_err(X, Y, ref["X"], ref["Yt"]) <= REL
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 3), (8, 1), (8, 3), (64, 64)])
+@pytest.mark.parametrize("shape", [(1, 1, -1, -1), (1, 3, -1, -1), (8, 1, -1, -1), (8, 3, -1, -1),
+                                   (64, 64, -1, -1), (8, 3, 1, 1), (3, 8, 1, 0), (64, 64, 1, 1), (1, 1, 0, 0),
+                                   (2, 5, 0, 1)])
 def test_launch_shapes_match_oracle(orc, shape):
-    # one kernel per half (a single split) or split stream + NNLS kernels, on a
-    # ragged size with several tiles; every shape reaches the oracle's iterates
+    # each half as one kernel (the tile's last split solves) or as a split
+    # stream + NNLS kernel, on a ragged size with several tiles; every launch
+    # plan reaches the oracle's iterates
     n, m, k = 1100, 230, 5
-    print(f"case launch shape {shape} n={n} m={m} k={k}", flush=True)
+    print(f"case launch plan {shape} n={n} m={m} k={k}", flush=True)
     M, X0, Y0 = synth.make(spec(n, m, k, 1e-3, True), 12)
     ctx = gpu_ctx(M, k, X0, Y0, x_splits=shape[0], y_splits=shape[1])
+    ctx.set_launch_fusion(shape[2], shape[3])
+    plan = ctx.launch_plan()
+    assert plan[2] == (shape[0] == 1 if shape[2] < 0 else bool(shape[2]))
+    assert plan[3] == (shape[1] == 1 if shape[3] < 0 else bool(shape[3]))
     ctx.anls_step(6)
     X, Y = ctx.factors()
     ref = orc.anls(M, X0, Y0.T.copy(), exact_sweeps=6)
     assert rel_err(X, Y, ref["X"], ref["Yt"]) <= REL
-    # switching the shape in the middle of a run keeps the iterates
+    # switching the plan in the middle of a run keeps the iterates
     ctx.set_launch_shape(shape[1], shape[0])
+    ctx.set_launch_fusion(shape[3], shape[2])
     ctx.anls_step(3)
     X, Y = ctx.factors()
     ref = orc.anls(M, X0, Y0.T.copy(), exact_sweeps=9)

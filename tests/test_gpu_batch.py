@@ -136,7 +136,8 @@ def test_append_rearms_the_sweep_budget():
 
 def test_batch_many_groups_mixed_halves_with_polls():
     # seven K groups in one batch (their offset tables together exceed one
-    # entry per problem), problems whose halves run split, fused or mixed,
+    # entry per problem), problems whose halves run as two kernels, as one
+    # kernel (with one split or several) or mixed,
     # and a poll between every step: each problem still ends bitwise where
     # its standalone sweeps end
     import torch
@@ -148,14 +149,15 @@ def test_batch_many_groups_mixed_halves_with_polls():
         n, m = (1500, 300) if q % 3 == 0 else (int(rng.integers(100, 600)), int(rng.integers(20, 120)))
         M, X0, Y0 = synth.make(dict(kind="pdf", n=n, m=m, k=k, sigma=1e-3, sigma_relative=True), 10400 + q)
         probs.append((M, X0, Y0, k))
-        shapes.append([None, (1, 2), (2, 1)][q % 3])
-    print("case batch of 9 problems over 7 K groups, split / fused / mixed halves", flush=True)
+        shapes.append([None, (1, 2, -1, -1), (2, 1, -1, -1), (3, 2, 1, 1), (2, 3, 0, 1)][q % 5])
+    print("case batch of 9 problems over 7 K groups, two-kernel / one-kernel / mixed halves", flush=True)
 
     def make():
         cs = contexts(probs)
         for c, sh in zip(cs, shapes):
             if sh is not None:
-                c.set_launch_shape(*sh)
+                c.set_launch_shape(sh[0], sh[1])
+                c.set_launch_fusion(sh[2], sh[3])
         return cs
 
     solo = make()
