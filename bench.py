@@ -143,9 +143,14 @@ def roofline(ctx, n, m, k, shape, workload, sweeps=100):
     per = {name: {"ms": t, "bytes": b, "GBs": b / (t * 1e-3) / 1e9} for name, (t, b) in per.items()}
     dom = max(per, key=lambda q: per[q]["ms"])
     ach = per[dom]["GBs"]
+    # the whole sweep: every kernel's algorithmic bytes over the summed kernel times
+    sweep_bytes = sum(v["bytes"] for v in per.values())
+    sweep_ms = sum(v["ms"] for v in per.values())
+    sweep_gbs = sweep_bytes / (sweep_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(dom, shape, workload),
-            "bytes_per_launch": per[dom]["bytes"], "launch_plan": list(shape), "per_kernel": per}
+            "bytes_per_launch": per[dom]["bytes"], "launch_plan": list(shape), "per_kernel": per,
+            "sweep": {"bytes": sweep_bytes, "ms": sweep_ms, "achieved": sweep_gbs, "frac": sweep_gbs / HBM_PEAK_GBS}}
 
 
 def full_solve(name, seeds, tol, cap):

@@ -97,12 +97,23 @@ template <>
 struct MElem<NMF_GRAM_FP64> {
     using T = double;
     static __device__ __forceinline__ double load(const AnlsParams &p, int64_t off) { return p.M[off]; }
+    // elements off and off + 1 in one 16-byte load (off even)
+    static __device__ __forceinline__ void load2(const AnlsParams &p, int64_t off, double &a, double &b) {
+        const double2 v = *reinterpret_cast<const double2 *>(p.M + off);
+        a = v.x;
+        b = v.y;
+    }
 };
 template <>
 struct MElem<NMF_GRAM_FP32> {
     using T = float;
     static __device__ __forceinline__ float load(const AnlsParams &p, int64_t off) {
         return __uint_as_float(p.Mlo[off]);
+    }
+    static __device__ __forceinline__ void load2(const AnlsParams &p, int64_t off, float &a, float &b) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p.Mlo + off);
+        a = __uint_as_float(u.x);
+        b = __uint_as_float(u.y);
     }
 };
 template <>
@@ -111,6 +122,11 @@ struct MElem<NMF_GRAM_BF16X2> {
     static __device__ __forceinline__ float load(const AnlsParams &p, int64_t off) {
         const uint32_t u = p.Mlo[off];
         return __uint_as_float(u & 0xFFFF0000u) + __uint_as_float(u << 16);
+    }
+    static __device__ __forceinline__ void load2(const AnlsParams &p, int64_t off, float &a, float &b) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p.Mlo + off);
+        a = __uint_as_float(u.x & 0xFFFF0000u) + __uint_as_float(u.x << 16);
+        b = __uint_as_float(u.y & 0xFFFF0000u) + __uint_as_float(u.y << 16);
     }
 };
 
@@ -553,9 +569,11 @@ __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
 // Streams the rows [r0, r1) of the tile's J = 64 / K columns of M against X
 // and leaves each wave's transpose-reduced sums in red[w * YVALS + lane]
 // (value jj * K + a is B_Y[a][jb + jj]); ends with a barrier.  With `stop`
-// set the block returns false before any load.  (Loading the next row ahead
-// of the arithmetic, or the first row before the stop test, measured slower:
-// the extra registers cost more than the overlap gains.)
+// set the block returns false before any load.  For k >= 5 each lane takes
+// two adjacent rows at a time with 16-byte loads (8-byte for the 4-byte copies
+// of M), which halves the load instructions: a row costs k loads of X beside
+// the J = 64/k loads of M, as many at k = 8.  r0 is even (row splits are
+// multiples of 64 rows), so every pair load is aligned.
 template <int K, int P>
 __device__ __forceinline__ bool ystream_sums(const AnlsParams &p, int ct, int64_t r0, int64_t r1, double *red,
                                              bool stop) {
@@ -565,31 +583,58 @@ __device__ __forceinline__ bool ystream_sums(const AnlsParams &p, int ct, int64_
     const int64_t jb = (int64_t)ct * J;
     const int nj = (int)min((int64_t)J, p.m - jb);
 
-    // a row's loads, with no branch between them: columns past the tile's
-    // last load its last column and are zeroed
-    auto load_row = [&](int64_t i, T (&x)[K], T (&mv)[J]) {
-        const int64_t ic = i < r1 ? i : r1 - 1;
-        const int64_t base = jb * p.ldM + ic;
-#pragma unroll
-        for (int a = 0; a < K; ++a) x[a] = (T)p.X[(int64_t)a * p.ldX + ic];
-#pragma unroll
-        for (int jj = 0; jj < J; ++jj) {
-            const T v = MElem<P>::load(p, base + (int64_t)min(jj, nj - 1) * p.ldM);
-            mv[jj] = jj < nj ? v : T(0);
-        }
-    };
-
     T v[YVALS];
 #pragma unroll
     for (int q = 0; q < YVALS; ++q) v[q] = T(0);
     if (stop) return false;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += STHR) {
-        T x[K], mv[J];
-        load_row(i, x, mv);
+    if constexpr (K <= 4) {
+        // J >= 16 loads of M per row: one row per lane (row pairs measured
+        // slower here, and at k <= 2 they would not fit the registers)
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += STHR) {
+            const int64_t base = jb * p.ldM + i;
+            T x[K], mv[J];
 #pragma unroll
-        for (int jj = 0; jj < J; ++jj) {
+            for (int a = 0; a < K; ++a) x[a] = (T)p.X[(int64_t)a * p.ldX + i];
 #pragma unroll
-            for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
+            for (int jj = 0; jj < J; ++jj) {
+                const T e = MElem<P>::load(p, base + (int64_t)min(jj, nj - 1) * p.ldM);
+                mv[jj] = jj < nj ? e : T(0);
+            }
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) {
+#pragma unroll
+                for (int a = 0; a < K; ++a) v[jj * K + a] = fma(mv[jj], x[a], v[jj * K + a]);
+            }
+        }
+    } else {
+        for (int64_t i = r0 + 2 * (int64_t)threadIdx.x; i < r1; i += 2 * STHR) {
+            // rows i and i + 1; the second is dropped past r1 (its loads stay
+            // inside the padded leading dimensions, which hold n + 1 rows when n
+            // is odd), and so are columns past the tile's last
+            const bool two = i + 1 < r1;
+            T x0[K], x1[K], m0[J], m1[J];
+#pragma unroll
+            for (int a = 0; a < K; ++a) {
+                const double2 xv = *reinterpret_cast<const double2 *>(p.X + (int64_t)a * p.ldX + i);
+                x0[a] = (T)xv.x;
+                x1[a] = two ? (T)xv.y : T(0);
+            }
+            const int64_t base = jb * p.ldM + i;
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) {
+                T e0, e1;
+                MElem<P>::load2(p, base + (int64_t)min(jj, nj - 1) * p.ldM, e0, e1);
+                m0[jj] = jj < nj ? e0 : T(0);
+                m1[jj] = (jj < nj && two) ? e1 : T(0);
+            }
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) {
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    v[jj * K + a] = fma(m0[jj], x0[a], v[jj * K + a]);
+                    v[jj * K + a] = fma(m1[jj], x1[a], v[jj * K + a]);
+                }
+            }
         }
     }
     red[w * YVALS + lane] = (double)wave_transpose_reduce(v, lane);

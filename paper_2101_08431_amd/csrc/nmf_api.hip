@@ -59,7 +59,9 @@ Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, in
     if (n * m <= (int64_t)1 << 18) sy = 1;
     if (y_splits > 0) sy = y_splits;
     sy = std::max<int64_t>(1, std::min<int64_t>(sy, std::min<int64_t>(kSyMax, n)));
-    P.yrows = (int)ceil_div(n, sy);
+    // row splits are whole multiples of 64 rows (the Y stream loads row pairs
+    // and needs even split starts), so Sy can come out below the request
+    P.yrows = (int)(ceil_div(ceil_div(n, sy), 64) * 64);
     P.Sy = (int)ceil_div(n, P.yrows);
     P.Bx = (int)ceil_div(n, nmfk::NTHR);
     P.By = (int)ceil_div(m, nmfk::NTHR);
