@@ -71,25 +71,24 @@ __device__ __forceinline__ T wave_transpose_reduce32(T (&v)[32], int lane) {
 // Ends with a barrier.  len <= blockDim.  It is split in two so that a kernel
 // can issue the loads (records_partial: thread tid of nthr threads returns its
 // group sum, no barrier) together with its other loads and add them up later
-// (records_finish).
+// (records_finish).  Records past the end count as zero, so the order of the
+// real ones is unchanged.
 __device__ __forceinline__ double records_partial(const double *src, int cnt, int len, int tid, int nthr) {
     const int G = nthr / len;
     if (G <= 0) return 0.0;   // len > nthr: not a supported call
     const int q = tid % len, g = tid / len;
     // threads past the G groups, and records past the end, load record 0 or
-    // cnt - 1 and drop it: four loads in flight per step, no branch between
-    // them
+    // cnt - 1 and drop it: 16 loads in flight per step, no branch between
+    // them (one step covers 16 G records)
+    constexpr int D = 16;
     const int gc = g < G ? g : 0;
     double acc = 0.0;
-    for (int t = gc; t < cnt; t += 4 * G) {
-        const double a0 = src[(size_t)t * len + q];
-        const double a1 = src[(size_t)min(t + G, cnt - 1) * len + q];
-        const double a2 = src[(size_t)min(t + 2 * G, cnt - 1) * len + q];
-        const double a3 = src[(size_t)min(t + 3 * G, cnt - 1) * len + q];
-        acc += a0;
-        acc += t + G < cnt ? a1 : 0.0;
-        acc += t + 2 * G < cnt ? a2 : 0.0;
-        acc += t + 3 * G < cnt ? a3 : 0.0;
+    for (int t = gc; t < cnt; t += D * G) {
+        double a[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) a[u] = src[(size_t)min(t + u * G, cnt - 1) * len + q];
+#pragma unroll
+        for (int u = 0; u < D; ++u) acc += t + u * G < cnt ? a[u] : 0.0;
     }
     return g < G ? acc : 0.0;
 }

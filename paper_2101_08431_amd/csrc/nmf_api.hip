@@ -29,7 +29,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Plan {
     int64_t ldM, ldX, ldY;
-    int Tn, Sx, xcols, Sy, yrows, Tm, J, Bx, By;
+    int Tn, Sx, xcols, Sy, yrows, Tm, J, Bx, By, Nx, Ny;
     bool FX, FY;   // the half runs as one kernel
 };
 
@@ -65,6 +65,8 @@ Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, in
     P.Sy = (int)ceil_div(n, P.yrows);
     P.Bx = (int)ceil_div(n, nmfk::NTHR);
     P.By = (int)ceil_div(m, nmfk::NTHR);
+    P.Nx = (int)ceil_div(n, nmfk::WTHR);
+    P.Ny = (int)ceil_div(m, nmfk::WTHR);
     P.FX = fuse_x < 0 ? P.Sx == 1 : fuse_x != 0;
     P.FY = fuse_y < 0 ? P.Sy == 1 : fuse_y != 0;
     return P;
@@ -101,7 +103,9 @@ Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
     // statistics / Gram records: one per NNLS block, or one per stream tile
     // when a half runs as one kernel (Tn >= Bx rows, Tm >= By columns)
     const int64_t TmMax = ceil_div(m_cap, nmfk::yhalf_cols(K));
-    const int64_t RxMax = std::max<int64_t>(P.Bx, P.Tn), RyMax = std::max<int64_t>(ByMax, TmMax);
+    const int64_t NyMax = ceil_div(m_cap, nmfk::WTHR);
+    const int64_t RxMax = std::max<int64_t>(P.Nx, P.Tn),
+                  RyMax = std::max<int64_t>(std::max<int64_t>(ByMax, NyMax), TmMax);
     L.gx = c.take<double>((size_t)RxMax * K * K);
     L.gy = c.take<double>((size_t)RyMax * K * K);
     L.xst = c.take<double>((size_t)RxMax * nmfk::NST);
@@ -171,10 +175,12 @@ static void refresh_shape(nmf_ctx *c) {
     p.yrows = c->plan.yrows;
     p.Bx = c->plan.Bx;
     p.By = c->plan.By;
+    p.Nx = c->plan.Nx;
+    p.Ny = c->plan.Ny;
     p.fx = c->plan.FX ? 1 : 0;
     p.fy = c->plan.FY ? 1 : 0;
-    p.Rx = p.fx ? p.Tn : p.Bx;
-    p.Ry = p.fy ? p.Tm : p.By;
+    p.Rx = p.fx ? p.Tn : p.Nx;
+    p.Ry = p.fy ? p.Tm : p.Ny;
 }
 
 extern "C" {
@@ -793,8 +799,8 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
             b->order.push_back(q);
             g.g.single = p;
             const bool fx = p.fx != 0, fy = p.fy != 0;
-            const int cnt[nmfk::NBK] = {fx ? 0 : p.Tn * p.Sx, fx ? 0 : p.Bx, fy ? 0 : p.Tm * p.Sy,
-                                        fy ? 0 : p.By,     fx ? p.Tn * p.Sx : 0, fy ? p.Tm * p.Sy : 0};
+            const int cnt[nmfk::NBK] = {fx ? 0 : p.Tn * p.Sx, fx ? 0 : p.Nx, fy ? 0 : p.Tm * p.Sy,
+                                        fy ? 0 : p.Ny,     fx ? p.Tn * p.Sx : 0, fy ? p.Tm * p.Sy : 0};
             for (int k = 0; k < nmfk::NBK; ++k) o[k].push_back(o[k].back() + cnt[k]);
         }
         for (int k = 0; k < nmfk::NBK; ++k) {
