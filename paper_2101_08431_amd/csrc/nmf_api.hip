@@ -36,8 +36,10 @@ struct Plan {
 // Stage-1 launch shape.  X stream: 64-row tiles, column splits so that about
 // 4096 waves stream M (8 per block).  Y stream: J = 64/K columns per tile, row
 // splits while every thread still covers >= 1 row and the grid is short of
-// ~4096 waves.  A single split makes the half one kernel that streams and
-// solves (chosen for matrices of at most 2^18 entries, or by the caller).  NNLS kernels: 256 problems per block.
+// ~4096 waves; row splits are whole multiples of 64 rows.  A single split
+// makes the half one kernel that streams and solves (chosen for matrices of
+// at most 2^18 entries, or by the caller).  NNLS kernels: one wave (64
+// problems) per block.
 // fuse_x / fuse_y: 1 runs the half as one kernel whatever its splits, 0 as two
 // kernels, -1 (automatic) as one kernel exactly when it has a single split.
 Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, int y_splits = 0, int fuse_x = -1,
