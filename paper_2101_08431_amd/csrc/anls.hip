@@ -4,7 +4,7 @@
 //              (Sx column splits); 8 waves per block, each wave a slice of
 //              the split's columns, eight 512-byte loads of M in flight per
 //              wave; Y for the split is staged in LDS.
-//   k_xnnls    one thread per row, one wave per block: sums the Sx
+//   k_xnnls    one thread per row (one wave per block up to k = 8): sums the Sx
 //              partials in order, reduces G_Y = Y Y^T from the records of the
 //              last Y-half,
 //              measures the KKT parts of E(.;0) at the old point (r =
@@ -15,12 +15,12 @@
 //   k_ystream  B_Y = X^T M in split partials.  Grid (Tm tiles of J = 64/K
 //              columns) x (Sy row splits); every lane accumulates J*K dot
 //              products and a wave transpose-reduce leaves one sum per lane.
-//   k_ynnls    one thread per column, one wave per block: eq. (2) with C = X;
-//              a record of the new G_Y per wave; the last wave applies the
+//   k_ynnls    one thread per column (blocks as k_xnnls): eq. (2) with C = X;
+//              a record of the new G_Y per wave; the last block applies the
 //              stop rule of Sec. IV.
 //
 // All hand-overs between blocks cross a kernel boundary, except the sweep
-// summary in k_ynnls (ceil(m/64) blocks).  Every sum runs in a fixed order,
+// summary in k_ynnls.  Every sum runs in a fixed order,
 // so results are bitwise reproducible.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -478,47 +478,13 @@ __device__ __forceinline__ void xfused_body(const AnlsParams &p, int tile, int s
                            p.mode == 0 ? p.gx_part + (int64_t)tile * K * K : nullptr);
 }
 
-// G = the sum of `cnt` Gram records (k x k, fixed order) into LDS for a
-// one-wave NNLS block.  For k <= 8 the loads are issued by gram_records_issue
-// (before the caller's stop test, with its other loads) and summed by
-// gram_records_finish; beyond, the k^2 entries are summed 64 at a time, each
-// lane over all records of its entry in record order.
-template <int K>
-__device__ __forceinline__ double gram_records_issue(const double *src, int cnt) {
-    if constexpr (K * K <= WTHR) return records_partial(src, cnt, K * K, (int)threadIdx.x, WTHR);
-    else return 0.0;
-}
-template <int K>
-__device__ __forceinline__ void gram_records_finish(double acc, const double *src, int cnt, double *G,
-                                                    double *scr) {
-    if constexpr (K * K <= WTHR) {
-        records_finish(acc, K * K, 0, WTHR, G, scr);
-    } else {
-        for (int q0 = 0; q0 < K * K; q0 += WTHR) {
-            const int q = min(q0 + (int)threadIdx.x, K * K - 1);
-            double v = 0.0;
-            int t = 0;
-            for (; t + 3 < cnt; t += 4) {
-                const double a0 = src[(size_t)t * K * K + q], a1 = src[(size_t)(t + 1) * K * K + q];
-                const double a2 = src[(size_t)(t + 2) * K * K + q], a3 = src[(size_t)(t + 3) * K * K + q];
-                v += a0;
-                v += a1;
-                v += a2;
-                v += a3;
-            }
-            for (; t < cnt; ++t) v += src[(size_t)t * K * K + q];
-            if (q0 + (int)threadIdx.x < K * K) G[q] = v;
-        }
-        __syncthreads();
-    }
-}
-
 template <int K>
 __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
+    constexpr int NT = nnls_threads(K);
     __shared__ double G[K * K];
-    __shared__ double lds[WTHR];
+    __shared__ double lds[NT];
     const bool stop = sweep_stopped(p);
-    const int64_t i = (int64_t)bid * WTHR + threadIdx.x;
+    const int64_t i = (int64_t)bid * NT + threadIdx.x;
     const bool live = i < p.n;
     // the row's loads and the G_Y records go out before anything waits on
     // memory; lanes past the last row load row n - 1 and solve nothing
@@ -531,9 +497,9 @@ __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
     }
     const uint32_t old_mask = p.xmask[ic];
     sum_split_partials<K>(p.bx_part, p.ldX, ic, p.Sx, b);
-    const double gacc = gram_records_issue<K>(p.gy_part, p.Ry);
+    const double gacc = records_partial(p.gy_part, p.Ry, K * K, (int)threadIdx.x, NT);
     if (stop) return;
-    gram_records_finish<K>(gacc, p.gy_part, p.Ry, G, lds);
+    records_finish(gacc, K * K, 0, NT, G, lds);
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
@@ -541,8 +507,11 @@ __device__ __forceinline__ void xnnls_body(const AnlsParams &p, int bid) {
 #pragma unroll
     for (int a = 0; a < K; ++a) xn[a] = 0.0;
     if (live) x_row<K>(p, G, i, x, b, old_mask, st, xn);
-    wave_stats_and_gram<K>(st, xn, p.xstat + (int64_t)bid * NST,
-                           p.mode == 0 ? p.gx_part + (int64_t)bid * K * K : nullptr);
+    // the wave's record; with four-wave blocks, waves wholly past the last
+    // row have none (the branch is uniform within a wave)
+    const int64_t wv = i / WTHR;
+    if (wv < p.Wx)
+        wave_stats_and_gram<K>(st, xn, p.xstat + wv * NST, p.mode == 0 ? p.gx_part + wv * K * K : nullptr);
 }
 
 // ---------------------------------------------------------------- Y-half
@@ -712,11 +681,12 @@ __device__ __forceinline__ void yfused_body(const AnlsParams &p, int ct, int spl
 
 template <int K>
 __device__ __forceinline__ void ynnls_body(const AnlsParams &p, int bid) {
+    constexpr int NT = nnls_threads(K);
     __shared__ double G[K * K];
-    __shared__ double lds[WTHR];
+    __shared__ double lds[NT];
     __shared__ unsigned flag;
     const bool stop = sweep_stopped(p);
-    const int64_t j = (int64_t)bid * WTHR + threadIdx.x;
+    const int64_t j = (int64_t)bid * NT + threadIdx.x;
     const bool live = j < p.m;
     // the column's loads and the G_X records go out before anything waits on
     // memory; lanes past the last column load column m - 1 and solve nothing
@@ -729,9 +699,9 @@ __device__ __forceinline__ void ynnls_body(const AnlsParams &p, int bid) {
     }
     const uint32_t old_mask = p.ymask[jc];
     sum_split_partials<K>(p.by_part, p.ldY, jc, p.Sy, b);
-    const double gacc = gram_records_issue<K>(p.gx_part, p.Rx);
+    const double gacc = records_partial(p.gx_part, p.Rx, K * K, (int)threadIdx.x, NT);
     if (stop) return;
-    gram_records_finish<K>(gacc, p.gx_part, p.Rx, G, lds);
+    records_finish(gacc, K * K, 0, NT, G, lds);
     double st[NST];
 #pragma unroll
     for (int q = 0; q < NST; ++q) st[q] = 0.0;
@@ -739,7 +709,8 @@ __device__ __forceinline__ void ynnls_body(const AnlsParams &p, int bid) {
 #pragma unroll
     for (int a = 0; a < K; ++a) yn[a] = 0.0;
     if (live) y_col<K>(p, G, j, y, b, old_mask, st, yn);
-    wave_stats_and_gram<K>(st, yn, p.ystat + (int64_t)bid * NST, p.gy_part + (int64_t)bid * K * K);
+    const int64_t wv = j / WTHR;   // the wave's record (none past the last column)
+    if (wv < p.Wy) wave_stats_and_gram<K>(st, yn, p.ystat + wv * NST, p.gy_part + wv * K * K);
     if (!last_arrival(p.cnt_fin, (unsigned)p.Ny, &flag)) return;
     sweep_summary(p, lds);
 }
@@ -759,11 +730,11 @@ __global__ __launch_bounds__(STHR) void k_xfused(AnlsParams p) {
 template <int K, int P>
 __global__ __launch_bounds__(STHR) void k_yfused(AnlsParams p) { yfused_body<K, P>(p, blockIdx.x, blockIdx.y); }
 template <int K>
-__global__ __launch_bounds__(WTHR) void k_xnnls(AnlsParams p) { xnnls_body<K>(p, blockIdx.x); }
+__global__ __launch_bounds__(nnls_threads(K)) void k_xnnls(AnlsParams p) { xnnls_body<K>(p, blockIdx.x); }
 template <int K, int P>
 __global__ __launch_bounds__(STHR) void k_ystream(AnlsParams p) { ystream_body<K, P>(p, blockIdx.x, blockIdx.y); }
 template <int K>
-__global__ __launch_bounds__(WTHR) void k_ynnls(AnlsParams p) { ynnls_body<K>(p, blockIdx.x); }
+__global__ __launch_bounds__(nnls_threads(K)) void k_ynnls(AnlsParams p) { ynnls_body<K>(p, blockIdx.x); }
 
 // A batch of problems with the same K and precision: one flattened grid, block
 // b belongs to the problem q with off[q] <= b < off[q + 1] and runs that
@@ -805,7 +776,7 @@ __global__ __launch_bounds__(STHR) void kb_xfused(const AnlsParams *tab, const i
     xfused_body<K, P>(p, local % p.Tn, local / p.Tn, lds);
 }
 template <int K>
-__global__ __launch_bounds__(WTHR) void kb_xnnls(const AnlsParams *tab, const int *off, int np) {
+__global__ __launch_bounds__(nnls_threads(K)) void kb_xnnls(const AnlsParams *tab, const int *off, int np) {
     const int q = batch_problem(off, np, blockIdx.x);
     const AnlsParams p = tab[q];
     xnnls_body<K>(p, blockIdx.x - off[q]);
@@ -825,7 +796,7 @@ __global__ __launch_bounds__(STHR) void kb_yfused(const AnlsParams *tab, const i
     yfused_body<K, P>(p, local % p.Tm, local / p.Tm);
 }
 template <int K>
-__global__ __launch_bounds__(WTHR) void kb_ynnls(const AnlsParams *tab, const int *off, int np) {
+__global__ __launch_bounds__(nnls_threads(K)) void kb_ynnls(const AnlsParams *tab, const int *off, int np) {
     const int q = batch_problem(off, np, blockIdx.x);
     const AnlsParams p = tab[q];
     ynnls_body<K>(p, blockIdx.x - off[q]);
@@ -1087,7 +1058,7 @@ hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t 
 
 hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (p.fx) return hipSuccess;   // solved inside k_xfused
-    NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_xnnls<KK>, dim3(p.Nx), dim3(WTHR), 0, s, e0, e1, 0, p));
+    NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_xnnls<KK>, dim3(p.Nx), dim3(nnls_threads(KK)), 0, s, e0, e1, 0, p));
     return hipGetLastError();
 }
 
@@ -1116,7 +1087,7 @@ hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t 
 
 hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (p.fy) return hipSuccess;   // solved inside k_yfused
-    NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_ynnls<KK>, dim3(p.Ny), dim3(WTHR), 0, s, e0, e1, 0, p));
+    NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_ynnls<KK>, dim3(p.Ny), dim3(nnls_threads(KK)), 0, s, e0, e1, 0, p));
     return hipGetLastError();
 }
 
@@ -1154,12 +1125,12 @@ hipError_t launch_batch_sweep(int K, int prec, const BatchGroup &g, hipStream_t 
     NMF_BATCH_STREAM(kb_xstream, g.blocks[0], ox)
     NMF_BATCH_STREAM(kb_xfused, g.blocks[4], ofx)
     if (g.blocks[1] > 0)
-        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_xnnls<KK>, dim3(g.blocks[1]), dim3(WTHR), 0, s, t, onx, np));
+        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_xnnls<KK>, dim3(g.blocks[1]), dim3(nnls_threads(KK)), 0, s, t, onx, np));
     // Y-half
     NMF_BATCH_STREAM(kb_ystream, g.blocks[2], oy)
     NMF_BATCH_STREAM(kb_yfused, g.blocks[5], ofy)
     if (g.blocks[3] > 0)
-        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_ynnls<KK>, dim3(g.blocks[3]), dim3(WTHR), 0, s, t, ony, np));
+        NMF_K_SWITCH(K, hipLaunchKernelGGL(kb_ynnls<KK>, dim3(g.blocks[3]), dim3(nnls_threads(KK)), 0, s, t, ony, np));
 #undef NMF_BATCH_STREAM
     return hipGetLastError();
 }

@@ -29,7 +29,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Plan {
     int64_t ldM, ldX, ldY;
-    int Tn, Sx, xcols, Sy, yrows, Tm, J, Bx, By, Nx, Ny;
+    int Tn, Sx, xcols, Sy, yrows, Tm, J, Bx, By, Nx, Ny, Wx, Wy;
     bool FX, FY;   // the half runs as one kernel
 };
 
@@ -39,7 +39,7 @@ struct Plan {
 // ~4096 waves; row splits are whole multiples of 64 rows.  A single split
 // makes the half one kernel that streams and solves (chosen for matrices of
 // at most 2^18 entries, or by the caller).  NNLS kernels: one wave (64
-// problems) per block.
+// problems) per block up to k = 8, four waves beyond.
 // fuse_x / fuse_y: 1 runs the half as one kernel whatever its splits, 0 as two
 // kernels, -1 (automatic) as one kernel exactly when it has a single split.
 Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, int y_splits = 0, int fuse_x = -1,
@@ -67,8 +67,10 @@ Plan plan_shape(int64_t n, int64_t m, int64_t m_cap, int K, int x_splits = 0, in
     P.Sy = (int)ceil_div(n, P.yrows);
     P.Bx = (int)ceil_div(n, nmfk::NTHR);
     P.By = (int)ceil_div(m, nmfk::NTHR);
-    P.Nx = (int)ceil_div(n, nmfk::WTHR);
-    P.Ny = (int)ceil_div(m, nmfk::WTHR);
+    P.Nx = (int)ceil_div(n, nmfk::nnls_threads(K));
+    P.Ny = (int)ceil_div(m, nmfk::nnls_threads(K));
+    P.Wx = (int)ceil_div(n, nmfk::WTHR);
+    P.Wy = (int)ceil_div(m, nmfk::WTHR);
     P.FX = fuse_x < 0 ? P.Sx == 1 : fuse_x != 0;
     P.FY = fuse_y < 0 ? P.Sy == 1 : fuse_y != 0;
     return P;
@@ -106,7 +108,7 @@ Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
     // when a half runs as one kernel (Tn >= Bx rows, Tm >= By columns)
     const int64_t TmMax = ceil_div(m_cap, nmfk::yhalf_cols(K));
     const int64_t NyMax = ceil_div(m_cap, nmfk::WTHR);
-    const int64_t RxMax = std::max<int64_t>(P.Nx, P.Tn),
+    const int64_t RxMax = std::max<int64_t>(P.Wx, P.Tn),
                   RyMax = std::max<int64_t>(std::max<int64_t>(ByMax, NyMax), TmMax);
     L.gx = c.take<double>((size_t)RxMax * K * K);
     L.gy = c.take<double>((size_t)RyMax * K * K);
@@ -179,10 +181,12 @@ static void refresh_shape(nmf_ctx *c) {
     p.By = c->plan.By;
     p.Nx = c->plan.Nx;
     p.Ny = c->plan.Ny;
+    p.Wx = c->plan.Wx;
+    p.Wy = c->plan.Wy;
     p.fx = c->plan.FX ? 1 : 0;
     p.fy = c->plan.FY ? 1 : 0;
-    p.Rx = p.fx ? p.Tn : p.Nx;
-    p.Ry = p.fy ? p.Tm : p.Ny;
+    p.Rx = p.fx ? p.Tn : p.Wx;
+    p.Ry = p.fy ? p.Tm : p.Wy;
 }
 
 extern "C" {

@@ -14,7 +14,11 @@ namespace nmfk {
 
 constexpr int KMAX = 16;
 constexpr int NTHR = 256;      // threads of the element-wise and reduction kernels
-constexpr int WTHR = 64;       // threads of the stage-1 NNLS kernels: one wave, one problem per lane
+constexpr int WTHR = 64;       // one wave
+// Threads of the stage-1 NNLS kernels (one problem per lane): one wave up to
+// k = 8; beyond, four waves, so that the k^2-entry Gram records of the other
+// half are summed by enough threads.  Records are written per wave either way.
+constexpr int nnls_threads(int K) { return K <= 8 ? 64 : 256; }
 constexpr int SWAVES = 8;      // waves of the streaming kernels
 constexpr int STHR = 64 * SWAVES;
 constexpr int XTILE = 64;      // rows of M per X-stream tile (one row per lane)
@@ -65,10 +69,11 @@ struct AnlsParams {
     int Sx, Tn, xcols; // X stream: Tn row tiles x Sx column splits of xcols columns
     int Sy, Tm, yrows; // Y stream: Tm column tiles x Sy row splits of yrows rows
     int Bx, By;        // row / column blocks of 256 (stage-2 kernels): ceil(n / 256), ceil(m / 256)
-    int Nx, Ny;        // stage-1 NNLS blocks of one wave: ceil(n / 64), ceil(m / 64)
+    int Nx, Ny;        // stage-1 NNLS blocks: ceil(n / nnls_threads(K)), ceil(m / nnls_threads(K))
+    int Wx, Wy;        // waves of the stage-1 NNLS kernels: ceil(n / 64), ceil(m / 64)
     int fx, fy;        // 1: the half is one kernel (k_xfused / k_yfused) whose tile's last
                        // split to finish solves the tile; 0: stream kernel + NNLS kernel
-    int Rx, Ry;        // statistics / Gram records of the X- and Y-half: Nx and Ny, or Tn
+    int Rx, Ry;        // statistics / Gram records of the X- and Y-half: Wx and Wy, or Tn
                        // and Tm when the half is one kernel
     unsigned *tile_cnt; // [Tn + Tm_max] arrival counters of the one-kernel halves' tiles
     int mode;          // X: 0 = solve, 1 = measure E only; Y: 0 = sweep, 2 = appended columns
