@@ -66,38 +66,42 @@ def _apply_single(ctx, xs, ys, fx, fy):
     ctx.set_launch_fusion(fx, fy)
 
 
-def tune_single(ctx, xs_cands=(1, 2, 4, 8, 11, 16), ys_cands=(1, 2, 3, 4, 6), sweeps=30, use_cache=True):
+def tune_single(ctx, xs_cands=(1, 2, 4, 8, 11, 16), ys_cands=(1, 2, 3, 4, 6), sweeps=30, use_cache=True,
+                pairs=None, try_fusion=True):
     """Pick the stage-1 launch plan of one context, (x_splits, y_splits,
     fuse_x, fuse_y), by timing back-to-back sweeps of each candidate: every
     split pair with the automatic kernel split (one kernel per half exactly at
     a single split) and, for ranks up to FUSE_KMAX, with each half forced into
-    one kernel.  Returns the choice and sets it.  The sweeps advance the
+    one kernel.  `pairs` (a list of (x_splits, y_splits)) replaces the product
+    of the two candidate lists; try_fusion=False keeps the automatic kernel
+    split only.  Returns the choice and sets it.  The sweeps advance the
     factorisation, so tune a context whose stop rule cannot hold yet (or a
     copy of one)."""
-    key = f"single2:{ctx.n}:{ctx.m}:{ctx.k}:{int(ctx.options.gram_precision)}"
+    shapes = list(pairs) if pairs is not None else [(xs, ys) for xs in xs_cands for ys in ys_cands]
+    key = (f"single2:{ctx.n}:{ctx.m}:{ctx.k}:{int(ctx.options.gram_precision)}:"
+           + hashlib.sha1(json.dumps([shapes, try_fusion]).encode()).hexdigest()[:8])
     cache = _load() if use_cache else {}
     if key in cache:
         choice = tuple(cache[key]["choice"])
         _apply_single(ctx, *choice)
         return choice
     import torch
-    fusions = [(-1, -1)] + ([(1, -1), (-1, 1), (1, 1)] if ctx.k <= FUSE_KMAX else [])
+    fusions = [(-1, -1)] + ([(1, -1), (-1, 1), (1, 1)] if try_fusion and ctx.k <= FUSE_KMAX else [])
     timings = {}
-    for xs in xs_cands:
-        for ys in ys_cands:
-            for fx, fy in fusions:
-                _apply_single(ctx, xs, ys, fx, fy)
-                plan = ctx.launch_plan()
-                if any(plan == ctx_plan for ctx_plan, _ in timings.values()):
-                    continue   # the same launch plan as an earlier candidate
-                ctx.anls_step(3, report=False)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(ctx.stream)
-                ctx.anls_step(sweeps, report=False)
-                e1.record(ctx.stream)
-                e1.synchronize()
-                timings[(xs, ys, fx, fy)] = (plan, e0.elapsed_time(e1) / sweeps)
+    for xs, ys in shapes:
+        for fx, fy in fusions:
+            _apply_single(ctx, xs, ys, fx, fy)
+            plan = ctx.launch_plan()
+            if any(plan == ctx_plan for ctx_plan, _ in timings.values()):
+                continue   # the same launch plan as an earlier candidate
+            ctx.anls_step(3, report=False)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            ctx.anls_step(sweeps, report=False)
+            e1.record(ctx.stream)
+            e1.synchronize()
+            timings[(xs, ys, fx, fy)] = (plan, e0.elapsed_time(e1) / sweeps)
     best = min(timings, key=lambda c: timings[c][1])
     _apply_single(ctx, *best)
     global last_timings
