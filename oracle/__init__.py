@@ -160,7 +160,7 @@ def anls(M, X0, Yt0, eps_stol=1e-6, max_sweeps=1000, exact_sweeps=None):
 
 from .ipm_oracle import (  # noqa: E402
     IPMOptions, gradients, kkt_error, kkt_error_anls, merit, transition, newton_direction,
-    step_max, ipm, two_stage, normalise,
+    step_max, ipm, two_stage, normalise, complementarity_avg, affine_mu, centring, mu_flag_update, armijo,
 )
 
 

@@ -67,6 +67,7 @@ class IPMOptions:
     max_inner: int = 1000          # total inner iterations over the whole stage
     max_backtracks: int = 60
     history: bool = False
+    snapshots: tuple = ()          # E(.;0) levels at which to keep a copy of the iterate
 
 
 def gradients(M, X, Yt):
@@ -166,6 +167,56 @@ def step_max(pairs, tau):
     return a
 
 
+def complementarity_avg(X, Yt, r, s):
+    """(x^T r + y^T s) / (nk + mk): the average complementarity that eq. (9)
+    measures mu_aff against."""
+    N = X.size + Yt.size
+    return (float(np.sum(X * r)) + float(np.sum(Yt * s))) / N
+
+
+def affine_mu(X, Yt, r, s, dxa, dya):
+    """mu_aff of eq. (8)-(9) for the predictor direction (dxa, dya) of the
+    mu = 0 system: the dual parts follow eq. (11) with mu = 0,
+    dr = -r - (r / x) dx, and the step lengths are those of eq. (7) with
+    tau = 1 (the largest steps that keep the point in the closed orthant)."""
+    dra = -r - (r / X) * dxa
+    dsa = -s - (s / Yt) * dya
+    a1a = step_max([(X, dxa), (Yt, dya)], 1.0)
+    a2a = step_max([(r, dra), (s, dsa)], 1.0)
+    N = X.size + Yt.size
+    return (float(np.sum((X + a1a * dxa) * (r + a2a * dra)))
+            + float(np.sum((Yt + a1a * dya) * (s + a2a * dsa)))) / N
+
+
+def centring(mu_aff, avg):
+    """sigma = min{(mu_aff / avg)^3, 0.99}, eq. (9).  mu_aff is a
+    complementarity of points in the closed orthant, so it is >= 0 in exact
+    arithmetic; a rounding residue below 0 from the step to the boundary
+    counts as 0."""
+    return min((max(mu_aff, 0.0) / avg) ** 3, 0.99)
+
+
+def mu_flag_update(sigma, avg, sigma_c):
+    """The update of Alg. 3 after the predictor: mu <- sigma * avg and the
+    exact-Hessian flag, set exactly when sigma <= sigma_c (Sec. IV)."""
+    return sigma * avg, (1 if sigma <= sigma_c else 0)
+
+
+def armijo(phi, phi0, a1, slope, eta, max_backtracks):
+    """Backtracking of Alg. 2 / Alg. 3, eq. (13): the first t = 0, 1, ... with
+    phi(a1 / 2^t) <= phi0 + eta (a1 / 2^t) slope.  After ``max_backtracks``
+    halvings the last trial is taken.  Returns (alpha, t, phi(alpha), capped)."""
+    t = 0
+    while True:
+        al = a1 / (2.0 ** t)
+        phi1 = phi(al)
+        if phi1 <= phi0 + eta * al * slope:
+            return al, t, phi1, False
+        if t >= max_backtracks:
+            return al, t, phi1, True
+        t += 1
+
+
 @dataclass
 class IPMResult:
     X: np.ndarray
@@ -183,18 +234,17 @@ class IPMResult:
     fallbacks: int = 0
     phi_hist: list = field(default_factory=list)
     E0_hist: list = field(default_factory=list)
+    snapshots: dict = field(default_factory=dict)
 
 
 def ipm(M, X, Yt, r, s, mu, rho, opts: IPMOptions):
     """Interior-point stage of Alg. 3 from a strictly interior point."""
-    n, k = X.shape
-    m = Yt.shape[0]
-    N = n * k + m * k
     flag = 0
     gx, gy, R = gradients(M, X, Yt)
     E0 = kkt_error(X, Yt, r, s, 0.0, gx, gy)
     outer = inner = caps = exact_steps = fallbacks = 0
     phis, e0s = [], []
+    snaps = {}
     while E0 > opts.eps_tol and outer < opts.max_outer and inner < opts.max_inner:
         outer += 1
         eps_mu = mu
@@ -229,16 +279,9 @@ def ipm(M, X, Yt, r, s, mu, rho, opts: IPMOptions):
             a2 = step_max([(r, dr), (s, ds)], opts.tau)
             slope = float(np.sum(dx * gphi_x) + np.sum(dy * gphi_y))
             phi0 = merit(M, X, Yt, mu)
-            t = 0
-            while True:
-                al = a1 / (2.0 ** t)
-                phi1 = merit(M, X + al * dx, Yt + al * dy, mu)
-                if phi1 <= phi0 + opts.eta * al * slope:
-                    break
-                if t >= opts.max_backtracks:
-                    caps += 1
-                    break
-                t += 1
+            al, _, phi1, capped = armijo(lambda a: merit(M, X + a * dx, Yt + a * dy, mu), phi0, a1, slope,
+                                         opts.eta, opts.max_backtracks)
+            caps += int(capped)
             X = X + al * dx
             Yt = Yt + al * dy
             r = r + a2 * dr
@@ -248,28 +291,24 @@ def ipm(M, X, Yt, r, s, mu, rho, opts: IPMOptions):
             gx, gy, R = gradients(M, X, Yt)
             E0 = kkt_error(X, Yt, r, s, 0.0, gx, gy)
             e0s.append(E0)
+            for lev in opts.snapshots:
+                if E0 <= lev and lev not in snaps:
+                    snaps[lev] = dict(X=X.copy(), Yt=Yt.copy(), r=r.copy(), s=s.copy(), E0=E0, inner=inner,
+                                      outer=outer)
         if E0 <= opts.eps_tol:
             break
         # predictor (affine scaling) probe, eq. (8)-(9)
         d = newton_direction(X, Yt, r, s, 0.0, rho, gx, gy, R, exact=False)
         if d is None:
             raise FloatingPointError("Schur matrix of the predictor system is not SPD")
-        dxa, dya = d
-        dra = -r - (r / X) * dxa
-        dsa = -s - (s / Yt) * dya
-        a1a = step_max([(X, dxa), (Yt, dya)], 1.0)
-        a2a = step_max([(r, dra), (s, dsa)], 1.0)
-        mu_aff = (float(np.sum((X + a1a * dxa) * (r + a2a * dra)))
-                  + float(np.sum((Yt + a1a * dya) * (s + a2a * dsa)))) / N
-        avg = (float(np.sum(X * r)) + float(np.sum(Yt * s))) / N
-        # mu_aff >= 0 in exact arithmetic (points of the closed orthant); a
-        # rounding residue below 0 from the step to the boundary counts as 0
-        sigma = min((max(mu_aff, 0.0) / avg) ** 3, 0.99)
-        mu = sigma * avg
-        flag = 1 if sigma <= opts.sigma_c else 0
+        mu_aff = affine_mu(X, Yt, r, s, d[0], d[1])
+        avg = complementarity_avg(X, Yt, r, s)
+        sigma = centring(mu_aff, avg)
+        mu, flag = mu_flag_update(sigma, avg, opts.sigma_c)
     return IPMResult(X=X, Yt=Yt, r=r, s=s, mu=mu, flag=flag, E0=E0, outer=outer, inner=inner,
                      converged=E0 <= opts.eps_tol, backtrack_cap_hits=caps,
-                     exact_steps=exact_steps, fallbacks=fallbacks, phi_hist=phis, E0_hist=e0s)
+                     exact_steps=exact_steps, fallbacks=fallbacks, phi_hist=phis, E0_hist=e0s,
+                     snapshots=snaps)
 
 
 def two_stage(M, X0, Yt0, opts: IPMOptions = None, anls_fn=None):
