@@ -6,8 +6,11 @@ and the stream.  Importing works without a GPU; using a context needs one.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnmf_hip.so")
@@ -58,6 +61,39 @@ class Report(ctypes.Structure):
 
 _lib = None
 
+# Live contexts and batches.  At interpreter exit they are released by
+# _release_all() while torch's HIP runtime is still up (this handler is
+# registered after torch is imported, so it runs before torch's own exit
+# handlers); after that every __del__ is a no-op, so no HIP call is made
+# while the runtime is being torn down.
+_live_ctx = weakref.WeakSet()
+_live_batch = weakref.WeakSet()
+_exiting = False
+
+
+def _release_all():
+    global _exiting
+    if _lib is None or _exiting:
+        _exiting = True
+        return
+    try:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for b in list(_live_batch):
+        try:
+            b.close()
+        except Exception:
+            pass
+    for c in list(_live_ctx):
+        try:
+            c.close()
+        except Exception:
+            pass
+    _exiting = True
+
 
 def load():
     """Load libnmf_hip.so; raises if it has not been built."""
@@ -72,6 +108,7 @@ def load():
     # finds no device.
     import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
+    atexit.register(_release_all)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     L.nmf_default_options.argtypes = [ctypes.POINTER(Options)]
     L.nmf_default_options.restype = None
@@ -199,6 +236,7 @@ class NMF:
             raise NMFError(st, L.nmf_last_error(None).decode())
         self._ctx = out
         self.n, self.k = int(n), int(k)
+        _live_ctx.add(self)
 
     # -- helpers
     def _check(self, st, ok=(NMF_OK, NMF_CONVERGED, NMF_ENOTCONV)):
@@ -293,11 +331,14 @@ class NMF:
         return int(out[0]), int(out[1]), bool(out[2]), bool(out[3])
 
     def close(self):
+        """Releases the context now (its workspace is freed with this object)."""
         if getattr(self, "_ctx", None):
             load().nmf_destroy(self._ctx)
             self._ctx = None
 
     def __del__(self):
+        if _exiting or sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -314,17 +355,20 @@ class Batch:
         L = load()
         self.contexts = list(contexts)
         n = len(self.contexts)
-        nbytes = int(L.nmf_batch_workspace_bytes(n))
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.Stream()
         arr = (ctypes.c_void_p * n)(*[c._ctx.value for c in self.contexts])
         out = ctypes.c_void_p()
-        torch.cuda.synchronize()
+        # the contexts' setup work runs on their own streams
+        for c in self.contexts:
+            c.stream.synchronize()
+        nbytes = int(L.nmf_batch_workspace_bytes(n))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         st = L.nmf_batch_create(arr, n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(out))
         if st != NMF_OK:
             raise NMFError(st, L.nmf_last_error(None).decode())
         self._b = out
+        _live_batch.add(self)
 
     def step(self, sweeps, graph=True):
         st = load().nmf_batch_anls_step(self._b, int(sweeps), 1 if graph else 0)
@@ -352,11 +396,15 @@ class Batch:
         return conv.astype(bool), sw
 
     def close(self):
+        """Waits for the batch's stream, then releases the batch and its graph."""
         if getattr(self, "_b", None):
+            load().nmf_batch_sync(self._b)
             load().nmf_batch_destroy(self._b)
             self._b = None
 
     def __del__(self):
+        if _exiting or sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

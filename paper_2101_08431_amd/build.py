@@ -28,14 +28,26 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False, jobs=None):
-    """Compile every source to an object and link the shared library."""
+def _stale(src, obj, inc_dirs):
+    """True when obj is missing or older than src or any header it may include."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(d, f) for d in inc_dirs for f in os.listdir(d) if f.endswith(".h")]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose=False, jobs=None, force=True):
+    """Compile every source to an object and link the shared library.
+    force=False recompiles only objects older than their source or a header."""
     os.makedirs(OBJDIR, exist_ok=True)
     hipcc = _hipcc()
     inc = ["-I", CSRC, "-I", os.path.join(os.path.dirname(HERE), "include")]
 
     def compile_one(src):
         obj = os.path.join(OBJDIR, src + ".o")
+        if not force and not _stale(os.path.join(CSRC, src), obj, [CSRC, os.path.join(os.path.dirname(HERE), "include")]):
+            return obj
         cmd = [hipcc, *FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
@@ -56,4 +68,4 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, force="--changed" not in sys.argv))

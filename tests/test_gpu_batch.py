@@ -176,3 +176,34 @@ def test_batch_many_groups_mixed_halves_with_polls():
         assert np.array_equal(c.factors()[0], s.factors()[0])
         assert np.array_equal(c.factors()[1], s.factors()[1])
     b.close()
+
+
+def test_batch_problems_match_oracle(orc):
+    # uneven problems (k from 2 to 8; halves as one kernel and as split
+    # kernels) swept in one batch, each against the FP64 oracle's sweeps
+    import torch
+    from paper_2101_08431_amd import Batch
+    rng = np.random.default_rng(10300)
+    probs = []
+    for q in range(10):
+        big = q % 3 == 0   # above 2^18 entries: split halves
+        n = int(rng.integers(1200, 2400)) if big else int(rng.integers(100, 900))
+        m = int(rng.integers(230, 400)) if big else int(rng.integers(20, 200))
+        k = 2 + q % 7
+        M, X0, Y0 = synth.make(dict(kind="pdf", n=n, m=m, k=k, sigma=1e-3, sigma_relative=True), 10300 + q)
+        probs.append((M, X0, Y0, k))
+    print("case batch of 10 uneven problems vs oracle", flush=True)
+    ctxs = contexts(probs)
+    plans = [c.launch_plan() for c in ctxs]
+    assert any(not p[2] for p in plans) and any(p[2] for p in plans)
+    b = Batch(ctxs)
+    b.step(7, graph=True)
+    b.sync()
+    torch.cuda.synchronize()
+    for (M, X0, Y0, k), c in zip(probs, ctxs):
+        X, Y = c.factors()
+        ref = orc.anls(M, X0, Y0.T.copy(), exact_sweeps=7)
+        scale = max(np.abs(ref["X"]).max(), np.abs(ref["Yt"]).max())
+        err = max(np.abs(X - ref["X"]).max(), np.abs(Y.T - ref["Yt"]).max()) / scale
+        assert err <= 1e-8, (k, M.shape, err)
+    b.close()

@@ -71,3 +71,37 @@ def test_mix_equals_alone_across_launch_shape_change():
         assert a.rid == b.rid
         assert a.sweeps == b.sweeps, (a.rid, a.sid, a.sweeps, b.sweeps)
         assert np.array_equal(a.result[0], b.result[0]) and np.array_equal(a.result[1], b.result[1]), (a.rid, a.sid)
+
+
+def test_served_requests_match_oracle(orc):
+    # fixed sweep budgets (no stop rule) make every request's work a known
+    # count, so the oracle can replay each stream: its first window for
+    # `initial` sweeps, then per request the Y-half over all columns with the
+    # appended ones (nmf_append_columns) and `per_req` sweeps (Alg. 1)
+    initial, per_req = 30, 6
+    specs, reqs = build_workload(streams=4, rate=400.0, seconds=0.03, m0=24, add=8, seed=11, big_every=2,
+                                 small=(300, 3), big=(600, 5))
+    print(f"case served requests vs oracle: {len(reqs)} requests on 4 streams", flush=True)
+    srv = Server(specs, eps_stol=-1.0, initial_sweeps=initial, request_sweeps=per_req, record=True,
+                 sweeps_per_round=3, max_active=64)
+    srv.open_all()
+    out = srv.run([Request(r.rid, r.sid, r.cols, r.arrival) for r in reqs])
+    srv.close_all()
+    assert max(srv.batch_sizes) > 1
+    state = {}
+    for sp in specs:
+        ref = orc.anls(sp.M0, sp.X0, sp.Y0.T.copy(), exact_sweeps=initial)
+        state[sp.sid] = (np.asfortranarray(sp.M0), ref["X"], ref["Yt"])
+    for r in out:   # arrival order is each stream's request order
+        M, X, Yt = state[r.sid]
+        M = np.asfortranarray(np.hstack([M, r.cols]))
+        Yt = np.vstack([Yt, np.zeros((r.cols.shape[1], Yt.shape[1]))])
+        Yt, _, bad = orc.half_y(M, X, Yt)
+        assert bad == 0
+        ref = orc.anls(M, X, Yt, exact_sweeps=per_req)
+        state[r.sid] = (M, ref["X"], ref["Yt"])
+        assert r.sweeps == per_req
+        Xg, Yg = r.result
+        scale = max(np.abs(ref["X"]).max(), np.abs(ref["Yt"]).max())
+        err = max(np.abs(Xg - ref["X"]).max(), np.abs(Yg.T - ref["Yt"]).max()) / scale
+        assert err <= 1e-8, (r.rid, r.sid, err)
