@@ -230,6 +230,22 @@ size_t nmf_batch_workspace_bytes(int32_t count);
 nmf_status nmf_batch_create(nmf_ctx *const *ctxs, int32_t count, void *device_workspace, size_t ws_bytes,
                             void *hip_stream, nmf_batch **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, request loops that must not call hipMalloc, harnesses that forbid
+ * it): nmf_batch_create() without a caller workspace.  The batch tables live
+ * in a fixed array of device memory inside the library, one copy per device
+ * (batch_bytes(NMF_BATCH_STATIC_MAX), 304 KiB, held until the process
+ * ends), looked up on the current device, which must be the contexts' device.
+ * Nothing is allocated on the device.  The array is shared by every batch made
+ * this way on that device: creating another one (or refreshing one) rewrites
+ * the tables, so only the most recent such batch may be stepped or polled, and
+ * calls that overlap on one device race.  Batches made with a workspace are
+ * not affected.  Results are those of nmf_batch_create() on the same contexts.
+ * Errors: as nmf_batch_create(); NMF_ECAPACITY when count exceeds
+ * NMF_BATCH_STATIC_MAX. */
+#define NMF_BATCH_STATIC_MAX 1024
+nmf_status nmf_batch_create_static(nmf_ctx *const *ctxs, int32_t count, void *hip_stream, nmf_batch **out);
+
 /* Re-reads the contexts' sizes and launch shapes (after nmf_set_launch_shape
  * or nmf_append_columns) and drops any captured graph. */
 nmf_status nmf_batch_refresh(nmf_batch *b);

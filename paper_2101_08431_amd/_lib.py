@@ -27,7 +27,9 @@ EXPORTS = [
     "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
     "nmf_get_duals", "nmf_set_launch_shape", "nmf_set_launch_fusion", "nmf_get_launch_shape", "nmf_set_anls_budget", "nmf_batch_workspace_bytes", "nmf_batch_create",
     "nmf_batch_refresh", "nmf_batch_anls_step", "nmf_batch_poll", "nmf_batch_sync", "nmf_batch_destroy",
+    "nmf_batch_create_static",
 ]
+BATCH_STATIC_MAX = 1024   # NMF_BATCH_STATIC_MAX
 
 
 class Options(ctypes.Structure):
@@ -146,6 +148,8 @@ def load():
     L.nmf_batch_workspace_bytes.restype = ctypes.c_size_t
     L.nmf_batch_create.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.nmf_batch_create.restype = ctypes.c_int
+    L.nmf_batch_create_static.argtypes = [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(vp)]
+    L.nmf_batch_create_static.restype = ctypes.c_int
     for name in ("nmf_batch_refresh", "nmf_batch_sync", "nmf_batch_destroy"):
         getattr(L, name).argtypes = [vp]
         getattr(L, name).restype = ctypes.c_int
@@ -350,7 +354,10 @@ class Batch:
     include/nmf.h).  Uses its own non-default stream so sweeps can be captured
     into a HIP graph."""
 
-    def __init__(self, contexts, stream=None):
+    def __init__(self, contexts, stream=None, static=False):
+        """static=True builds the batch with nmf_batch_create_static: no
+        workspace is allocated (the library's own per-device table array is
+        used, so only the most recent static batch is valid)."""
         import torch
         L = load()
         self.contexts = list(contexts)
@@ -361,10 +368,14 @@ class Batch:
         # the contexts' setup work runs on their own streams
         for c in self.contexts:
             c.stream.synchronize()
-        nbytes = int(L.nmf_batch_workspace_bytes(n))
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        st = L.nmf_batch_create(arr, n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
-                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(out))
+        if static:
+            self.workspace = None
+            st = L.nmf_batch_create_static(arr, n, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(out))
+        else:
+            nbytes = int(L.nmf_batch_workspace_bytes(n))
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            st = L.nmf_batch_create(arr, n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(out))
         if st != NMF_OK:
             raise NMFError(st, L.nmf_last_error(None).decode())
         self._b = out

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -747,9 +748,40 @@ struct nmf_batch {
 // NBK * 2 * count entries over all groups (a group has at least one member).
 static size_t offsets_bytes(size_t count) { return align_up((size_t)nmfk::NBK * 2 * count * sizeof(int), 256); }
 
-static size_t batch_bytes(int32_t count) {
-    return align_up((size_t)count * sizeof(AnlsParams), 256) + offsets_bytes((size_t)count) +
-           align_up((size_t)2 * count * sizeof(long long), 256) + 256;
+static constexpr size_t batch_bytes(int32_t count) {
+    return ((size_t)count * sizeof(AnlsParams) + 255) / 256 * 256 +
+           ((size_t)nmfk::NBK * 2 * count * sizeof(int) + 255) / 256 * 256 +
+           ((size_t)2 * count * sizeof(long long) + 255) / 256 * 256 + 256;
+}
+
+// Batch tables of nmf_batch_create_static: one copy per device, in device
+// memory that the library owns for the life of the process.  Host code never
+// passes the array's name to a kernel or a copy: it uses the address
+// hipGetSymbolAddress returns on each device (static_scratch()).
+constexpr size_t kStaticBatchBytes = batch_bytes(NMF_BATCH_STATIC_MAX);
+static __device__ __align__(256) uint8_t scratch[kStaticBatchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current.
+static hipError_t static_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 static void drop_graph(nmf_batch *b) {
@@ -855,6 +887,19 @@ nmf_status nmf_batch_create(nmf_ctx *const *ctxs, int32_t count, void *ws, size_
     }
     *out = b;
     return NMF_OK;
+}
+
+nmf_status nmf_batch_create_static(nmf_ctx *const *ctxs, int32_t count, void *stream, nmf_batch **out) {
+    if (!out || !ctxs || count < 1) return fail(nullptr, NMF_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    if (count > NMF_BATCH_STATIC_MAX)
+        return fail(nullptr, NMF_ECAPACITY,
+                    "nmf_batch_create_static: " + std::to_string(count) + " contexts exceed the static batch limit of " +
+                        std::to_string(NMF_BATCH_STATIC_MAX));
+    void *ws = nullptr;
+    const hipError_t e = static_scratch(&ws);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress of the static batch tables");
+    return nmf_batch_create(ctxs, count, ws, kStaticBatchBytes, stream, out);
 }
 
 static nmf_status batch_enqueue(nmf_batch *b, int sweeps) {
