@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmf_hip.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["anls.hip", "ipm.hip", "nmf_api.hip"]
+SOURCES = ["anls.hip", "ipm.hip", "dense.hip", "nmf_api.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep packed FP32 instructions out of the generated code

@@ -1,0 +1,782 @@
+// Dense linear algebra of the interior-point stage (Sec. III-B, eq. (20)):
+// formation of the Gauss-Newton Schur complement, its Cholesky factorisation
+// and the two triangular solves, on FP64 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Ordering of S.  The unknowns dy are ordered component-major, row a*m + j for
+// Y_aj.  Then S = Q2bar - sum_i (x_i x_i^T) (x) C_i with C_i[j][l] =
+// Y_j^T Q1bar_i^-1 Y_l = Z_i[:, j] . Z_i[:, l] (Z_i = L_i^-1 Y): the k x k grid
+// of m x m blocks, block (a, b) = sum_i X_ia X_ib C_i, is symmetric block by
+// block, so one product C_i[J, L] of a 16 x 16 tile pair (J >= L) serves
+// every (a, b) with a >= b and its mirrored tile.
+//
+// S is stored column-major with leading dimension ldS >= NT*64 and padded to
+// NT*64 rows and columns with the identity, so every kernel works on whole
+// 64 x 64 tiles.  Only the lower triangle is read.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "dense.h"
+
+namespace nmfk {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// D = A B + C on one 16 x 16 x 4 FP64 matrix-core step.  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16]
+// (v = 0..3; checked on the device).
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// 1/sqrt(v) for v > 0: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double v) {
+    double y = __builtin_amdgcn_rsq(v);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-v * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+__device__ __forceinline__ double lane_read(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Orders this wave's LDS accesses (a wave executes its LDS operations in
+// order; this keeps the compiler from moving them across the point).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr unsigned kSpinLimit = 1u << 24;   // ~1 s of polling, then give up and flag it
+
+// Publishes flags[idx] = epoch after every store of the block (release,
+// device scope).
+__device__ __forceinline__ void post_flag(unsigned *flags, int idx, unsigned epoch) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(flags + idx, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ------------------------------------------------------------- Schur complement
+// Tile pair index -> (jt, lt), jt >= lt, row-major over the lower triangle.
+__device__ __forceinline__ void tri_pair(int64_t tp, int64_t &jt, int64_t &lt) {
+    jt = (int64_t)((sqrt(8.0 * (double)tp + 1.0) - 1.0) * 0.5);
+    while ((jt + 1) * (jt + 2) / 2 <= tp) ++jt;
+    while (jt * (jt + 1) / 2 > tp) --jt;
+    lt = tp - jt * (jt + 1) / 2;
+}
+
+// Packed index t of (a, b), a >= b: t = a (a + 1) / 2 + b.
+__device__ __forceinline__ void tri_ab(int t, int &a, int &b) {
+    a = 0;
+    while ((a + 1) * (a + 2) / 2 <= t) ++a;
+    b = t - a * (a + 1) / 2;
+}
+
+// Writes one 16 x 16 tile of block (a, b) of S (lane values in the matrix-
+// core output layout) and, for a > b off the diagonal tile, its mirror; on
+// the diagonal tile adds delta_jl Q2bar_j[a][b] = G_X[a][b] + delta_ab (rho +
+// s_aj / y_aj).
+template <int K>
+__device__ __forceinline__ void schur_store(const SchurArgs &g, int64_t jt, int64_t lt, int a, int b, const double (&val)[4]) {
+    const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
+    const int64_t m = g.m;
+    const int64_t l = lt * 16 + r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t j = jt * 16 + gq + 4 * v;
+        if (j < m && l < m) {
+            double x = val[v];
+            if (jt == lt && j == l) {
+                x = g.GX[a * K + b] - x;
+                if (a == b) x += g.rho + g.s[(int64_t)a * g.ldY + j] / g.Y[(int64_t)a * g.ldY + j];
+            } else {
+                x = -x;
+            }
+            g.S[(b * m + l) * g.ldS + a * m + j] = x;
+            if (a > b && jt != lt) g.S[(b * m + j) * g.ldS + a * m + l] = x;
+        }
+    }
+}
+
+// One wave per unit (tile pair, (a,b) chunk); the four waves of a block
+// share a row split, whose rows i they sum of X_ia X_ib C_i[J, L], C_i[J, L]
+// from KS matrix-core steps over the (zero-padded) components of Z_i.  The
+// X_ia X_ib of CH rows at a time are staged in LDS (one copy per block,
+// broadcast reads); the Z operands of the next RU rows are loaded while the
+// current RU rows are summed.
+template <int K>
+__global__ __launch_bounds__(256) void k_schur_gn(SchurArgs g) {
+    constexpr int NL = K * (K + 1) / 2;
+    constexpr int NCH = (NL + 35) / 36;
+    constexpr int CS = (NL + NCH - 1) / NCH;
+    constexpr int KS = zpad(K) / 4;
+    constexpr int RU = 4;
+    constexpr int CH = 32;
+    __shared__ double xs[CH * NL];
+    const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int p = (int)(blockIdx.x % g.P);
+    const int64_t wu = (int64_t)(blockIdx.x / g.P) * 4 + wave;
+    const int64_t nunits = (int64_t)g.npairs * NCH;
+    const bool active = wu < nunits;   // wave-uniform
+    const int ch = active ? (int)(wu % NCH) : 0;
+    const int64_t tp = active ? wu / NCH : 0;
+    int64_t jt, lt;
+    tri_pair(tp, jt, lt);
+    const int64_t i0 = (int64_t)p * g.rows_per_split;
+    const int64_t i1 = min(g.n, i0 + g.rows_per_split);
+    const int t0 = ch * CS;
+    int64_t offA[KS], offB[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        offA[s] = (int64_t)(gq + 4 * s) * g.ldY + jt * 16 + r;
+        offB[s] = (int64_t)(gq + 4 * s) * g.ldY + lt * 16 + r;
+    }
+    const int64_t zstride = (int64_t)zpad(K) * g.ldY;
+    double acc[CS][4];
+#pragma unroll
+    for (int t = 0; t < CS; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[t][v] = 0.0;
+    for (int64_t c0 = i0; c0 < i1; c0 += CH) {
+        const int nr = (int)min((int64_t)CH, i1 - c0);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < nr * NL; idx += 256) xs[idx] = g.XX[c0 * NL + idx];
+        __syncthreads();
+        if (!active) continue;
+        double av[RU][KS], bv[RU][KS], an[RU][KS], bn[RU][KS];
+#pragma unroll
+        for (int uu = 0; uu < RU; ++uu) {
+            const double *zi = g.Z + (c0 + min(uu, nr - 1)) * zstride;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                av[uu][s] = zi[offA[s]];
+                bv[uu][s] = zi[offB[s]];
+            }
+        }
+        for (int rb = 0; rb < nr; rb += RU) {
+            // next group (rows clamped into the chunk: loads stay in range)
+#pragma unroll
+            for (int uu = 0; uu < RU; ++uu) {
+                const double *zi = g.Z + (c0 + min(rb + RU + uu, nr - 1)) * zstride;
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    an[uu][s] = zi[offA[s]];
+                    bn[uu][s] = zi[offB[s]];
+                }
+            }
+#pragma unroll
+            for (int uu = 0; uu < RU; ++uu) {
+                if (rb + uu < nr) {   // wave-uniform
+                    v4d c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) c = mfma16(av[uu][s], bv[uu][s], c);
+                    const double *xr = xs + (rb + uu) * NL + t0;
+#pragma unroll
+                    for (int t = 0; t < CS; ++t) {
+                        if (t0 + t < NL) {
+                            const double w = xr[t];
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acc[t][v] = fma(c[v], w, acc[t][v]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int uu = 0; uu < RU; ++uu)
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    av[uu][s] = an[uu][s];
+                    bv[uu][s] = bn[uu][s];
+                }
+        }
+    }
+    if (!active) return;
+    if (g.P == 1) {
+#pragma unroll
+        for (int t = 0; t < CS; ++t) {
+            if (t0 + t < NL) {
+                int a, b;
+                tri_ab(t0 + t, a, b);
+                schur_store<K>(g, jt, lt, a, b, acc[t]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < CS; ++t) {
+            if (t0 + t < NL) {
+                double *dst = g.part + (((int64_t)p * g.npairs + tp) * NL + t0 + t) * 256 + lane * 4;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dst[v] = acc[t][v];
+            }
+        }
+    }
+}
+
+// Sums the row-split partials in split order and stores them into S; one
+// wave per (tile pair, (a, b)).
+template <int K>
+__global__ __launch_bounds__(256) void k_schur_reduce(SchurArgs g) {
+    constexpr int NL = K * (K + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (u >= (int64_t)g.npairs * NL) return;
+    const int t = (int)(u % NL);
+    const int64_t tp = u / NL;
+    double val[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = 0; p < g.P; ++p) {
+        const double *src = g.part + (((int64_t)p * g.npairs + tp) * NL + t) * 256 + lane * 4;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) val[v] += src[v];
+    }
+    int64_t jt, lt;
+    tri_pair(tp, jt, lt);
+    int a, b;
+    tri_ab(t, a, b);
+    schur_store<K>(g, jt, lt, a, b, val);
+}
+
+// XX[i][t] = X_ia X_ib for t = (a, b), a >= b.
+template <int K>
+__global__ __launch_bounds__(256) void k_xx(const double *X, int64_t ldX, int64_t n, double *XX) {
+    constexpr int NL = K * (K + 1) / 2;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double x[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) x[a] = X[(int64_t)a * ldX + i];
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) XX[i * NL + a * (a + 1) / 2 + b] = x[a] * x[b];
+}
+
+// Identity in the padding rows and columns [N, Np) of S (lower triangle).
+__global__ __launch_bounds__(256) void k_pad_identity(double *S, int64_t ldS, int64_t N, int64_t Np) {
+    const int64_t col = blockIdx.x;   // 0 .. Np-1
+    for (int64_t row = N + threadIdx.x; row < Np; row += 256) {
+        if (row >= col) S[col * ldS + row] = (row == col) ? 1.0 : 0.0;
+    }
+}
+
+// ------------------------------------------------------------- Cholesky of S
+// Column c of a 64 x 64 factor kept in LDS (Lc[c*64 + p]), rows from c+1 on,
+// loaded in 16-byte pairs, all issued before any is used.
+template <int C>
+__device__ __forceinline__ void load_col_tail(const double *Lc, double (&v)[64]) {
+    const double2 *col = reinterpret_cast<const double2 *>(Lc + C * 64);
+#pragma unroll
+    for (int p2 = (C + 1) / 2; p2 < 32; ++p2) {
+        const double2 w = col[p2];
+        v[2 * p2] = w.x;
+        v[2 * p2 + 1] = w.y;
+    }
+}
+
+// Pivot C of the right-looking factorisation (lane = row): the pivot comes
+// from lane C's fully updated a[C]; this lane's entry of column C is returned
+// and published in Lc.
+template <int C>
+__device__ __forceinline__ double pivot_publish(double (&a)[64], double *Lc, bool &ok, double &mydiag, int lane) {
+    const double d = lane_read(a[C], C);
+    ok = ok && (d > 0.0);
+    const double dd = d > 0.0 ? d : 1.0;
+    const double s = rsqrt_nr(dd);
+    double l = 0.0;
+    if (lane > C) l = a[C] * s;
+    if (lane == C) {
+        l = dd * s;
+        mydiag = l;
+    }
+    Lc[C * 64 + lane] = l;
+    return l;
+}
+
+// Step C with one step of look-ahead: column C is published (this lane's
+// entry lC); the lane first updates a[C+1] with it, forms and publishes pivot
+// C+1, and only then applies column C to the rest of its row, so that the
+// updates overlap the next column's round trip through LDS.
+template <int C>
+struct PotrfStep {
+    static __device__ __forceinline__ void run(double (&a)[64], double *Lc, bool &ok, double &mydiag, int lane,
+                                               double lC) {
+        wave_lds_sync();
+        double col[64];
+        load_col_tail<C>(Lc, col);
+        if (C + 1 < 64) {
+            constexpr int N1 = C + 1 < 64 ? C + 1 : 63;
+            a[N1] = fma(-lC, col[N1], a[N1]);
+            const double lN = pivot_publish<N1>(a, Lc, ok, mydiag, lane);
+#pragma unroll
+            for (int j = C + 2; j < 64; ++j) a[j] = fma(-lC, col[j], a[j]);
+            PotrfStep<C + 1>::run(a, Lc, ok, mydiag, lane, lN);
+        }
+    }
+};
+template <>
+struct PotrfStep<64> {
+    static __device__ __forceinline__ void run(double (&)[64], double *, bool &, double &, int, double) {}
+};
+
+// Factor of one 64 x 64 tile by one wave (right-looking: step c publishes
+// column c in LDS and updates the rows below it independently).  T holds the
+// tile (row-major, stride 65; the lower triangle is read).  On return Lc
+// holds L column by column (Lc[q*64 + p] = L[p][q], zeros above the diagonal).
+// A pivot that is not positive sets *bad and is replaced by 1.
+__device__ __forceinline__ void potrf_wave(const double *T, double *Lc, int *bad) {
+    const int lane = threadIdx.x & 63;
+    double a[64];
+#pragma unroll
+    for (int q = 0; q < 64; ++q) a[q] = (q <= lane) ? T[lane * 65 + q] : 0.0;
+    bool ok = true;
+    double mydiag = 1.0;
+    const double l0 = pivot_publish<0>(a, Lc, ok, mydiag, lane);
+    PotrfStep<0>::run(a, Lc, ok, mydiag, lane, l0);
+    wave_lds_sync();
+    if (!ok && lane == 0) *bad = 1;
+}
+
+// Broadcast of lane OWNER's value within each quad of lanes (DPP quad_perm).
+template <int OWNER>
+__device__ __forceinline__ double quad_bcast(double v) {
+    constexpr int ctrl = OWNER * 0x55;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Step Q of X = A L^-T with four lanes per row (quad): lane part P owns
+// columns 16P..16P+15 of its row in x[].  The owner of column Q scales it by
+// 1 / L_QQ, the quad shares it, and every lane updates its own columns with
+// column Q of the strictly lower part of L (Lz, zeros on and above the
+// diagonal, so no lane needs a bound); column Q+1 is loaded one step ahead.
+template <int Q>
+struct TrsmQuadStep {
+    static __device__ __forceinline__ void run(double (&x)[16], const double *Lz, const double *dsh, int part,
+                                               const double (&cur)[16], double dcur) {
+        constexpr int OWNER = Q >> 4, UQ = Q & 15;
+        double nxt[16], dnxt = 0.0;
+        if (Q + 1 < 64) {
+            const double2 *col = reinterpret_cast<const double2 *>(Lz + (Q + 1 < 64 ? Q + 1 : 63) * 64 + part * 16);
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const double2 w = col[h];
+                nxt[2 * h] = w.x;
+                nxt[2 * h + 1] = w.y;
+            }
+            dnxt = dsh[Q + 1 < 64 ? Q + 1 : 63];
+        }
+        if (part == OWNER) x[UQ] *= dcur;
+        const double xq = quad_bcast<OWNER>(x[UQ]);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) x[v] = fma(-xq, cur[v], x[v]);
+        TrsmQuadStep<Q + 1>::run(x, Lz, dsh, part, nxt, dnxt);
+    }
+};
+template <>
+struct TrsmQuadStep<64> {
+    static __device__ __forceinline__ void run(double (&)[16], const double *, const double *, int,
+                                               const double (&)[16], double) {}
+};
+
+// X = A L^-T for a 64 x 64 tile by a block of 256 threads: thread (row =
+// 16*wave + lane/4, part = lane%4) starts from x = A[row][16 part ..] and
+// ends with X[row][16 part ..].  Lz: strictly lower part of L column by
+// column (Lz[q*64 + p] = L[p][q] for p > q, else 0); dsh[q] = 1 / L_qq.
+__device__ __forceinline__ void trsm_quad(double (&x)[16], const double *Lz, const double *dsh) {
+    const int part = threadIdx.x & 3;
+    double c0[16];
+    const double2 *col = reinterpret_cast<const double2 *>(Lz + part * 16);
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        const double2 w = col[h];
+        c0[2 * h] = w.x;
+        c0[2 * h + 1] = w.y;
+    }
+    TrsmQuadStep<0>::run(x, Lz, dsh, part, c0, dsh[0]);
+}
+
+// Step kt (-1 .. NT-2) of the right-looking factorisation by 64-wide block
+// columns, for column c = kt + 1:
+//   every tile (i, j), c <= j <= i, gets A_ij -= L_i,kt L_j,kt^T (kt >= 0);
+//   blocks 0 .. NT-c-1 serve the tiles (c + b, c) of column c: each updates
+//   the diagonal tile (c, c) as well as its own and factors it (the same
+//   arithmetic in every such block, so every copy of L_cc is identical); block
+//   0 stores L_cc, the others solve their panel tile L_ic = A_ic L_cc^-T;
+//   the other blocks, tiles right of column c, only store their update.
+// No block waits for another.  The inverses of the diagonal factor tiles (for
+// the triangular solves) are formed after the last step (k_chol_inverses).
+__global__ __launch_bounds__(256) void k_chol_step(CholArgs g, int kt) {
+    __shared__ __align__(16) double T[64 * 65];
+    __shared__ __align__(16) double Lc[64 * 64];
+    __shared__ double dsh[64];
+    const int c = kt + 1;
+    const int NT = g.NT;
+    const int bid = blockIdx.x;
+    const int npanel = NT - c;
+    int ti, tj;
+    if (bid < npanel) {
+        ti = c + bid;
+        tj = c;
+    } else {
+        // trailing tiles c < tj <= ti < NT, column by column
+        int rr = bid - npanel;
+        tj = c + 1;
+        while (rr >= NT - tj) {
+            rr -= NT - tj;
+            ++tj;
+        }
+        ti = tj + rr;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
+    const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+    double *S = g.S;
+    const int64_t ldS = g.ldS;
+    const int64_t rb = (int64_t)ti * 64, cb = (int64_t)tj * 64;
+    const bool colc = tj == c;               // block of column c
+    const bool diag = colc && ti == c;
+    const int64_t db = (int64_t)c * 64;
+    // acc[x][y][v] is tile entry (R0 + 16x + r, C0 + 16y + gq + 4v): the
+    // products below are formed transposed (B^T A^T) so that 16 lanes hold 16
+    // consecutive rows of one column.  dac is the same for tile (c, c).
+    v4d acc[2][2], dac[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                acc[x][y][v] = S[(cb + C0 + 16 * y + gq + 4 * v) * ldS + rb + R0 + 16 * x + r];
+                dac[x][y][v] = (colc && !diag) ? S[(db + C0 + 16 * y + gq + 4 * v) * ldS + db + R0 + 16 * x + r] : 0.0;
+            }
+    if (kt >= 0) {
+        const int64_t kb = (int64_t)kt * 64;
+        double av[16][2], bv[16][2], dv[16][2];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const double *col = S + (kb + 4 * s + gq) * ldS;
+            av[s][0] = -col[rb + R0 + r];
+            av[s][1] = -col[rb + R0 + 16 + r];
+            bv[s][0] = col[cb + C0 + r];
+            bv[s][1] = col[cb + C0 + 16 + r];
+            dv[s][0] = (colc && !diag) ? -col[db + R0 + r] : 0.0;
+            dv[s][1] = (colc && !diag) ? -col[db + R0 + 16 + r] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) acc[x][y] = mfma16(bv[s][y], av[s][x], acc[x][y]);
+        if (colc && !diag) {
+            // the diagonal tile's update: its columns are those of column c
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) dac[x][y] = mfma16(bv[s][y], dv[s][x], dac[x][y]);
+        }
+    }
+    if (!colc) {
+        // trailing tile: store the update
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    S[(cb + C0 + 16 * y + gq + 4 * v) * ldS + rb + R0 + 16 * x + r] = acc[x][y][v];
+        return;
+    }
+    // diagonal tile -> T (row-major, stride 65); own panel tile -> Lc (row-major, stride 64)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = R0 + 16 * x + r, cl = C0 + 16 * y + gq + 4 * v;
+                if (diag) {
+                    T[row * 65 + cl] = acc[x][y][v];
+                } else {
+                    T[row * 65 + cl] = dac[x][y][v];
+                    Lc[row * 64 + cl] = acc[x][y][v];
+                }
+            }
+    __syncthreads();
+    const int qrow = 16 * wave + (lane >> 2), part = lane & 3;
+    double x16[16];
+    if (!diag) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) x16[v] = Lc[qrow * 64 + part * 16 + v];
+    }
+    __syncthreads();
+    if (wave == 0) potrf_wave(T, Lc, g.fail);
+    __syncthreads();
+    if (diag) {
+        for (int idx = threadIdx.x; idx < 4096; idx += 256) S[(db + (idx >> 6)) * ldS + db + (idx & 63)] = Lc[idx];
+        return;
+    }
+    // strictly lower part of L_cc into T (column by column) and 1 / diagonal
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+        const int q = idx >> 6, pp = idx & 63;
+        const double v = Lc[idx];
+        T[idx] = pp > q ? v : 0.0;
+        if (pp == q) dsh[q] = 1.0 / v;
+    }
+    __syncthreads();
+    trsm_quad(x16, T, dsh);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) S[(db + part * 16 + v) * ldS + rb + qrow] = x16[v];
+}
+
+// Inverses of the NT diagonal factor tiles, one block per tile: row j of
+// I L^-T is column j of L^-1, stored column-major (Dinv[j*64 + i] = L^-1[i][j]).
+__global__ __launch_bounds__(256) void k_chol_inverses(CholArgs g) {
+    __shared__ __align__(16) double Lz[64 * 64];
+    __shared__ double dsh[64];
+    const int t = blockIdx.x;
+    const int64_t db = (int64_t)t * 64;
+    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
+        const int q = idx >> 6, pp = idx & 63;
+        const double v = g.S[(db + q) * g.ldS + db + pp];
+        Lz[idx] = pp > q ? v : 0.0;
+        if (pp == q) dsh[q] = 1.0 / v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = 16 * wave + (lane >> 2), part = lane & 3;
+    double x[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) x[v] = (part * 16 + v == row) ? 1.0 : 0.0;
+    trsm_quad(x, Lz, dsh);
+    double *D = g.Dinv + (int64_t)t * 4096 + row * 64 + part * 16;
+#pragma unroll
+    for (int v = 0; v < 16; v += 2) *reinterpret_cast<double2 *>(D + v) = make_double2(x[v], x[v + 1]);
+}
+
+// ------------------------------------------------------------- triangular solves
+// Thread 0 waits for flags[q] == epoch, then extends over the following
+// flags of the range [q, end) (step dir = +1 or -1) that are already set, and
+// returns (through LDS) the last ready index; one acquire fence covers them.
+__device__ __forceinline__ int wait_run(const unsigned *flags, int q, int end, int dir, unsigned epoch, int *fail,
+                                        int *s_last) {
+    if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                atomicExch(fail, 2);
+                break;
+            }
+        }
+        int h = q;
+        while (h + dir != end &&
+               __hip_atomic_load(flags + h + dir, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch)
+            h += dir;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_last = h;
+    }
+    __syncthreads();
+    return *s_last;
+}
+
+// Forward solve L y = b by 64-row tiles, one block per tile, in one launch:
+// block t accumulates L_tq y_q for q < t as the y_q are published, then
+// y_t = Dinv[t] (b_t - sum).  Blocks wait only on lower block indices.  The
+// tile of L needed next is loaded before each wait.
+__global__ __launch_bounds__(256) void k_trsv_fwd_lb(SolveArgs g) {
+    __shared__ double red[4][64];
+    __shared__ double vs[64];
+    __shared__ int s_last;
+    const int t = blockIdx.x;
+    const int r = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int64_t ldS = g.ldS;
+    const double *Lrow = g.S + (int64_t)part * 16 * ldS + (int64_t)t * 64 + r;   // + q*64*ldS + u*ldS
+    double acc = 0.0, Lp[16], Dv[16];
+    // this tile's inverse diagonal block and right-hand side, loaded before
+    // any wait
+    const double *D = g.Dinv + (int64_t)t * 4096;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) Dv[u] = D[(part * 16 + u) * 64 + r];
+    const double bt = g.b[(int64_t)t * 64 + r];
+    if (t > 0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) Lp[u] = Lrow[(int64_t)u * ldS];
+    }
+    int q = 0;
+    while (q < t) {
+        const int h = wait_run(g.flags, q, t, 1, g.epoch, g.fail, &s_last);
+        for (; q <= h; ++q) {
+            double Lc[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) Lc[u] = Lp[u];
+            if (q + 1 < t) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) Lp[u] = Lrow[((int64_t)(q + 1) * 64 + u) * ldS];
+            }
+            const double *yq = g.y + (int64_t)q * 64 + part * 16;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc = fma(-Lc[u], yq[u], acc);
+        }
+        __syncthreads();
+    }
+    red[part][r] = acc;
+    __syncthreads();
+    if (part == 0) vs[r] = bt + ((red[0][r] + red[1][r]) + (red[2][r] + red[3][r]));
+    __syncthreads();
+    double w = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) w = fma(Dv[u], vs[part * 16 + u], w);
+    __syncthreads();
+    red[part][r] = w;
+    __syncthreads();
+    if (part == 0) g.y[(int64_t)t * 64 + r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    post_flag(g.flags, t, g.epoch);
+}
+
+// Backward solve L^T x = y in place on y, tiles from the last up: block b
+// serves tile t = NT-1-b and accumulates L_qt^T x_q for q > t as the x_q are
+// published, then x_t = Dinv[t]^T (y_t - sum).
+__global__ __launch_bounds__(256) void k_trsv_bwd_lb(SolveArgs g) {
+    __shared__ double red[4][64];
+    __shared__ double vs[64];
+    __shared__ int s_last;
+    const int NT = g.NT;
+    const int t = NT - 1 - (int)blockIdx.x;
+    const int r = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int64_t ldS = g.ldS;
+    const double *Lcol = g.S + ((int64_t)t * 64 + r) * ldS + part * 16;   // + q*64 + u
+    double acc = 0.0, Lp[16], Dv[16];
+    const double *D = g.Dinv + (int64_t)t * 4096 + (int64_t)r * 64 + part * 16;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) Dv[u] = D[u];
+    if (t < NT - 1) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) Lp[u] = Lcol[(int64_t)(NT - 1) * 64 + u];
+    }
+    int q = NT - 1;
+    while (q > t) {
+        const int h = wait_run(g.flags, q, t, -1, g.epoch, g.fail, &s_last);
+        for (; q >= h; --q) {
+            double Lc[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) Lc[u] = Lp[u];
+            if (q - 1 > t) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) Lp[u] = Lcol[(int64_t)(q - 1) * 64 + u];
+            }
+            const double *xq = g.y + (int64_t)q * 64 + part * 16;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc = fma(-Lc[u], xq[u], acc);
+        }
+        __syncthreads();
+    }
+    red[part][r] = acc;
+    __syncthreads();
+    if (part == 0) vs[r] = g.y[(int64_t)t * 64 + r] + ((red[0][r] + red[1][r]) + (red[2][r] + red[3][r]));
+    __syncthreads();
+    double w = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) w = fma(Dv[u], vs[part * 16 + u], w);
+    __syncthreads();
+    red[part][r] = w;
+    __syncthreads();
+    if (part == 0) g.y[(int64_t)t * 64 + r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+    post_flag(g.flags, t, g.epoch);
+}
+
+// ------------------------------------------------------------- launchers
+#define DENSE_K_SWITCH(K, CALL)                                  \
+    switch (K) {                                                 \
+        case 1: { constexpr int KK = 1; CALL; } break;           \
+        case 2: { constexpr int KK = 2; CALL; } break;           \
+        case 3: { constexpr int KK = 3; CALL; } break;           \
+        case 4: { constexpr int KK = 4; CALL; } break;           \
+        case 5: { constexpr int KK = 5; CALL; } break;           \
+        case 6: { constexpr int KK = 6; CALL; } break;           \
+        case 7: { constexpr int KK = 7; CALL; } break;           \
+        case 8: { constexpr int KK = 8; CALL; } break;           \
+        case 9: { constexpr int KK = 9; CALL; } break;           \
+        case 10: { constexpr int KK = 10; CALL; } break;         \
+        case 11: { constexpr int KK = 11; CALL; } break;         \
+        case 12: { constexpr int KK = 12; CALL; } break;         \
+        case 13: { constexpr int KK = 13; CALL; } break;         \
+        case 14: { constexpr int KK = 14; CALL; } break;         \
+        case 15: { constexpr int KK = 15; CALL; } break;         \
+        case 16: { constexpr int KK = 16; CALL; } break;         \
+        default: return hipErrorInvalidValue;                    \
+    }
+
+int schur_chunks(int K) {
+    const int NL = K * (K + 1) / 2;
+    return (NL + 35) / 36;
+}
+
+hipError_t launch_xx(int K, const double *X, int64_t ldX, int64_t n, double *XX, hipStream_t st) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_xx<KK>, grid, dim3(256), 0, st, X, ldX, n, XX));
+    return hipGetLastError();
+}
+
+hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st) {
+    const int64_t units = (int64_t)g.npairs * schur_chunks(K);
+    const dim3 grid((unsigned)((units + 3) / 4 * g.P));
+    DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_schur_gn<KK>, grid, dim3(256), 0, st, g));
+    if (g.P > 1) {
+        const int64_t ru = (int64_t)g.npairs * (K * (K + 1) / 2);
+        const dim3 rg((unsigned)((ru + 3) / 4));
+        DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_schur_reduce<KK>, rg, dim3(256), 0, st, g));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_identity(double *S, int64_t ldS, int64_t N, int64_t Np, hipStream_t st) {
+    if (Np <= N) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_identity, dim3((unsigned)Np), dim3(256), 0, st, S, ldS, N, Np);
+    return hipGetLastError();
+}
+
+hipError_t launch_cholesky(const CholArgs &g, hipStream_t st) {
+    const int NT = g.NT;
+    for (int kt = -1; kt <= NT - 2; ++kt) {
+        const int c = kt + 1;
+        const int R = NT - c - 1;
+        const int64_t blocks = (int64_t)(NT - c) + (kt >= 0 ? (int64_t)R * (R + 1) / 2 : 0);
+        hipLaunchKernelGGL(k_chol_step, dim3((unsigned)blocks), dim3(256), 0, st, g, kt);
+    }
+    if (NT == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chol_inverses, dim3((unsigned)NT), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const SolveArgs &fwd, const SolveArgs &bwd, hipStream_t st) {
+    hipLaunchKernelGGL(k_trsv_fwd_lb, dim3((unsigned)fwd.NT), dim3(256), 0, st, fwd);
+    hipLaunchKernelGGL(k_trsv_bwd_lb, dim3((unsigned)bwd.NT), dim3(256), 0, st, bwd);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(unsigned *p, int64_t count, unsigned v) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < count) p[e] = v;
+}
+
+hipError_t launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+}  // namespace nmfk

@@ -24,7 +24,7 @@ struct IpmScal {
     double out[4 * PARTW];     // outputs of the last k_finish calls
     double f;                  // 1/2 ||XY - M||^2 at the current point
     int chol_fail;
-    int pad;
+    int solve_fail;            // 2: a triangular-solve block timed out waiting for its predecessor
 };
 
 struct IpmState {
@@ -40,9 +40,15 @@ struct IpmState {
     double *Lq = nullptr;                      // [K(K+1)/2 + K][ldX]: Cholesky of Q1bar_i and 1/diag
     double *Qi = nullptr;                      // [K(K+1)/2][ldX]: Q1bar_i^-1 (exact Hessian)
     double *Z = nullptr;                       // [n][K][ldY]: L_i^-1 Y
-    double *S = nullptr;                       // [mK][ldS] column-major, lower triangle used
+    double *S = nullptr;                       // [ldS][ldS] column-major, lower triangle used
     double *vec = nullptr, *vec2 = nullptr;    // [ldS] right-hand side / solution
-    double *invd = nullptr;                    // [ldS] 1 / diagonal of the Cholesky factor of S
+    double *XX = nullptr;                      // [n][K(K+1)/2] products X_ia X_ib
+    double *Dinv = nullptr;                    // [ldS/64][64*64] inverses of the diagonal factor tiles
+    double *spart = nullptr;                   // Schur row-split partial sums (P > 1)
+    unsigned *flags = nullptr;                 // [3][ldS/64] hand-over flags: factor, forward, backward solve
+    unsigned epoch = 0;                        // last flag value used
+    bool flags_ready = false;
+    int P = 1;                                 // row splits of the Schur formation
     double *part = nullptr;                    // [nblk][PARTW] block records
     double *fpart = nullptr;                   // [Tn * Sx] objective partials
     IpmScal *sc = nullptr;

@@ -21,22 +21,24 @@
 // coefficients come from one pass over M; the barrier terms of phi for a batch
 // of trial steps a = a1max / 2^t come from one pass over (x, y).
 //
-// Dense linear algebra.  S (mk x mk) is factored by a blocked right-looking
-// Cholesky (diagonal block in LDS, panel solve, trailing update in 64 x 64
-// tiles), and the two triangular solves are blocked the same way.
+// Dense linear algebra (dense.hip).  The unknowns dy are ordered component-
+// major (index a*m + j); the Gauss-Newton S is formed on FP64 matrix cores,
+// factored by 64-wide block columns (one launch per block column) and solved
+// by two single-launch blocked triangular solves.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
 
 #include <vector>
 
+#include "dense.h"
 #include "device_util.h"
 #include "ipm.h"
 
 namespace nmfk {
 
 constexpr int PRS = KMAX * KMAX;   // stride of block records in `part`
-constexpr int CB = 64;             // dense Cholesky / triangular-solve block
+constexpr int CB = 64;             // dense Cholesky / triangular-solve tile
 constexpr int TJ = 16;             // Schur tile: 16 x 16 (j, l) pairs
 constexpr int ZRB = 8;             // rows per block of the Z kernel
 
@@ -462,7 +464,8 @@ __global__ __launch_bounds__(NTHR) void k_factor(AnlsParams p, IpmArgs ia, doubl
     }
 }
 
-// Z_i = L_i^-1 Y for ZRB rows per block: Z[(i*K + c)*ldY + j].
+// Z_i = L_i^-1 Y for ZRB rows per block: Z[(i*KP + c)*ldY + j], KP = K
+// rounded up to a multiple of 4, zero for c >= K and for j >= m.
 template <int K>
 __global__ __launch_bounds__(NTHR) void k_zmat(AnlsParams p, IpmArgs ia) {
     constexpr int NL = K * (K + 1) / 2;
@@ -475,10 +478,12 @@ __global__ __launch_bounds__(NTHR) void k_zmat(AnlsParams p, IpmArgs ia) {
     }
     __syncthreads();
     const int nr = (int)min((int64_t)ZRB, p.n - i0);
-    for (int64_t j = threadIdx.x; j < p.m; j += NTHR) {
+    constexpr int KP = zpad(K);
+    // every column up to ldY and components up to KP: the padding is 0
+    for (int64_t j = threadIdx.x; j < p.ldY; j += NTHR) {
         double y[K];
 #pragma unroll
-        for (int a = 0; a < K; ++a) y[a] = p.Y[(int64_t)a * p.ldY + j];
+        for (int a = 0; a < K; ++a) y[a] = j < p.m ? p.Y[(int64_t)a * p.ldY + j] : 0.0;
         for (int rr = 0; rr < nr; ++rr) {
             double z[K];
 #pragma unroll
@@ -489,7 +494,7 @@ __global__ __launch_bounds__(NTHR) void k_zmat(AnlsParams p, IpmArgs ia) {
                 z[r] = v * Ls[rr][NL + r];
             }
 #pragma unroll
-            for (int c = 0; c < K; ++c) ia.Z[((i0 + rr) * K + c) * p.ldY + j] = z[c];
+            for (int c = 0; c < KP; ++c) ia.Z[((i0 + rr) * KP + c) * p.ldY + j] = c < K ? z[c] : 0.0;
         }
     }
 }
@@ -530,7 +535,7 @@ __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double 
             const int rr = q / (K * 2 * TJ), c = (q / (2 * TJ)) % K, col = q % (2 * TJ);
             const int64_t i = i0 + rr;
             const int64_t jc = col < TJ ? jt * TJ + col : lt * TJ + col - TJ;
-            Zs[rr][c][col] = (i < p.n && jc < p.m) ? ia.Z[(i * K + c) * p.ldY + jc] : 0.0;
+            Zs[rr][c][col] = (i < p.n && jc < p.m) ? ia.Z[(i * zpad(K) + c) * p.ldY + jc] : 0.0;
         }
         for (int q = threadIdx.x; q < SR * K; q += 256) {
             const int rr = q / K, a = q % K;
@@ -619,8 +624,14 @@ __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double 
             }
         }
     }
-    if (j < p.m && l < p.m) {
+    // Component-major ordering (row a*m + j).  Pair (j, l) with j > l gives
+    // every entry of S that couples j and l: entry (a*m + j, b*m + l) goes to
+    // the lower triangle as is (a >= b) or transposed (a < b); a pair with
+    // j == l gives the lower (a >= b) entries of its own k x k block; pairs
+    // with j < l add nothing new.
+    if (j < p.m && l < p.m && j >= l) {
         const double *G = ia.sc->GX;
+        const int64_t m = p.m;
 #pragma unroll
         for (int a = 0; a < K; ++a) {
 #pragma unroll
@@ -631,7 +642,11 @@ __global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double 
                     v += G[a * K + b];
                     if (a == b) v += rho + ia.s[(int64_t)a * p.ldY + j] / p.Y[(int64_t)a * p.ldY + j];
                 }
-                ia.S[(l * K + b) * ia.ldS + (j * K + a)] = v;
+                const int64_t row = a * m + j, col = b * m + l;
+                if (row >= col)
+                    ia.S[col * ia.ldS + row] = v;
+                else if (j > l)
+                    ia.S[row * ia.ldS + col] = v;
             }
         }
     }
@@ -644,6 +659,8 @@ __global__ __launch_bounds__(NTHR) void k_rhs(AnlsParams p, IpmArgs ia, double m
     for (int q = threadIdx.x; q < K * K; q += NTHR) T[q] = ia.sc->XtV[q];
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    const int64_t N = p.m * K, Np = (N + CB - 1) / CB * CB;
+    if (j < Np - N) ia.vec[N + j] = 0.0;   // the identity padding of S solves to 0
     if (j >= p.m) return;
     double y[K];
 #pragma unroll
@@ -654,7 +671,7 @@ __global__ __launch_bounds__(NTHR) void k_rhs(AnlsParams p, IpmArgs ia, double m
 #pragma unroll
         for (int b = 0; b < K; ++b) v -= T[a * K + b] * y[b];
         if (EXACT) v -= ia.tY[(int64_t)a * p.ldY + j];
-        ia.vec[j * K + a] = v;
+        ia.vec[a * p.m + j] = v;
     }
 }
 
@@ -669,7 +686,7 @@ __global__ __launch_bounds__(NTHR) void k_post_y(AnlsParams p, IpmArgs ia, doubl
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             const int64_t o = (int64_t)a * p.ldY + j;
-            const double d = ia.vec2[j * K + a];
+            const double d = ia.vec2[a * p.m + j];
             const double y = p.Y[o], s = ia.s[o];
             ia.dy[o] = d;
             const double dsv = mu / y - s - (s / y) * d;
@@ -763,259 +780,6 @@ __global__ __launch_bounds__(NTHR) void k_post_x(AnlsParams p, IpmArgs ia, doubl
         for (int w = 1; w < NTHR / 64; ++w) m = mins[threadIdx.x][w] < m ? mins[threadIdx.x][w] : m;
         rec[1 + threadIdx.x] = m;
     }
-}
-
-// ---------------------------------------------------------------- dense Cholesky of S
-// S is column-major, element (r, c) at S[c * ldS + r]; the Schur kernel fills
-// the lower triangle.  Right-looking blocked factorisation with CB-wide block
-// columns: factor the diagonal block and solve the panel below it (one
-// kernel), update the trailing lower triangle (a second).  The factor ends up
-// below the diagonal blocks (panels) and, transposed, in the whole upper
-// triangle (diagonal blocks included); invd[r] = 1 / L[r][r].
-
-// Value of v in lane `lane` (a compile-time constant after unrolling).
-__device__ __forceinline__ double lane_value(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// Block column [k0, k0 + CB) of the factorisation in one kernel.  Every block
-// first factors the diagonal block [k0, k0 + nb) in registers: thread (tx, ty)
-// keeps the 4 x 4 entries (tx + 16u, ty + 16v); step c takes the square root
-// of the pivot in its owner, scales column c, shares it in LDS and applies the
-// rank-one update (a pivot that is not positive sets sc->chol_fail and is
-// replaced by 1).  Block 0 stores L_kk transposed into the upper triangle
-// (S[(k0 + i) * ldS + k0 + j] = L[k0 + i][k0 + j], j < i) and 1 / diag; the
-// lower triangle of the diagonal block keeps its input, which the other
-// blocks read.  Then each block solves 64 rows of the panel below,
-// L[r, k0:k0+CB) = S[r, k0:k0+CB) L_kk^-T, four lanes per row each owning 16
-// entries: step q, the owner of entry q scales it by 1 / L_qq, the quad shares
-// it and every lane updates its own later entries.  The panel rows are also
-// stored transposed, S[r * ldS + k0 + q] = L[r][k0 + q], so that the backward
-// triangular solve reads them coalesced.
-constexpr int PROWS = 64;   // panel rows per block (4 lanes each)
-__global__ __launch_bounds__(256) void k_chol_col(double *S, int64_t ldS, int64_t N, int64_t k0, double *invd,
-                                                IpmScal *sc) {
-    __shared__ double colv[CB];
-    __shared__ double piv;
-    __shared__ int bad;
-    __shared__ double Lk[CB * CB];          // Lk[q * CB + j] = L[k0 + j][k0 + q], j > q
-    __shared__ double id[CB];
-    __shared__ double T[CB * (PROWS + 1)];  // T[q * (PROWS + 1) + rr] = L[base + rr][k0 + q]
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int nb = (int)min((int64_t)CB, N - k0);
-    double a[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = tx + 16 * u, j = ty + 16 * v;
-            a[u][v] = (i >= j && i < nb) ? S[(k0 + j) * ldS + k0 + i] : (i == j ? 1.0 : 0.0);
-        }
-    if (threadIdx.x == 0) bad = 0;
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-        const int cu = c >> 4, cr = c & 15;
-        if (tx == cr && ty == cr) {
-            const double d = a[cu][cu];
-            const bool ok = d > 0.0;
-            if (!ok) bad = 1;
-            const double l = sqrt(ok ? d : 1.0);
-            a[cu][cu] = l;
-            piv = 1.0 / l;
-        }
-        __syncthreads();
-        if (ty == cr) {
-            const double il = piv;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = tx + 16 * u;
-                if (i > c) {
-                    a[u][cu] *= il;
-                    colv[i] = a[u][cu];
-                }
-            }
-        }
-        __syncthreads();
-        double li[4], lj[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            li[u] = (tx + 16 * u > c) ? colv[tx + 16 * u] : 0.0;
-            lj[u] = (ty + 16 * u > c) ? colv[ty + 16 * u] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) a[u][v] = fma(-li[u], lj[v], a[u][v]);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = tx + 16 * u, j = ty + 16 * v;
-            if (i > j) Lk[j * CB + i] = a[u][v];
-            if (i == j) id[i] = 1.0 / a[u][v];
-            // block 0 keeps L_kk only in the upper triangle (transposed): the
-            // lower triangle still holds the input other blocks may be reading
-            if (blockIdx.x == 0 && i < nb) {
-                if (i > j) S[(k0 + i) * ldS + k0 + j] = a[u][v];
-                if (i == j) invd[k0 + i] = 1.0 / a[u][v];
-            }
-        }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && bad) sc->chol_fail = 1;
-    if (N - k0 <= CB) return;   // no panel below the last block (uniform)
-    __syncthreads();
-    const int rr = threadIdx.x >> 2, part = threadIdx.x & 3;
-    const int lane = threadIdx.x & 63;
-    const int64_t base = k0 + CB + (int64_t)blockIdx.x * PROWS;
-    const int64_t r = base + rr;
-    const bool live = r < N;
-    double x[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) x[u] = live ? S[(k0 + 16 * part + u) * ldS + r] : 0.0;
-#pragma unroll
-    for (int q = 0; q < CB; ++q) {
-        const int owner = q >> 4, u = q & 15;
-        if (part == owner) x[u] *= id[q];
-        const double xq = __shfl(x[u], (lane & ~3) | owner, 64);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int j = 16 * part + v;
-            if (j > q) x[v] = fma(-xq, Lk[q * CB + j], x[v]);
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        if (live) S[(k0 + 16 * part + u) * ldS + r] = x[u];
-        T[(16 * part + u) * (PROWS + 1) + rr] = x[u];
-    }
-    __syncthreads();
-    const int w = threadIdx.x >> 6;
-    for (int r2 = w; r2 < PROWS; r2 += 4) {
-        const int64_t rg = base + r2;
-        if (rg < N) S[rg * ldS + k0 + lane] = T[lane * (PROWS + 1) + r2];
-    }
-}
-
-// Trailing update of the lower triangle: S[r][c] -= sum_q L[r][k0+q] L[c][k0+q]
-// over 64 x 64 tiles (R >= C) of [k0 + CB, N)^2.  Thread (tx, ty) owns rows
-// tx + 16a and columns ty + 16b of its tile (4 x 4 accumulators).
-__global__ __launch_bounds__(256) void k_chol_syrk(double *S, int64_t ldS, int64_t N, int64_t k0) {
-    __shared__ double PR[CB * CB];   // PR[q * CB + rr] = L[rb + rr][k0 + q]
-    __shared__ double PC[CB * CB];
-    const int64_t T0 = k0 + CB;
-    const int64_t tix = blockIdx.x;
-    int64_t R = (int64_t)((sqrt(8.0 * (double)tix + 1.0) - 1.0) * 0.5);
-    while ((R + 1) * (R + 2) / 2 <= tix) ++R;
-    while (R * (R + 1) / 2 > tix) --R;
-    const int64_t C = tix - R * (R + 1) / 2;
-    const int64_t rb = T0 + R * CB, cb = T0 + C * CB;
-    for (int t = threadIdx.x; t < CB * CB; t += 256) {
-        const int rr = t % CB, q = t / CB;
-        PR[t] = (rb + rr < N) ? S[(k0 + q) * ldS + rb + rr] : 0.0;
-        PC[t] = (cb + rr < N) ? S[(k0 + q) * ldS + cb + rr] : 0.0;
-    }
-    __syncthreads();
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-#pragma unroll 4
-    for (int q = 0; q < CB; ++q) {
-        double pr[4], pc[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            pr[a] = PR[q * CB + tx + 16 * a];
-            pc[a] = PC[q * CB + ty + 16 * a];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(pr[a], pc[b], acc[a][b]);
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int64_t colg = cb + ty + 16 * b;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int64_t row = rb + tx + 16 * a;
-            if (row < N && colg < N && row >= colg) S[colg * ldS + row] -= acc[a][b];
-        }
-    }
-}
-
-// Forward solve step: wave 0 of every block solves x_k = L_kk^-1 vec_k (lane
-// i keeps row i of L_kk, read from the transposed copy in the upper triangle;
-// step q takes x_q from lane q) into LDS; block 0
-// stores x_k in out; every block then subtracts L[r, k0:k0+nb) x_k from its
-// 256 rows r below the block.
-__global__ __launch_bounds__(256) void k_trsv_fwd(const double *S, int64_t ldS, int64_t N, int64_t k0,
-                                                  const double *invd, double *vec, double *out) {
-    __shared__ double xs[CB];
-    const int nb = (int)min((int64_t)CB, N - k0);
-    if (threadIdx.x < 64) {
-        const int i = threadIdx.x;
-        double l[CB];
-#pragma unroll
-        for (int j = 0; j < CB; ++j) l[j] = (j < i && i < nb) ? S[(k0 + i) * ldS + k0 + j] : 0.0;
-        double b = i < nb ? vec[k0 + i] : 0.0;
-        const double di = i < nb ? invd[k0 + i] : 0.0;
-        double mine = 0.0;
-#pragma unroll
-        for (int q = 0; q < CB; ++q) {
-            const double xq = lane_value(b, q) * lane_value(di, q);
-            if (i == q) mine = xq;
-            b = fma(-l[q], xq, b);
-        }
-        xs[i] = mine;
-        if (blockIdx.x == 0 && i < nb) out[k0 + i] = mine;
-    }
-    __syncthreads();
-    const int64_t row = k0 + nb + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (row >= N) return;
-    double v = vec[row];
-#pragma unroll 8
-    for (int q = 0; q < nb; ++q) v = fma(-S[(k0 + q) * ldS + row], xs[q], v);
-    vec[row] = v;
-}
-
-// Backward solve step with L^T, reading the transposed copy of L kept in the
-// upper triangle (S[(k0 + q) * ldS + c] = L[k0 + q][c], c < k0 + q): wave 0
-// of every block solves L_kk^T x_k = vec_k (lane j keeps column j of L_kk;
-// steps run from the last row up) into LDS; block 0 stores x_k in out; every
-// block then subtracts sum_q L[k0+q][c] x_q from its 256 rows c < k0.
-__global__ __launch_bounds__(256) void k_trsv_bwd(const double *S, int64_t ldS, int64_t N, int64_t k0,
-                                                  const double *invd, double *vec, double *out) {
-    __shared__ double xs[CB];
-    const int nb = (int)min((int64_t)CB, N - k0);
-    if (threadIdx.x < 64) {
-        const int j = threadIdx.x;
-        double cl[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) cl[q] = (q > j && q < nb) ? S[(k0 + q) * ldS + k0 + j] : 0.0;
-        double y = j < nb ? vec[k0 + j] : 0.0;
-        const double dj = j < nb ? invd[k0 + j] : 0.0;
-        double mine = 0.0;
-#pragma unroll
-        for (int q = CB - 1; q >= 0; --q) {
-            const double xq = lane_value(y, q) * lane_value(dj, q);
-            if (j == q) mine = xq;
-            y = fma(-cl[q], xq, y);
-        }
-        xs[j] = mine;
-        if (blockIdx.x == 0 && j < nb) out[k0 + j] = mine;
-    }
-    __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= k0) return;
-    double v = vec[c];
-#pragma unroll 8
-    for (int q = 0; q < nb; ++q) v = fma(-S[(k0 + q) * ldS + c], xs[q], v);
-    vec[c] = v;
 }
 
 // ---------------------------------------------------------------- line search
@@ -1216,9 +980,22 @@ __global__ __launch_bounds__(NTHR) void k_duals_out(AnlsParams p, IpmArgs ia, do
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct IpmLayout {
-    size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Qi, Z, S, vec, vec2, invd, part, fpart, sc, total;
+    size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Qi, Z, S, vec, vec2, XX, Dinv, spart, flags, part, fpart, sc,
+        total;
     int64_t ldX, ldY, ldS;
+    int P;
 };
+
+// Row splits of the Schur formation.  Blocks are dealt to the 8 XCDs in
+// turn and split p of block b is b mod P, so with P = 8 each XCD streams the
+// Z rows of one split only (its L2 holds them for every tile pair).  Large
+// problems (enough tile pairs to fill the chip many times) use one split.
+static int schur_splits(int64_t n, int64_t m, int K) {
+    const int64_t T = (m + 15) / 16;
+    const int64_t units = T * (T + 1) / 2 * schur_chunks(K);
+    if (units >= 8192 || n < 8 * 32) return 1;
+    return 8;
+}
 
 static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     IpmLayout L;
@@ -1237,11 +1014,17 @@ static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     L.s = take(vy); L.dy = take(vy); L.ds = take(vy); L.gy = take(vy); L.tY = take(vy);
     L.Lq = take((size_t)(NL + K) * L.ldX * 8);
     L.Qi = take((size_t)NL * L.ldX * 8);
-    L.Z = take((size_t)n * K * L.ldY * 8);
-    L.S = take((size_t)N * L.ldS * 8);
+    L.Z = take((size_t)n * zpad(K) * L.ldY * 8);
+    L.S = take((size_t)L.ldS * L.ldS * 8);
     L.vec = take((size_t)L.ldS * 8);
     L.vec2 = take((size_t)L.ldS * 8);
-    L.invd = take((size_t)L.ldS * 8);
+    L.XX = take((size_t)n * NL * 8);
+    const int64_t NT = L.ldS / CB;
+    L.Dinv = take((size_t)NT * CB * CB * 8);
+    L.P = schur_splits(n, m_cap, K);
+    const int64_t T16 = (m_cap + 15) / 16;
+    L.spart = take(L.P > 1 ? (size_t)L.P * (T16 * (T16 + 1) / 2) * NL * 256 * 8 : 256);
+    L.flags = take((size_t)3 * NT * sizeof(unsigned));
     L.part = take((size_t)nblk * PRS * 8);
     L.fpart = take((size_t)Tn * 64 * 8 * sizeof(double));   // Tn * Sx records of 8 (Sx <= 64)
     L.sc = take(sizeof(IpmScal));
@@ -1261,7 +1044,13 @@ nmf_status ipm_bind(IpmState &s, uint8_t *base, int64_t n, int64_t m_cap, int K)
     s.V = (double *)(base + L.V); s.tX = (double *)(base + L.tX); s.tY = (double *)(base + L.tY);
     s.Lq = (double *)(base + L.Lq); s.Qi = (double *)(base + L.Qi); s.Z = (double *)(base + L.Z);
     s.S = (double *)(base + L.S); s.vec = (double *)(base + L.vec); s.vec2 = (double *)(base + L.vec2);
-    s.invd = (double *)(base + L.invd);
+    s.XX = (double *)(base + L.XX);
+    s.Dinv = (double *)(base + L.Dinv);
+    s.spart = (double *)(base + L.spart);
+    s.flags = (unsigned *)(base + L.flags);
+    s.P = L.P;
+    s.flags_ready = false;
+    s.epoch = 0;
     s.part = (double *)(base + L.part); s.fpart = (double *)(base + L.fpart);
     s.sc = (IpmScal *)(base + L.sc);
     s.bound = true;
@@ -1330,9 +1119,15 @@ nmf_status kkt(Ctx &c, double mu) {
     double h[4];
     nmf_status st = read_out(c, h, 4);
     if (st != NMF_OK) return st;
-    double f = 0.0;
-    HCK(hipMemcpyAsync(&f, &c.s.sc->f, sizeof(double), hipMemcpyDeviceToHost, c.st));
+    struct { double f; int chol_fail, solve_fail; } tail;
+    static_assert(sizeof(tail) == sizeof(double) + 2 * sizeof(int), "IpmScal tail layout");
+    HCK(hipMemcpyAsync(&tail, &c.s.sc->f, sizeof(tail), hipMemcpyDeviceToHost, c.st));
     HCK(hipStreamSynchronize(c.st));
+    if (tail.solve_fail) {
+        c.s.err = "a block of a triangular solve waited too long for the tile before it";
+        return NMF_EDEVICE;
+    }
+    const double f = tail.f;
     c.s.S1 = h[0];
     c.s.SR = h[3];
     c.s.C0 = h[1];
@@ -1343,41 +1138,59 @@ nmf_status kkt(Ctx &c, double mu) {
     return NMF_OK;
 }
 
-nmf_status cholesky(Ctx &c, int64_t N) {
-    double *S = c.s.S;
-    const int64_t ldS = c.s.ldS;
-    for (int64_t k0 = 0; k0 < N; k0 += CB) {
-        const int64_t below = N - k0 - CB;
-        const unsigned nb = below > 0 ? (unsigned)((below + PROWS - 1) / PROWS) : 1u;
-        hipLaunchKernelGGL(k_chol_col, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, c.s.invd, c.s.sc);
-        if (below > 0) {
-            const int64_t nt = (below + CB - 1) / CB;
-            hipLaunchKernelGGL(k_chol_syrk, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, c.st, S, ldS, N, k0);
-        }
-    }
-    HCK(hipGetLastError());
+// Flag arrays of the two triangular solves (2 x NT; a third NT is spare): zeroed once,
+// then every launch that hands over through them uses a fresh epoch.
+nmf_status ensure_flags(Ctx &c) {
+    if (c.s.flags_ready) return NMF_OK;
+    HCK(launch_fill_u32(c.s.flags, 3 * (c.s.ldS / CB), 0u, c.st));
+    static const int zero = 0;
+    HCK(hipMemcpyAsync(&c.s.sc->solve_fail, &zero, sizeof(int), hipMemcpyHostToDevice, c.st));
+    c.s.flags_ready = true;
+    c.s.epoch = 0;
     return NMF_OK;
 }
 
-// vec2 = S^-1 vec (S = L L^T, factored in place); vec is overwritten.
+unsigned next_epoch(Ctx &c) {
+    if (++c.s.epoch == 0) ++c.s.epoch;   // 0 is the cleared state
+    return c.s.epoch;
+}
+
+// S = L L^T in place (lower triangle), with the inverse of every diagonal
+// tile of L; Np = N rounded up to whole tiles, the padding is the identity.
+nmf_status cholesky(Ctx &c, int64_t N) {
+    const int64_t Np = (N + CB - 1) / CB * CB;
+    HCK(launch_pad_identity(c.s.S, c.s.ldS, N, Np, c.st));
+    CholArgs g;
+    g.S = c.s.S;
+    g.ldS = c.s.ldS;
+    g.NT = (int)(Np / CB);
+    g.Dinv = c.s.Dinv;
+    g.fail = &c.s.sc->chol_fail;
+    HCK(launch_cholesky(g, c.st));
+    return NMF_OK;
+}
+
+// vec2 = S^-1 vec with the factor of cholesky(); vec is left as is.
 nmf_status solve_S(Ctx &c, int64_t N) {
-    const double *S = c.s.S;
-    const int64_t ldS = c.s.ldS;
-    for (int64_t k0 = 0; k0 < N; k0 += CB) {
-        const int64_t below = N - k0 - CB;
-        const unsigned nb = below > 0 ? (unsigned)((below + 255) / 256) : 1u;
-        hipLaunchKernelGGL(k_trsv_fwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, (const double *)c.s.invd,
-                           c.s.vec, c.s.vec2);
-    }
-    // backward on vec2 (y) -> vec (x)
-    const int64_t last = (N - 1) / CB * CB;
-    for (int64_t k0 = last; k0 >= 0; k0 -= CB) {
-        const unsigned nb = k0 > 0 ? (unsigned)((k0 + 255) / 256) : 1u;
-        hipLaunchKernelGGL(k_trsv_bwd, dim3(nb), dim3(256), 0, c.st, S, ldS, N, k0, (const double *)c.s.invd,
-                           c.s.vec2, c.s.vec);
-    }
-    HCK(hipMemcpyAsync(c.s.vec2, c.s.vec, sizeof(double) * N, hipMemcpyDeviceToDevice, c.st));
-    HCK(hipGetLastError());
+    HCK(ensure_flags(c) == NMF_OK ? hipSuccess : hipErrorUnknown);
+    const int64_t Np = (N + CB - 1) / CB * CB;
+    const int NT = (int)(Np / CB);
+    const int64_t NTcap = c.s.ldS / CB;
+    SolveArgs f;
+    f.S = c.s.S;
+    f.ldS = c.s.ldS;
+    f.NT = NT;
+    f.Dinv = c.s.Dinv;
+    f.b = c.s.vec;
+    f.y = c.s.vec2;
+    f.flags = c.s.flags + NTcap;
+    f.epoch = next_epoch(c);
+    f.fail = &c.s.sc->solve_fail;
+    SolveArgs bk = f;
+    bk.b = nullptr;
+    bk.flags = c.s.flags + 2 * NTcap;
+    bk.epoch = next_epoch(c);
+    HCK(launch_solve(f, bk, c.st));
     return NMF_OK;
 }
 
@@ -1409,11 +1222,28 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
         IPM_KS(K, hipLaunchKernelGGL(k_zmat<KK>, dim3((unsigned)((p.n + ZRB - 1) / ZRB)), dim3(NTHR), 0, c.st,
                                            p, c.ia));
         const int64_t nt = (p.m + TJ - 1) / TJ;
-        const dim3 gs((unsigned)(nt * (nt + 1) / 2));
         if (exact) {
+            const dim3 gs((unsigned)(nt * (nt + 1) / 2));
             IPM_KS(K, hipLaunchKernelGGL((k_schur<KK, true>), gs, dim3(256), 0, c.st, p, c.ia, rho));
         } else {
-            IPM_KS(K, hipLaunchKernelGGL((k_schur<KK, false>), gs, dim3(256), 0, c.st, p, c.ia, rho));
+            HCK(launch_xx(K, p.X, p.ldX, p.n, c.s.XX, c.st));
+            SchurArgs g;
+            g.Z = c.s.Z;
+            g.XX = c.s.XX;
+            g.n = p.n;
+            g.m = p.m;
+            g.ldY = p.ldY;
+            g.npairs = (int)(nt * (nt + 1) / 2);
+            g.P = c.s.P;
+            g.rows_per_split = (p.n + g.P - 1) / g.P;
+            g.part = c.s.spart;
+            g.S = c.s.S;
+            g.ldS = c.s.ldS;
+            g.GX = c.s.sc->GX;
+            g.s = c.s.s;
+            g.Y = p.Y;
+            g.rho = rho;
+            HCK(launch_schur_gn(K, g, c.st));
         }
         nmf_status st = cholesky(c, N);
         if (st != NMF_OK) return st;
