@@ -1409,6 +1409,10 @@ nmf_status mu_update(Ctx &c) {
 nmf_status ipm_transition(IpmState &s, const AnlsParams &p, const nmf_options &o, hipStream_t st) {
     if (!s.bound) { s.err = "no stage-2 workspace"; return NMF_ESTATE; }
     Ctx c{s, p, o, st, args_of(s), s.K};
+    // the hand-over flags and the solve-failure word start cleared (the
+    // workspace arrives uninitialised)
+    s.flags_ready = false;
+    if (ensure_flags(c) != NMF_OK) return NMF_EDEVICE;
     // rho0 = 1e-6 max(x, y) on the stage-1 point, eq. (22)
     IPM_KS(c.K, hipLaunchKernelGGL(k_maxes<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, st, p, c.ia, 0));
     HCK(finish(c, s.part, PRS, p.Bx + p.By, 2, 0x3u, s.sc->out));

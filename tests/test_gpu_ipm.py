@@ -8,12 +8,18 @@ compared entry by entry; a few IPM iterations are compared as trajectories
 compared after removing the scaling freedom, and certified independently by
 the KKT conditions eq. (3).
 """
+import os
+
 import numpy as np
 import pytest
 
 from paper_2101_08431_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+# Agreement of normalised end points with the oracle's (the north-star bar on
+# factor entries); measured: about 1e-11 at 3000x500x5, 1e-15 at 200x50x3.
+GOLDEN_FACTOR_BAR = 1e-8
 
 
 def start_point(orc, name, seed, sweeps=None, eps_stol=1e-6):
@@ -66,8 +72,10 @@ def test_first_iterations_match_oracle(orc, name, seed, iters):
     X1, Y1, r1, s1, mu1, rho1 = orc.transition(M, X, Yt, 1e-10)
     res = orc.ipm(M, X1, Y1, r1, s1, mu1, rho1, opts)
     assert res.inner == iters
-    assert rel(Xg, res.X) <= 1e-7 and rel(Yg.T, res.Yt) <= 1e-7
-    assert rel(Rg, res.r) <= 1e-6 and rel(Sg.T, res.s) <= 1e-6
+    print(f"trajectory agreement: X {rel(Xg, res.X):.2e} Y {rel(Yg.T, res.Yt):.2e} "
+          f"R {rel(Rg, res.r):.2e} S {rel(Sg.T, res.s):.2e}", flush=True)
+    assert rel(Xg, res.X) <= 1e-8 and rel(Yg.T, res.Yt) <= 1e-8
+    assert rel(Rg, res.r) <= 1e-8 and rel(Sg.T, res.s) <= 1e-8
 
 
 @pytest.mark.parametrize("seed", [0, 1, 4])
@@ -86,7 +94,9 @@ def test_full_solve_200x50x3_matches_oracle(orc, seed):
     assert abs(fg - fo) <= 1e-10 * fo + 1e-16 * 0.5 * np.sum(M * M)
     Xn, Yn = orc.normalise(Xg, Yg.T)
     Xon, Yon = orc.normalise(res.X, res.Yt)
-    assert rel(Xn, Xon) <= 1e-6 and rel(Yn, Yon) <= 1e-6
+    print(f"end-point agreement: f {abs(fg - fo) / fo:.2e}, normalised X {rel(Xn, Xon):.2e}, "
+          f"Y {rel(Yn, Yon):.2e}", flush=True)
+    assert rel(Xn, Xon) <= 1e-8 and rel(Yn, Yon) <= 1e-8
     # independent certificate: E(.;0) from the GPU's own iterate and duals
     Rg, Sg = ctx.duals()
     gx, gy, _ = orc.gradients(M, Xg, Yg.T)
@@ -136,29 +146,61 @@ def test_first_iteration_3000x500x5_matches_oracle(orc):
     Rg, Sg = ctx.duals()
     X1, Y1, r1, s1, mu1, rho1 = orc.transition(M, X, Yt, 1e-8)
     res = orc.ipm(M, X1, Y1, r1, s1, mu1, rho1, orc.IPMOptions(eps_tol=1e-8, max_inner=1))
-    assert rel(Xg, res.X) <= 1e-7 and rel(Yg.T, res.Yt) <= 1e-7
-    assert rel(Rg, res.r) <= 1e-6 and rel(Sg.T, res.s) <= 1e-6
+    print(f"trajectory agreement: X {rel(Xg, res.X):.2e} Y {rel(Yg.T, res.Yt):.2e} "
+          f"R {rel(Rg, res.r):.2e} S {rel(Sg.T, res.s):.2e}", flush=True)
+    assert rel(Xg, res.X) <= 1e-8 and rel(Yg.T, res.Yt) <= 1e-8
+    assert rel(Rg, res.r) <= 1e-8 and rel(Sg.T, res.s) <= 1e-8
 
 
-def test_solve_3000x500x5_certificate(orc):
-    # Alg. 3 at full size: whatever the outcome within the cap, the reported
-    # E(.;0) is the one eq. (10) gives for the returned iterate and duals, the
-    # iterate is strictly interior, and a converged solve meets the tolerance.
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "solve_pdf_3000x500_k5_seed0.npz")
+
+
+def test_solve_3000x500x5_matches_oracle_golden(orc):
+    # Alg. 3 at full size from the oracle's stage-1 end point (stored by
+    # tests/golden/make_solve_golden.py, which calls only the oracle): the GPU
+    # must converge to E(.;0) <= 1e-10 within a cap well above the oracle's
+    # 458 iterations, certify it independently (eq. (10) from its own iterate
+    # and duals), and land on the oracle's end point
+    g = np.load(GOLDEN)
+    M, _, _ = synth.make("pdf_3000x500_k5", 0)
+    M = np.asarray(M)
+    print("case golden solve pdf_3000x500_k5 seed 0 to 1e-10", flush=True)
+    ctx = gpu_ctx(M, g["X1"], g["Yt1"], eps_tol=1e-10, max_ipm_iters=3000)
+    st, rep = ctx.ipm_step(3000)
+    print({k: rep[k] for k in ("E0", "f", "ipm_iters", "ipm_outer", "exact_steps", "fallbacks")}, flush=True)
+    assert st == 1 and rep["E0"] <= 1e-10, rep
+    Xg, Yg = ctx.factors()
+    Rg, Sg = ctx.duals()
+    gx, gy, _ = orc.gradients(M, Xg, Yg.T)
+    assert orc.kkt_error(Xg, Yg.T, Rg, Sg.T, 0.0, gx, gy) <= 2e-10
+    assert np.all(Xg > 0) and np.all(Yg > 0)
+    fg = orc.objective(M, Xg, Yg.T.copy())
+    f_err = abs(fg - float(g["f"])) / float(g["f"])
+    Xn, Yn = orc.normalise(Xg, Yg.T)
+    Xon, Yon = orc.normalise(g["X"], g["Yt"])
+    x_err, y_err = rel(Xn, Xon), rel(Yn, Yon)
+    print(f"golden agreement: f {f_err:.2e}, normalised X {x_err:.2e}, Y {y_err:.2e}", flush=True)
+    assert f_err <= 1e-10
+    assert x_err <= GOLDEN_FACTOR_BAR and y_err <= GOLDEN_FACTOR_BAR
+
+
+def test_nmf_solve_3000x500x5_converges(orc):
+    # the whole two-stage solve from the seeded start must converge (cap far
+    # above the measured iteration counts) and certify E(.;0) <= 1e-8
     M, X0, Y0 = synth.make("pdf_3000x500_k5", 1)
     print("case nmf_solve pdf_3000x500_k5 seed 1 to 1e-8", flush=True)
     from paper_2101_08431_amd import NMF, default_options
-    ctx = NMF(np.asarray(M), 5, X0, Y0, options=default_options(eps_tol=1e-8, max_ipm_iters=300))
+    ctx = NMF(np.asarray(M), 5, X0, Y0, options=default_options(eps_tol=1e-8, max_ipm_iters=5000))
     st, rep = ctx.solve()
-    print(rep, flush=True)
-    assert st in (1, -4)
+    print({k: rep[k] for k in ("E0", "f", "sweeps", "ipm_iters", "exact_steps")}, flush=True)
+    assert st == 1 and rep["E0"] <= 1e-8
     Xg, Yg = ctx.factors()
     Rg, Sg = ctx.duals()
     gx, gy, _ = orc.gradients(np.asarray(M), Xg, Yg.T)
     E = orc.kkt_error(Xg, Yg.T, Rg, Sg.T, 0.0, gx, gy)
     assert E == pytest.approx(rep["E0"], rel=1e-5, abs=1e-12)
+    assert E <= 1.01e-8
     assert np.all(Xg > 0) and np.all(Yg > 0)
-    if st == 1:
-        assert E <= 1.01e-8
 
 
 def test_append_after_stage2_returns_to_stage1(orc):
