@@ -26,6 +26,23 @@ struct SchurArgs {
     double rho;
 };
 
+// Exact-Hessian Schur complement (eq. (27)): S = Q2bar - sum_i V_i^T V_i with
+// V_i[p][(a, j)] = X_ia Z_i[p][j] + (L_i^-1)[p][a] R_ij, R = XY - M; the sum
+// runs over the flattened (i, p) index on matrix cores.
+struct SchurExArgs {
+    const double *Z;        // [n][zpad(K)][ldY]
+    const double *X;        // [K][ldX]
+    const double *Linv;     // [n][K][K]: (L_i^-1)[p][a] at (i*K + p)*K + a
+    const double *R;        // [n][ldY]: R_ij = (XY - M)_ij, row-major
+    int64_t n, m, ldX, ldY;
+    int NT;                 // 64 x 64 tiles per side of the padded S
+    double *S;
+    int64_t ldS;
+    const double *GX;
+    const double *s, *Y;
+    double rho;
+};
+
 struct CholArgs {
     double *S;              // column-major NT*64 x NT*64 (lower triangle used), leading dimension ldS
     int64_t ldS;
@@ -49,6 +66,13 @@ struct SolveArgs {
 int schur_chunks(int K);
 hipError_t launch_xx(int K, const double *X, int64_t ldX, int64_t n, double *XX, hipStream_t st);
 hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st);
+hipError_t launch_schur_exact(int K, const SchurExArgs &g, hipStream_t st);
+// Linv[i][p][a] = (L_i^-1)[p][a] from the packed factors Lq ([K(K+1)/2 + K][ldX]:
+// lower triangle row by row, then the reciprocal diagonal).
+hipError_t launch_linv(int K, const double *Lq, int64_t ldX, int64_t n, double *Linv, hipStream_t st);
+// R[i*ldY + j] = (X Y - M)_ij for j < m, 0 for m <= j < ldY (M column-major, ldM).
+hipError_t launch_residual_rows(int K, const double *M, int64_t ldM, const double *X, int64_t ldX,
+                                const double *Y, int64_t ldY, int64_t n, int64_t m, double *R, hipStream_t st);
 hipError_t launch_pad_identity(double *S, int64_t ldS, int64_t N, int64_t Np, hipStream_t st);
 hipError_t launch_cholesky(const CholArgs &g, hipStream_t st);
 hipError_t launch_solve(const SolveArgs &fwd, const SolveArgs &bwd, hipStream_t st);

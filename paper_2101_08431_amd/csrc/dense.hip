@@ -246,6 +246,169 @@ __global__ __launch_bounds__(256) void k_schur_reduce(SchurArgs g) {
     schur_store<K>(g, jt, lt, a, b, val);
 }
 
+// Exact-Hessian Schur complement as one symmetric rank update on matrix
+// cores: tile (I, J) of S (64 x 64, I >= J) sums V[k][rows I] V[k][cols J]
+// over the flattened index k = i*K + p, 32 values of k at a time.  Each
+// chunk of V (both tiles' 64 entries) is generated into LDS from Z, X, L_i^-1
+// and the residual rows while the previous chunk feeds the matrix cores.
+template <int K>
+__global__ __launch_bounds__(256) void k_schur_exact(SchurExArgs g) {
+    constexpr int KC = 32;
+    constexpr int KP = zpad(K);
+    __shared__ double VA[2][KC * 64];
+    __shared__ double VB[2][KC * 64];
+    int64_t It, Jt;
+    tri_pair(blockIdx.x, It, Jt);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
+    const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+    const int64_t N = g.m * K;
+    // this thread generates column `col` of both tiles for k rows kk = wave + 4v
+    const int col = lane;
+    const int64_t rho0 = It * 64 + col, rho1 = Jt * 64 + col;
+    const bool ok0 = rho0 < N, ok1 = rho1 < N;
+    const int a0 = ok0 ? (int)(rho0 / g.m) : 0, a1 = ok1 ? (int)(rho1 / g.m) : 0;
+    const int64_t j0 = ok0 ? rho0 - a0 * g.m : 0, j1 = ok1 ? rho1 - a1 * g.m : 0;
+    const int64_t nk = g.n * K;
+    // raw operands of one chunk for this thread (k rows kk = wave + 4v), loaded
+    // a chunk ahead and combined into V when written to LDS
+    double px0[KC / 4], pz0[KC / 4], pl0[KC / 4], pr0[KC / 4];
+    double px1[KC / 4], pz1[KC / 4], pl1[KC / 4], pr1[KC / 4];
+    auto load = [&](int64_t k0) {
+        // k = k0 + wave + 4v: i and p advance by 4 in k per v
+        int64_t k = k0 + wave;
+        int64_t i = k / K;
+        int pq = (int)(k - i * K);
+#pragma unroll
+        for (int v = 0; v < KC / 4; ++v) {
+            const bool live = k < nk;
+            const int64_t ic = live ? i : 0;
+            const double *zr = g.Z + (ic * KP + pq) * g.ldY;
+            const double *rr = g.R + ic * g.ldY;
+            const double *li = g.Linv + (ic * K + pq) * K;
+            px0[v] = live ? g.X[(int64_t)a0 * g.ldX + ic] : 0.0;
+            pz0[v] = zr[j0];
+            pl0[v] = live ? li[a0] : 0.0;
+            pr0[v] = rr[j0];
+            px1[v] = live ? g.X[(int64_t)a1 * g.ldX + ic] : 0.0;
+            pz1[v] = zr[j1];
+            pl1[v] = live ? li[a1] : 0.0;
+            pr1[v] = rr[j1];
+            k += 4;
+            pq += 4;
+            while (pq >= K) {
+                pq -= K;
+                ++i;
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < KC / 4; ++v) {
+            const int kk = wave + 4 * v;
+            VA[buf][kk * 64 + col] = ok0 ? fma(px0[v], pz0[v], pl0[v] * pr0[v]) : 0.0;
+            VB[buf][kk * 64 + col] = ok1 ? fma(px1[v], pz1[v], pl1[v] * pr1[v]) : 0.0;
+        }
+    };
+    v4d acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = (v4d){0.0, 0.0, 0.0, 0.0};
+    load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = 0; k0 < nk; k0 += KC) {
+        const bool more = k0 + KC < nk;
+        if (more) load(k0 + KC);
+#pragma unroll
+        for (int s = 0; s < KC / 4; ++s) {
+            const int kk = 4 * s + gq;
+            const double a0v = VA[buf][kk * 64 + R0 + r], a1v = VA[buf][kk * 64 + R0 + 16 + r];
+            const double b0v = VB[buf][kk * 64 + C0 + r], b1v = VB[buf][kk * 64 + C0 + 16 + r];
+            acc[0][0] = mfma16(b0v, a0v, acc[0][0]);
+            acc[0][1] = mfma16(b1v, a0v, acc[0][1]);
+            acc[1][0] = mfma16(b0v, a1v, acc[1][0]);
+            acc[1][1] = mfma16(b1v, a1v, acc[1][1]);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // acc[x][y][v] = sum for S entry (row It*64 + R0 + 16x + r, col Jt*64 + C0 + 16y + gq + 4v)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = It * 64 + R0 + 16 * x + r, cl = Jt * 64 + C0 + 16 * y + gq + 4 * v;
+                if (row < N && cl < N) {
+                    const int a = (int)(row / g.m), b = (int)(cl / g.m);
+                    const int64_t j = row - a * g.m, l = cl - b * g.m;
+                    double val = -acc[x][y][v];
+                    if (j == l) {
+                        val += g.GX[a * K + b];
+                        if (a == b) val += g.rho + g.s[(int64_t)a * g.ldY + j] / g.Y[(int64_t)a * g.ldY + j];
+                    }
+                    g.S[cl * g.ldS + row] = val;
+                }
+            }
+}
+
+// Linv[i][p][a] = (L_i^-1)[p][a], one row i per thread.
+template <int K>
+__global__ __launch_bounds__(256) void k_linv(const double *Lq, int64_t ldX, int64_t n, double *Linv) {
+    constexpr int NL = K * (K + 1) / 2;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double L[NL], id[K];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] = Lq[(int64_t)q * ldX + i];
+#pragma unroll
+    for (int a = 0; a < K; ++a) id[a] = Lq[(int64_t)(NL + a) * ldX + i];
+    // column c of L^-1 by forward substitution from e_c
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        double x[K];
+#pragma unroll
+        for (int rr = 0; rr < K; ++rr) {
+            double v = (rr == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = 0; q < rr; ++q) v -= L[rr * (rr + 1) / 2 + q] * x[q];
+            x[rr] = v * id[rr];
+        }
+#pragma unroll
+        for (int pq = 0; pq < K; ++pq) Linv[(i * K + pq) * K + c] = x[pq];
+    }
+}
+
+// R[i*ldY + j] = (X Y - M)_ij by 32 x 32 tiles transposed through LDS (M is
+// column-major, R row-major).
+template <int K>
+__global__ __launch_bounds__(256) void k_residual_rows(const double *M, int64_t ldM, const double *X, int64_t ldX,
+                                                       const double *Y, int64_t ldY, int64_t n, int64_t m,
+                                                       double *R) {
+    __shared__ double tile[32][33];
+    const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int jj = ty; jj < 32; jj += 8) {
+        const int64_t i = i0 + tx, j = j0 + jj;
+        double v = 0.0;
+        if (i < n && j < m) {
+            v = -M[j * ldM + i];
+#pragma unroll
+            for (int a = 0; a < K; ++a) v = fma(X[(int64_t)a * ldX + i], Y[(int64_t)a * ldY + j], v);
+        }
+        tile[jj][tx] = v;
+    }
+    __syncthreads();
+    for (int ii = ty; ii < 32; ii += 8) {
+        const int64_t i = i0 + ii, j = j0 + tx;
+        if (i < n && j < ldY) R[i * ldY + j] = tile[tx][ii];
+    }
+}
+
 // XX[i][t] = X_ia X_ib for t = (a, b), a >= b.
 template <int K>
 __global__ __launch_bounds__(256) void k_xx(const double *X, int64_t ldX, int64_t n, double *XX) {
@@ -740,6 +903,26 @@ hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st) {
         const dim3 rg((unsigned)((ru + 3) / 4));
         DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_schur_reduce<KK>, rg, dim3(256), 0, st, g));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_schur_exact(int K, const SchurExArgs &g, hipStream_t st) {
+    const dim3 grid((unsigned)((int64_t)g.NT * (g.NT + 1) / 2));
+    DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_schur_exact<KK>, grid, dim3(256), 0, st, g));
+    return hipGetLastError();
+}
+
+hipError_t launch_linv(int K, const double *Lq, int64_t ldX, int64_t n, double *Linv, hipStream_t st) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_linv<KK>, grid, dim3(256), 0, st, Lq, ldX, n, Linv));
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_rows(int K, const double *M, int64_t ldM, const double *X, int64_t ldX,
+                                const double *Y, int64_t ldY, int64_t n, int64_t m, double *R, hipStream_t st) {
+    const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((ldY + 31) / 32));
+    DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_residual_rows<KK>, grid, dim3(256), 0, st, M, ldM, X, ldX, Y, ldY, n, m,
+                                         R));
     return hipGetLastError();
 }
 

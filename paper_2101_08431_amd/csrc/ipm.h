@@ -38,7 +38,8 @@ struct IpmState {
     double *V = nullptr;                       // Q1bar_i^-1 b1_i per row
     double *tX = nullptr, *tY = nullptr;       // residual products (exact Hessian)
     double *Lq = nullptr;                      // [K(K+1)/2 + K][ldX]: Cholesky of Q1bar_i and 1/diag
-    double *Qi = nullptr;                      // [K(K+1)/2][ldX]: Q1bar_i^-1 (exact Hessian)
+    double *Linv = nullptr;                    // [n][K][K]: L_i^-1 (exact Hessian)
+    double *Rrow = nullptr;                    // [n][ldY]: residual XY - M, row-major (exact Hessian)
     double *Z = nullptr;                       // [n][K][ldY]: L_i^-1 Y
     double *S = nullptr;                       // [ldS][ldS] column-major, lower triangle used
     double *vec = nullptr, *vec2 = nullptr;    // [ldS] right-hand side / solution

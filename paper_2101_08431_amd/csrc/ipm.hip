@@ -43,7 +43,7 @@ constexpr int TJ = 16;             // Schur tile: 16 x 16 (j, l) pairs
 constexpr int ZRB = 8;             // rows per block of the Z kernel
 
 struct IpmArgs {
-    double *r, *s, *dx, *dy, *dr, *ds, *gx, *gy, *V, *tX, *tY, *Lq, *Qi, *Z, *S, *vec, *vec2, *part;
+    double *r, *s, *dx, *dy, *dr, *ds, *gx, *gy, *V, *tX, *tY, *Lq, *Z, *S, *vec, *vec2, *part;
     IpmScal *sc;
     int64_t ldS, N;
 };
@@ -51,7 +51,7 @@ struct IpmArgs {
 static IpmArgs args_of(const IpmState &s) {
     IpmArgs a;
     a.r = s.r; a.s = s.s; a.dx = s.dx; a.dy = s.dy; a.dr = s.dr; a.ds = s.ds;
-    a.gx = s.gx; a.gy = s.gy; a.V = s.V; a.tX = s.tX; a.tY = s.tY; a.Lq = s.Lq; a.Qi = s.Qi;
+    a.gx = s.gx; a.gy = s.gy; a.V = s.V; a.tX = s.tX; a.tY = s.tY; a.Lq = s.Lq;
     a.Z = s.Z; a.S = s.S; a.vec = s.vec; a.vec2 = s.vec2; a.part = s.part; a.sc = s.sc;
     a.ldS = s.ldS;
     a.N = 0;
@@ -383,9 +383,8 @@ __global__ __launch_bounds__(NTHR) void k_fill_duals(AnlsParams p, IpmArgs ia, d
 
 // ---------------------------------------------------------------- direction
 // Per row i: the Cholesky factor L_i of Q1bar_i = Y Y^T + rho I + Diag(r_i / x_i)
-// (packed lower, then 1/diag), V_i = Q1bar_i^-1 b1_i with b1 = -(graX - mu/x),
-// and with EXACT also Q1bar_i^-1 (packed lower).
-template <int K, bool EXACT>
+// (packed lower, then 1/diag) and V_i = Q1bar_i^-1 b1_i with b1 = -(graX - mu/x).
+template <int K>
 __global__ __launch_bounds__(NTHR) void k_factor(AnlsParams p, IpmArgs ia, double mu, double rho) {
     constexpr int NL = K * (K + 1) / 2;
     __shared__ double G[K * K];
@@ -439,29 +438,6 @@ __global__ __launch_bounds__(NTHR) void k_factor(AnlsParams p, IpmArgs ia, doubl
     }
 #pragma unroll
     for (int a = 0; a < K; ++a) ia.V[(int64_t)a * p.ldX + i] = t[a];
-    if (EXACT) {
-        // columns of Q^-1 = L^-T L^-1 e_c; store the lower triangle
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            double u[K];
-#pragma unroll
-            for (int r = 0; r < K; ++r) {
-                double v = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-                for (int q = 0; q < r; ++q) v -= L[r * (r + 1) / 2 + q] * u[q];
-                u[r] = v * inv[r];
-            }
-#pragma unroll
-            for (int r = K - 1; r >= 0; --r) {
-                double v = u[r];
-#pragma unroll
-                for (int q = r + 1; q < K; ++q) v -= L[q * (q + 1) / 2 + r] * u[q];
-                u[r] = v * inv[r];
-            }
-#pragma unroll
-            for (int a = c; a < K; ++a) ia.Qi[(int64_t)(a * (a + 1) / 2 + c) * p.ldX + i] = u[a];
-        }
-    }
 }
 
 // Z_i = L_i^-1 Y for ZRB rows per block: Z[(i*KP + c)*ldY + j], KP = K
@@ -495,159 +471,6 @@ __global__ __launch_bounds__(NTHR) void k_zmat(AnlsParams p, IpmArgs ia) {
             }
 #pragma unroll
             for (int c = 0; c < KP; ++c) ia.Z[((i0 + rr) * KP + c) * p.ldY + j] = c < K ? z[c] : 0.0;
-        }
-    }
-}
-
-// Schur matrix, lower block triangle: one 16 x 16 tile of (j, l) column pairs
-// (j-tile >= l-tile) per block, one (j, l) pair per thread, all (a, b).
-//   S[(j,a), (l,b)] = delta_jl Q2bar_j[a][b] - sum_i (c_ijl X_ia X_ib [+ exact terms])
-template <int K, bool EXACT>
-__global__ __launch_bounds__(256) void k_schur(AnlsParams p, IpmArgs ia, double rho) {
-    constexpr int NL = K * (K + 1) / 2;
-    constexpr int SR = (K <= 8 && !EXACT) ? 16 : 8;   // rows of X staged per step
-    __shared__ double Zs[SR][K][2 * TJ];
-    __shared__ double XX[SR][EXACT ? K * K : K * (K + 1) / 2];
-    __shared__ double Xs[SR][K];
-    __shared__ double Ws[EXACT ? SR : 1][EXACT ? K : 1][2 * TJ];
-    __shared__ double Rs[EXACT ? SR : 1][2 * TJ];
-    __shared__ double Qs[EXACT ? SR : 1][EXACT ? K * K : 1];
-    __shared__ double Ls[EXACT ? SR : 1][EXACT ? NL + K : 1];
-    // tile index -> (jt, lt), jt >= lt
-    const int64_t tix = blockIdx.x;
-    int64_t jt = (int64_t)((sqrt(8.0 * (double)tix + 1.0) - 1.0) * 0.5);
-    while ((jt + 1) * (jt + 2) / 2 <= tix) ++jt;
-    while (jt * (jt + 1) / 2 > tix) --jt;
-    const int64_t lt = tix - jt * (jt + 1) / 2;
-    const int jj = threadIdx.x / TJ, ll = threadIdx.x % TJ;
-    const int64_t j = jt * TJ + jj, l = lt * TJ + ll;
-
-    // The Gauss-Newton part of block (j, l) is symmetric in (a, b): without
-    // the exact terms only its lower triangle is accumulated.
-    constexpr int NACC = EXACT ? K * K : NL;
-    double acc[NACC];
-#pragma unroll
-    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
-
-    for (int64_t i0 = 0; i0 < p.n; i0 += SR) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < SR * K * 2 * TJ; q += 256) {
-            const int rr = q / (K * 2 * TJ), c = (q / (2 * TJ)) % K, col = q % (2 * TJ);
-            const int64_t i = i0 + rr;
-            const int64_t jc = col < TJ ? jt * TJ + col : lt * TJ + col - TJ;
-            Zs[rr][c][col] = (i < p.n && jc < p.m) ? ia.Z[(i * zpad(K) + c) * p.ldY + jc] : 0.0;
-        }
-        for (int q = threadIdx.x; q < SR * K; q += 256) {
-            const int rr = q / K, a = q % K;
-            const int64_t i = i0 + rr;
-            Xs[rr][a] = i < p.n ? p.X[(int64_t)a * p.ldX + i] : 0.0;
-        }
-        if (EXACT) {
-            for (int q = threadIdx.x; q < SR * (NL + K); q += 256) {
-                const int rr = q / (NL + K), c = q % (NL + K);
-                const int64_t i = i0 + rr;
-                Ls[rr][c] = i < p.n ? ia.Lq[(int64_t)c * p.ldX + i] : 1.0;
-            }
-            for (int q = threadIdx.x; q < SR * K * K; q += 256) {
-                const int rr = q / (K * K), a = (q / K) % K, b = q % K;
-                const int64_t i = i0 + rr;
-                const int hi = a > b ? a : b, lo = a > b ? b : a;
-                Qs[rr][a * K + b] = i < p.n ? ia.Qi[(int64_t)(hi * (hi + 1) / 2 + lo) * p.ldX + i] : 0.0;
-            }
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < SR * NACC; q += 256) {
-            const int rr = q / NACC, t = q % NACC;
-            int a, b;
-            if (EXACT) {
-                a = t / K;
-                b = t % K;
-            } else {
-                a = 0;
-                while ((a + 1) * (a + 2) / 2 <= t) ++a;
-                b = t - a * (a + 1) / 2;
-            }
-            XX[rr][t] = Xs[rr][a] * Xs[rr][b];
-        }
-        if (EXACT) {
-            // w = L^-T z for the 32 staged columns; R_ij = X_i . Y_j - M_ij
-            for (int q = threadIdx.x; q < SR * 2 * TJ; q += 256) {
-                const int rr = q / (2 * TJ), col = q % (2 * TJ);
-                const int64_t i = i0 + rr;
-                const int64_t jc = col < TJ ? jt * TJ + col : lt * TJ + col - TJ;
-                double u[K];
-#pragma unroll
-                for (int c = 0; c < K; ++c) u[c] = Zs[rr][c][col];
-#pragma unroll
-                for (int r = K - 1; r >= 0; --r) {
-                    double v = u[r];
-#pragma unroll
-                    for (int qq = r + 1; qq < K; ++qq) v -= Ls[rr][qq * (qq + 1) / 2 + r] * u[qq];
-                    u[r] = v * Ls[rr][NL + r];
-                }
-#pragma unroll
-                for (int c = 0; c < K; ++c) Ws[rr][c][col] = u[c];
-                double res = 0.0;
-                if (i < p.n && jc < p.m) {
-                    res = -p.M[jc * p.ldM + i];
-#pragma unroll
-                    for (int a = 0; a < K; ++a) res = fma(Xs[rr][a], p.Y[(int64_t)a * p.ldY + jc], res);
-                }
-                Rs[rr][col] = res;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int rr = 0; rr < SR; ++rr) {
-            double c = 0.0;
-#pragma unroll
-            for (int q = 0; q < K; ++q) c = fma(Zs[rr][q][jj], Zs[rr][q][TJ + ll], c);
-#pragma unroll
-            for (int q = 0; q < NACC; ++q) acc[q] = fma(c, XX[rr][q], acc[q]);
-            if (EXACT) {
-                const double Rj = Rs[rr][jj], Rl = Rs[rr][TJ + ll];
-                const double RR = Rj * Rl;
-#pragma unroll
-                for (int a = 0; a < K; ++a) {
-                    const double xa_rl = Xs[rr][a] * Rl;
-                    const double wla_rj = Ws[rr][a][TJ + ll] * Rj;
-#pragma unroll
-                    for (int b = 0; b < K; ++b) {
-                        const int q = EXACT ? a * K + b : 0;
-                        double v = acc[q];
-                        v = fma(xa_rl, Ws[rr][b][jj], v);
-                        v = fma(wla_rj, Xs[rr][b], v);
-                        v = fma(RR, Qs[rr][a * K + b], v);
-                        acc[q] = v;
-                    }
-                }
-            }
-        }
-    }
-    // Component-major ordering (row a*m + j).  Pair (j, l) with j > l gives
-    // every entry of S that couples j and l: entry (a*m + j, b*m + l) goes to
-    // the lower triangle as is (a >= b) or transposed (a < b); a pair with
-    // j == l gives the lower (a >= b) entries of its own k x k block; pairs
-    // with j < l add nothing new.
-    if (j < p.m && l < p.m && j >= l) {
-        const double *G = ia.sc->GX;
-        const int64_t m = p.m;
-#pragma unroll
-        for (int a = 0; a < K; ++a) {
-#pragma unroll
-            for (int b = 0; b < K; ++b) {
-                const int q = EXACT ? a * K + b : (a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a);
-                double v = -acc[q];
-                if (j == l) {
-                    v += G[a * K + b];
-                    if (a == b) v += rho + ia.s[(int64_t)a * p.ldY + j] / p.Y[(int64_t)a * p.ldY + j];
-                }
-                const int64_t row = a * m + j, col = b * m + l;
-                if (row >= col)
-                    ia.S[col * ia.ldS + row] = v;
-                else if (j > l)
-                    ia.S[row * ia.ldS + col] = v;
-            }
         }
     }
 }
@@ -980,8 +803,8 @@ __global__ __launch_bounds__(NTHR) void k_duals_out(AnlsParams p, IpmArgs ia, do
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct IpmLayout {
-    size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Qi, Z, S, vec, vec2, XX, Dinv, spart, flags, part, fpart, sc,
-        total;
+    size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Linv, Rrow, Z, S, vec, vec2, XX, Dinv, spart, flags, part, fpart,
+        sc, total;
     int64_t ldX, ldY, ldS;
     int P;
 };
@@ -1013,7 +836,8 @@ static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     L.r = take(vx); L.dx = take(vx); L.dr = take(vx); L.gx = take(vx); L.V = take(vx); L.tX = take(vx);
     L.s = take(vy); L.dy = take(vy); L.ds = take(vy); L.gy = take(vy); L.tY = take(vy);
     L.Lq = take((size_t)(NL + K) * L.ldX * 8);
-    L.Qi = take((size_t)NL * L.ldX * 8);
+    L.Linv = take((size_t)n * K * K * 8);
+    L.Rrow = take((size_t)n * L.ldY * 8);
     L.Z = take((size_t)n * zpad(K) * L.ldY * 8);
     L.S = take((size_t)L.ldS * L.ldS * 8);
     L.vec = take((size_t)L.ldS * 8);
@@ -1042,7 +866,8 @@ nmf_status ipm_bind(IpmState &s, uint8_t *base, int64_t n, int64_t m_cap, int K)
     s.dr = (double *)(base + L.dr); s.ds = (double *)(base + L.ds);
     s.gx = (double *)(base + L.gx); s.gy = (double *)(base + L.gy);
     s.V = (double *)(base + L.V); s.tX = (double *)(base + L.tX); s.tY = (double *)(base + L.tY);
-    s.Lq = (double *)(base + L.Lq); s.Qi = (double *)(base + L.Qi); s.Z = (double *)(base + L.Z);
+    s.Lq = (double *)(base + L.Lq); s.Z = (double *)(base + L.Z);
+    s.Linv = (double *)(base + L.Linv); s.Rrow = (double *)(base + L.Rrow);
     s.S = (double *)(base + L.S); s.vec = (double *)(base + L.vec); s.vec2 = (double *)(base + L.vec2);
     s.XX = (double *)(base + L.XX);
     s.Dinv = (double *)(base + L.Dinv);
@@ -1208,11 +1033,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
     const int64_t N = p.m * K;
     const double rho = c.s.rho;
     // factors of Q1bar, V = Q1bar^-1 b1, X^T V
-    if (exact) {
-        IPM_KS(K, hipLaunchKernelGGL((k_factor<KK, true>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, rho));
-    } else {
-        IPM_KS(K, hipLaunchKernelGGL((k_factor<KK, false>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, rho));
-    }
+    IPM_KS(K, hipLaunchKernelGGL(k_factor<KK>, g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, rho));
     IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, c.s.V, p.ldX, p.n, c.s.part));
     HCK(finish(c, c.s.part, PRS, p.Bx, K * K, 0u, c.s.sc->XtV));
     const bool reuse = !exact && c.s.S_gn_valid;
@@ -1223,8 +1044,25 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
                                            p, c.ia));
         const int64_t nt = (p.m + TJ - 1) / TJ;
         if (exact) {
-            const dim3 gs((unsigned)(nt * (nt + 1) / 2));
-            IPM_KS(K, hipLaunchKernelGGL((k_schur<KK, true>), gs, dim3(256), 0, c.st, p, c.ia, rho));
+            HCK(launch_linv(K, c.s.Lq, p.ldX, p.n, c.s.Linv, c.st));
+            HCK(launch_residual_rows(K, p.M, p.ldM, p.X, p.ldX, p.Y, p.ldY, p.n, p.m, c.s.Rrow, c.st));
+            SchurExArgs g;
+            g.Z = c.s.Z;
+            g.X = p.X;
+            g.Linv = c.s.Linv;
+            g.R = c.s.Rrow;
+            g.n = p.n;
+            g.m = p.m;
+            g.ldX = p.ldX;
+            g.ldY = p.ldY;
+            g.NT = (int)((N + CB - 1) / CB);
+            g.S = c.s.S;
+            g.ldS = c.s.ldS;
+            g.GX = c.s.sc->GX;
+            g.s = c.s.s;
+            g.Y = p.Y;
+            g.rho = rho;
+            HCK(launch_schur_exact(K, g, c.st));
         } else {
             HCK(launch_xx(K, p.X, p.ldX, p.n, c.s.XX, c.st));
             SchurArgs g;
