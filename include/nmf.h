@@ -180,6 +180,17 @@ nmf_status nmf_get_report(nmf_ctx *ctx, nmf_report *report);
  * after the stop rule holds return at once and are still counted. */
 nmf_status nmf_anls_profile(nmf_ctx *ctx, int32_t sweeps, double *ms);
 
+/* Profiling of stage 2: runs like nmf_ipm_step(ctx, iters, NULL) while timing
+ * the dense steps of the Newton solve of Sec. III-B with HIP events (each
+ * timed region is synchronised, so the call runs slower than nmf_ipm_step).
+ * ms[0..4] (host, caller-owned): mean device milliseconds of one Gauss-Newton
+ * Schur formation (eq. (20)), one exact-Hessian formation (eq. (27)), one
+ * Cholesky factorisation of the Schur matrix, one pair of triangular solves,
+ * and the wall time per inner iteration of the whole call.  counts[0..4]
+ * (host, may be NULL): how many of each were timed and inner iterations run.
+ * Returns what nmf_ipm_step returns. */
+nmf_status nmf_ipm_profile(nmf_ctx *ctx, int32_t iters, double *ms, int64_t *counts);
+
 /* Re-plans the stage-1 launch shape of a context: column splits of the X-half
  * and row splits of the Y-half (0 = automatic, at most 64 each).  A single
  * split runs that half as one kernel that streams M and solves its tile.

@@ -27,7 +27,7 @@ EXPORTS = [
     "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
     "nmf_get_duals", "nmf_set_launch_shape", "nmf_set_launch_fusion", "nmf_get_launch_shape", "nmf_set_anls_budget", "nmf_batch_workspace_bytes", "nmf_batch_create",
     "nmf_batch_refresh", "nmf_batch_anls_step", "nmf_batch_poll", "nmf_batch_sync", "nmf_batch_destroy",
-    "nmf_batch_create_static",
+    "nmf_batch_create_static", "nmf_ipm_profile",
 ]
 BATCH_STATIC_MAX = 1024   # NMF_BATCH_STATIC_MAX
 
@@ -136,6 +136,8 @@ def load():
     L.nmf_get_report.restype = ctypes.c_int
     L.nmf_anls_profile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.nmf_anls_profile.restype = ctypes.c_int
+    L.nmf_ipm_profile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.nmf_ipm_profile.restype = ctypes.c_int
     L.nmf_set_launch_shape.argtypes = [vp, i32, i32]
     L.nmf_set_launch_shape.restype = ctypes.c_int
     L.nmf_set_launch_fusion.argtypes = [vp, i32, i32]
@@ -270,6 +272,17 @@ class NMF:
         ms = (ctypes.c_double * 4)()
         self._check(load().nmf_anls_profile(self._ctx, int(sweeps), ms), ok=(NMF_OK,))
         return tuple(ms)
+
+    def ipm_profile(self, iters):
+        """Runs up to `iters` stage-2 inner iterations with the dense steps
+        event-timed.  Returns (status, ms, counts): ms = mean device ms of a
+        Gauss-Newton Schur formation, an exact-Hessian formation, a Cholesky
+        factorisation, a pair of triangular solves, and wall ms per inner
+        iteration; counts = how many of each (the last: inner iterations)."""
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int64 * 5)()
+        st = self._check(load().nmf_ipm_profile(self._ctx, int(iters), ms, cnt))
+        return st, tuple(ms), tuple(int(v) for v in cnt)
 
     def solve(self):
         r = Report()

@@ -11,7 +11,9 @@
 //
 // S is stored column-major with leading dimension ldS >= NT*64 and padded to
 // NT*64 rows and columns with the identity, so every kernel works on whole
-// 64 x 64 tiles.  Only the lower triangle is read.
+// 64 x 64 tiles.  Only the lower triangle is read.  After the factorisation
+// the tiles below the diagonal hold L; the diagonal factor tiles are kept, as
+// their inverses, in Dinv.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -576,7 +578,9 @@ __device__ __forceinline__ void trsm_quad(double (&x)[16], const double *Lz, con
 //   blocks 0 .. NT-c-1 serve the tiles (c + b, c) of column c: each updates
 //   the diagonal tile (c, c) as well as its own and factors it (the same
 //   arithmetic in every such block, so every copy of L_cc is identical); block
-//   0 stores L_cc, the others solve their panel tile L_ic = A_ic L_cc^-T;
+//   0 stores L_cc in Dinv[c] (tile (c, c) of S is still being read by the
+//   others, so it is left unfactored), the others solve their panel tile
+//   L_ic = A_ic L_cc^-T;
 //   the other blocks, tiles right of column c, only store their update.
 // No block waits for another.  The inverses of the diagonal factor tiles (for
 // the triangular solves) are formed after the last step (k_chol_inverses).
@@ -689,7 +693,10 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs g, int kt) {
     if (wave == 0) potrf_wave(T, Lc, g.fail);
     __syncthreads();
     if (diag) {
-        for (int idx = threadIdx.x; idx < 4096; idx += 256) S[(db + (idx >> 6)) * ldS + db + (idx & 63)] = Lc[idx];
+        // L_cc goes to Dinv[c] (k_chol_inverses inverts it there): the other
+        // blocks of this launch may still be reading tile (c, c) of S
+        double *Dc = g.Dinv + (int64_t)c * 4096;
+        for (int idx = threadIdx.x; idx < 4096; idx += 256) Dc[idx] = Lc[idx];
         return;
     }
     // strictly lower part of L_cc into T (column by column) and 1 / diagonal
@@ -705,16 +712,17 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs g, int kt) {
     for (int v = 0; v < 16; ++v) S[(db + part * 16 + v) * ldS + rb + qrow] = x16[v];
 }
 
-// Inverses of the NT diagonal factor tiles, one block per tile: row j of
-// I L^-T is column j of L^-1, stored column-major (Dinv[j*64 + i] = L^-1[i][j]).
+// Inverses of the NT diagonal factor tiles, in place in Dinv (which holds
+// L_tt column by column on entry), one block per tile: row j of I L^-T is
+// column j of L^-1, stored column-major (Dinv[j*64 + i] = L^-1[i][j]).
 __global__ __launch_bounds__(256) void k_chol_inverses(CholArgs g) {
     __shared__ __align__(16) double Lz[64 * 64];
     __shared__ double dsh[64];
     const int t = blockIdx.x;
-    const int64_t db = (int64_t)t * 64;
+    const double *Lt = g.Dinv + (int64_t)t * 4096;
     for (int idx = threadIdx.x; idx < 4096; idx += 256) {
         const int q = idx >> 6, pp = idx & 63;
-        const double v = g.S[(db + q) * g.ldS + db + pp];
+        const double v = Lt[idx];
         Lz[idx] = pp > q ? v : 0.0;
         if (pp == q) dsh[q] = 1.0 / v;
     }

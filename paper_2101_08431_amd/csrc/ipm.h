@@ -60,6 +60,13 @@ struct IpmState {
     bool in_inner = false;                     // inside the inner loop of the current mu
     bool S_gn_valid = false;                   // S holds the factored Gauss-Newton Schur matrix of this point
     int64_t iters = 0, outer = 0, backtracks = 0, exact_steps = 0, fallbacks = 0, cap_hits = 0;
+    // optional device timing of the dense steps (nmf_ipm_profile): events
+    // around each Gauss-Newton / exact Schur formation, each factorisation
+    // and each pair of triangular solves; prof_ms / prof_n accumulate
+    bool prof = false;
+    hipEvent_t pev[2] = {nullptr, nullptr};
+    double prof_ms[4] = {0, 0, 0, 0};          // GN formation, exact formation, Cholesky, solve pair
+    int64_t prof_n[4] = {0, 0, 0, 0};
     std::string err;
 };
 

@@ -963,6 +963,22 @@ nmf_status kkt(Ctx &c, double mu) {
     return NMF_OK;
 }
 
+// Device time of the work enqueued between prof_begin and prof_end (a
+// synchronising measurement, used only by nmf_ipm_profile).
+void prof_begin(Ctx &c) {
+    if (c.s.prof) (void)hipEventRecord(c.s.pev[0], c.st);
+}
+void prof_end(Ctx &c, int slot) {
+    if (!c.s.prof) return;
+    (void)hipEventRecord(c.s.pev[1], c.st);
+    (void)hipEventSynchronize(c.s.pev[1]);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c.s.pev[0], c.s.pev[1]) == hipSuccess) {
+        c.s.prof_ms[slot] += ms;
+        c.s.prof_n[slot] += 1;
+    }
+}
+
 // Flag arrays of the two triangular solves (2 x NT; a third NT is spare): zeroed once,
 // then every launch that hands over through them uses a fresh epoch.
 nmf_status ensure_flags(Ctx &c) {
@@ -1043,6 +1059,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
         IPM_KS(K, hipLaunchKernelGGL(k_zmat<KK>, dim3((unsigned)((p.n + ZRB - 1) / ZRB)), dim3(NTHR), 0, c.st,
                                            p, c.ia));
         const int64_t nt = (p.m + TJ - 1) / TJ;
+        prof_begin(c);
         if (exact) {
             HCK(launch_linv(K, c.s.Lq, p.ldX, p.n, c.s.Linv, c.st));
             HCK(launch_residual_rows(K, p.M, p.ldM, p.X, p.ldX, p.Y, p.ldY, p.n, p.m, c.s.Rrow, c.st));
@@ -1083,8 +1100,11 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
             g.rho = rho;
             HCK(launch_schur_gn(K, g, c.st));
         }
+        prof_end(c, exact ? 1 : 0);
+        prof_begin(c);
         nmf_status st = cholesky(c, N);
         if (st != NMF_OK) return st;
+        prof_end(c, 2);
         int fail = 0;
         HCK(hipMemcpyAsync(&fail, &c.s.sc->chol_fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
         HCK(hipStreamSynchronize(c.st));
@@ -1103,8 +1123,10 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
     } else {
         IPM_KS(K, hipLaunchKernelGGL((k_rhs<KK, false>), g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu));
     }
+    prof_begin(c);
     nmf_status st = solve_S(c, N);
     if (st != NMF_OK) return st;
+    prof_end(c, 3);
     IPM_KS(K, hipLaunchKernelGGL(k_post_y<KK>, g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu, tau, 0));
     IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.m), dim3(NTHR), 0, c.st, c.s.dy, p.Y, p.ldY, p.m,
                                        c.s.part + (size_t)(p.By + p.Bx) * PRS));

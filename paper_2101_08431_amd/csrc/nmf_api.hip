@@ -697,6 +697,41 @@ nmf_status nmf_ipm_step(nmf_ctx *c, int32_t iters, nmf_report *r) {
     return st;
 }
 
+nmf_status nmf_ipm_profile(nmf_ctx *c, int32_t iters, double *ms, int64_t *counts) {
+    if (!c || !ms) return NMF_EINVAL;
+    nmfk::IpmState &s = c->ipm;
+    if (!c->opt.with_ipm) return fail(c, NMF_ESTATE, "context created without stage-2 workspace");
+    for (int q = 0; q < 4; ++q) {
+        s.prof_ms[q] = 0.0;
+        s.prof_n[q] = 0;
+    }
+    if (hipEventCreate(&s.pev[0]) != hipSuccess || hipEventCreate(&s.pev[1]) != hipSuccess) {
+        if (s.pev[0]) (void)hipEventDestroy(s.pev[0]);
+        s.pev[0] = s.pev[1] = nullptr;
+        return fail(c, NMF_EDEVICE, "hipEventCreate failed");
+    }
+    s.prof = true;
+    const int64_t it0 = s.iters;
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    const nmf_status st = nmf_ipm_step(c, iters, nullptr);
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCHK(c, hipEventSynchronize(c->ev1));
+    float total = 0.f;
+    (void)hipEventElapsedTime(&total, c->ev0, c->ev1);
+    s.prof = false;
+    (void)hipEventDestroy(s.pev[0]);
+    (void)hipEventDestroy(s.pev[1]);
+    s.pev[0] = s.pev[1] = nullptr;
+    const int64_t done = s.iters - it0;
+    for (int q = 0; q < 4; ++q) ms[q] = s.prof_n[q] ? s.prof_ms[q] / (double)s.prof_n[q] : 0.0;
+    ms[4] = done > 0 ? total / (double)done : 0.0;
+    if (counts) {
+        for (int q = 0; q < 4; ++q) counts[q] = s.prof_n[q];
+        counts[4] = done;
+    }
+    return st;
+}
+
 nmf_status nmf_solve(nmf_ctx *c, nmf_report *r) {
     if (!c) return NMF_EINVAL;
     nmf_status st = NMF_OK;

@@ -184,6 +184,26 @@ def test_solve_3000x500x5_matches_oracle_golden(orc):
     assert x_err <= GOLDEN_FACTOR_BAR and y_err <= GOLDEN_FACTOR_BAR
 
 
+def test_first_iteration_10000x2000x10_matches_oracle_golden(orc):
+    # the largest stage-2 case (Schur order 20000, S of 3.2 GB): the oracle's
+    # 20-sweep stage-1 point, the transition and one interior-point iteration,
+    # against the oracle's iteration stored by
+    # tests/golden/make_ipm_first_golden.py (oracle only)
+    g = np.load(os.path.join(os.path.dirname(GOLDEN), "ipm1_pdf_10000x2000_k10_seed0.npz"))
+    M, X0, Y0 = synth.make("pdf_10000x2000_k10", 0)
+    M = np.asarray(M)
+    r1 = orc.anls(M, X0, Y0.T.copy(), exact_sweeps=int(g["sweeps"]))
+    print("case ipm 1 iteration pdf_10000x2000_k10 seed 0 (golden)", flush=True)
+    ctx = gpu_ctx(M, r1["X"], r1["Yt"], eps_tol=float(g["eps_tol"]))
+    ctx.ipm_step(1)
+    Xg, Yg = ctx.factors()
+    Rg, Sg = ctx.duals()
+    print(f"trajectory agreement: X {rel(Xg, g['X']):.2e} Y {rel(Yg.T, g['Yt']):.2e} "
+          f"R {rel(Rg, g['r']):.2e} S {rel(Sg.T, g['s']):.2e}", flush=True)
+    assert rel(Xg, g["X"]) <= 1e-8 and rel(Yg.T, g["Yt"]) <= 1e-8
+    assert rel(Rg, g["r"]) <= 1e-8 and rel(Sg.T, g["s"]) <= 1e-8
+
+
 def test_nmf_solve_3000x500x5_converges(orc):
     # the whole two-stage solve from the seeded start must converge (cap far
     # above the measured iteration counts) and certify E(.;0) <= 1e-8
