@@ -409,9 +409,10 @@ def serving_section(seconds, rate=200.0, warm=1.0, plain=True):
     res = {"streams": 64, "rate_per_s": rate, "seconds": seconds, "requests": len(reqs),
            "m_final_max": max(s.m_capacity for s in specs), "warmup_s": warm,
            "request": "append 16 columns, then warm-started stage-1 sweeps until the stop rule "
-                      "(eps_STOL 1e-4) holds or 64 sweeps are done"}
+                      "(eps_STOL 1e-4) holds or 64 sweeps are done; E0_* give the KKT error E(.;0) of "
+                      "eq. (10) each request ends at (stage-1 duals), the same in the served and plain runs"}
     for name, cls in (("served", Server), ("plain", PlainServer)) if plain else (("served", Server),):
-        srv = cls(specs, sweeps_per_round=4, eps_stol=1e-4, request_sweeps=64)
+        srv = cls(specs, sweeps_per_round=4, eps_stol=1e-4, request_sweeps=64, kkt=True)
         srv.open_all()
         log(f"serving: {name} streams open")
         t0 = time.perf_counter()

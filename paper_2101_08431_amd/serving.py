@@ -12,7 +12,9 @@ on the grown problem.  Requests of one stream run in arrival order.
     the bytes of all open streams stay within ``hbm_budget``; otherwise it
     waits, first come first served, until a stream closes;
   * at most ``max_active`` requests are in flight;
-  * the requests in flight share batched sweeps (``nmf_batch_*``): rounds of
+  * the requests in flight share batched sweeps (``nmf_batch_*``; the batch is
+    rebuilt on every join or leave with ``nmf_batch_create_static``, which
+    allocates no device memory): rounds of
     ``sweeps_per_round`` sweeps, then a status poll; finished requests leave
     and waiting ones join between rounds, so new work enters while other
     requests are on the GPU;
@@ -65,6 +67,7 @@ class Request:
     sweeps: int = 0
     solves: int = 0
     result: Optional[tuple] = None
+    E0: Optional[float] = None   # E(.;0) of eq. (10) at the request's end point (stage-1 duals)
 
     @property
     def latency(self):
@@ -95,7 +98,7 @@ class _Base:
     sweeps_per_round: sweeps between two status checks."""
 
     def __init__(self, specs: List[StreamSpec], eps_stol=1e-4, initial_sweeps=2000, request_sweeps=64,
-                 sweeps_per_round=4, hbm_budget=None, record=False):
+                 sweeps_per_round=4, hbm_budget=None, record=False, kkt=False):
         import torch
         from ._lib import workspace_bytes
         self.torch = torch
@@ -104,6 +107,7 @@ class _Base:
         self.request_sweeps = int(request_sweeps)
         self.T = int(sweeps_per_round)
         self.record = record
+        self.kkt = bool(kkt)   # measure E(.;0) of every finished request (after its end time)
         for st in self.streams.values():
             st.nbytes = workspace_bytes(st.spec.n, st.spec.m_capacity, st.spec.k, self.opts)
         total = sum(st.nbytes for st in self.streams.values())
@@ -184,6 +188,8 @@ class _Base:
         req.solves = req.sweeps * (st.spec.n + m) + m
         if self.record:
             req.result = st.ctx.factors()
+        if self.kkt:
+            req.E0 = float(st.ctx.report()["E0"])
         st.active = None
         if req.close:
             self._close(st)
@@ -265,7 +271,10 @@ class Server(_Base):
             if running and dirty:
                 if batch is not None:
                     batch.close()
-                batch = Batch([s.ctx for s in running], stream=self._batch_stream())
+                # the batch tables live in the library's own per-device array
+                # (nmf_batch_create_static): a rebuild allocates nothing and
+                # waits only for the member streams
+                batch = Batch([s.ctx for s in running], stream=self._batch_stream(), static=True)
                 batch_members = list(running)
                 dirty = False
             if running:
@@ -333,11 +342,17 @@ def summarize(reqs: List[Request], t_from=0.0, t_to=None):
     lat = np.array([r.latency for r in sel]) * 1e3
     span = max(r.end for r in sel) - min(r.arrival for r in sel)
     solves = sum(r.solves for r in sel)
-    return {"requests": len(sel), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
-            "sweeps_per_request": float(np.mean([r.sweeps for r in sel])),
-            "requests_per_s": len(sel) / span if span > 0 else None,
-            "solves_per_s": solves / span if span > 0 else None}
+    out = {"requests": len(sel), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+           "sweeps_per_request": float(np.mean([r.sweeps for r in sel])),
+           "requests_per_s": len(sel) / span if span > 0 else None,
+           "solves_per_s": solves / span if span > 0 else None}
+    E = [r.E0 for r in sel if r.E0 is not None]
+    if E:
+        out["E0_median"] = float(np.median(E))
+        out["E0_p99"] = float(np.percentile(E, 99))
+        out["E0_max"] = float(np.max(E))
+    return out
 
 
 def build_workload(streams=64, rate=200.0, seconds=20.0, m0=64, add=16, seed=7, big_every=5,
