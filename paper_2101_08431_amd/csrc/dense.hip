@@ -48,14 +48,6 @@ __device__ __forceinline__ double lane_read(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Orders this wave's LDS accesses (a wave executes its LDS operations in
-// order; this keeps the compiler from moving them across the point).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 constexpr unsigned kSpinLimit = 1u << 24;   // ~1 s of polling, then give up and flag it
 
 // Publishes flags[idx] = epoch after every store of the block (release,
@@ -435,159 +427,105 @@ __global__ __launch_bounds__(256) void k_pad_identity(double *S, int64_t ldS, in
 }
 
 // ------------------------------------------------------------- Cholesky of S
-// Column c of a 64 x 64 factor kept in LDS (Lc[c*64 + p]), rows from c+1 on,
-// loaded in 16-byte pairs, all issued before any is used.
-template <int C>
-__device__ __forceinline__ void load_col_tail(const double *Lc, double (&v)[64]) {
-    const double2 *col = reinterpret_cast<const double2 *>(Lc + C * 64);
-#pragma unroll
-    for (int p2 = (C + 1) / 2; p2 < 32; ++p2) {
-        const double2 w = col[p2];
-        v[2 * p2] = w.x;
-        v[2 * p2 + 1] = w.y;
-    }
-}
+constexpr int LDT = 65;   // LDS row stride (doubles) of a 64 x 64 tile
 
-// Pivot C of the right-looking factorisation (lane = row): the pivot comes
-// from lane C's fully updated a[C]; this lane's entry of column C is returned
-// and published in Lc.
-template <int C>
-__device__ __forceinline__ double pivot_publish(double (&a)[64], double *Lc, bool &ok, double &mydiag, int lane) {
-    const double d = lane_read(a[C], C);
-    ok = ok && (d > 0.0);
-    const double dd = d > 0.0 ? d : 1.0;
-    const double s = rsqrt_nr(dd);
-    double l = 0.0;
-    if (lane > C) l = a[C] * s;
-    if (lane == C) {
-        l = dd * s;
-        mydiag = l;
-    }
-    Lc[C * 64 + lane] = l;
-    return l;
-}
-
-// Step C with one step of look-ahead: column C is published (this lane's
-// entry lC); the lane first updates a[C+1] with it, forms and publishes pivot
-// C+1, and only then applies column C to the rest of its row, so that the
-// updates overlap the next column's round trip through LDS.
-template <int C>
-struct PotrfStep {
-    static __device__ __forceinline__ void run(double (&a)[64], double *Lc, bool &ok, double &mydiag, int lane,
-                                               double lC) {
-        wave_lds_sync();
-        double col[64];
-        load_col_tail<C>(Lc, col);
-        if (C + 1 < 64) {
-            constexpr int N1 = C + 1 < 64 ? C + 1 : 63;
-            a[N1] = fma(-lC, col[N1], a[N1]);
-            const double lN = pivot_publish<N1>(a, Lc, ok, mydiag, lane);
+// Inverse W = L^-1 of the factor L of the 16 x 16 diagonal block j of the
+// tile T (row-major, stride LDT), by one wave.  Lane p = lane % 16 holds row p
+// of the block in a[]: step c takes pivot c from lane c, scales column c and
+// applies it to the rows below (right-looking); lanes above row c compute
+// values of the upper triangle that nothing reads, so no step needs a lane
+// mask.  The same steps run the forward substitution L w = e_p for column p
+// of W in w[] (entry c is final at step c), reusing the broadcast column
+// entries.  W goes to the same block of Lf; L itself is not kept.  A pivot
+// that is not positive sets *bad (the factor is then not used) and is
+// replaced by 1.
+__device__ __forceinline__ void potrf_inv16(const double *T, double *Lf, int j, int *bad) {
+    const int lane = threadIdx.x & 63, p = lane & 15;
+    const double *Trow = T + (16 * j + p) * LDT + 16 * j;
+    double a[16], w[16];
 #pragma unroll
-            for (int j = C + 2; j < 64; ++j) a[j] = fma(-lC, col[j], a[j]);
-            PotrfStep<C + 1>::run(a, Lc, ok, mydiag, lane, lN);
+    for (int q = 0; q < 16; ++q) {
+        a[q] = Trow[q];
+        w[q] = (q == p) ? 1.0 : 0.0;
+    }
+    double dmin = 1.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const double d = lane_read(a[c], c);
+        dmin = fmin(dmin, d);
+        const double s = rsqrt_nr(d > 0.0 ? d : 1.0);
+        const double l = a[c] * s;   // row p of column c; on lane c, sqrt(d)
+        a[c] = l;
+        w[c] *= s;
+#pragma unroll
+        for (int jj = c + 1; jj < 16; ++jj) {
+            const double ljc = lane_read(l, jj);   // L[jj][c]
+            a[jj] = fma(-l, ljc, a[jj]);
+            w[jj] = fma(-ljc, w[c], w[jj]);
+            // pins the update of w to this step (otherwise it sinks to the
+            // end of the loop and every broadcast value has to be kept)
+            asm volatile("" : "+v"(w[jj]));
         }
     }
-};
-template <>
-struct PotrfStep<64> {
-    static __device__ __forceinline__ void run(double (&)[64], double *, bool &, double &, int, double) {}
-};
-
-// Factor of one 64 x 64 tile by one wave (right-looking: step c publishes
-// column c in LDS and updates the rows below it independently).  T holds the
-// tile (row-major, stride 65; the lower triangle is read).  On return Lc
-// holds L column by column (Lc[q*64 + p] = L[p][q], zeros above the diagonal).
-// A pivot that is not positive sets *bad and is replaced by 1.
-__device__ __forceinline__ void potrf_wave(const double *T, double *Lc, int *bad) {
-    const int lane = threadIdx.x & 63;
-    double a[64];
+    if (lane < 16) {
 #pragma unroll
-    for (int q = 0; q < 64; ++q) a[q] = (q <= lane) ? T[lane * 65 + q] : 0.0;
-    bool ok = true;
-    double mydiag = 1.0;
-    const double l0 = pivot_publish<0>(a, Lc, ok, mydiag, lane);
-    PotrfStep<0>::run(a, Lc, ok, mydiag, lane, l0);
-    wave_lds_sync();
-    if (!ok && lane == 0) *bad = 1;
+        for (int q = 0; q < 16; ++q) Lf[(16 * j + q) * LDT + 16 * j + p] = w[q];
+    }
+    if (!(dmin > 0.0) && lane == 0) *bad = 1;
 }
 
-// Broadcast of lane OWNER's value within each quad of lanes (DPP quad_perm).
-template <int OWNER>
-__device__ __forceinline__ double quad_bcast(double v) {
-    constexpr int ctrl = OWNER * 0x55;
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), ctrl, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+// Block column j of the 64 x 64 factor, for row block i > j (one wave): the
+// sub-panels L_lj = T_lj W_jj^T for j < l <= i (L_ij stored in Lf; the others
+// are recomputed here, bit-identical to their owners' copies, so that no
+// second barrier is needed), then T_il -= L_ij L_lj^T for j < l <= i.  The
+// products are formed transposed (D[q][p] = X[p][q]), so that a product's
+// output registers are the next product's operands as they stand.
+__device__ __forceinline__ v4d sub_panel(const double *T, const double *Lf, int j, int l) {
+    const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
+    v4d d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        d = mfma16(Lf[(16 * j + r) * LDT + 16 * j + 4 * s + gq], T[(16 * l + r) * LDT + 16 * j + 4 * s + gq], d);
+    return d;
 }
 
-// Step Q of X = A L^-T with four lanes per row (quad): lane part P owns
-// columns 16P..16P+15 of its row in x[].  The owner of column Q scales it by
-// 1 / L_QQ, the quad shares it, and every lane updates its own columns with
-// column Q of the strictly lower part of L (Lz, zeros on and above the
-// diagonal, so no lane needs a bound); column Q+1 is loaded one step ahead.
-template <int Q>
-struct TrsmQuadStep {
-    static __device__ __forceinline__ void run(double (&x)[16], const double *Lz, const double *dsh, int part,
-                                               const double (&cur)[16], double dcur) {
-        constexpr int OWNER = Q >> 4, UQ = Q & 15;
-        double nxt[16], dnxt = 0.0;
-        if (Q + 1 < 64) {
-            const double2 *col = reinterpret_cast<const double2 *>(Lz + (Q + 1 < 64 ? Q + 1 : 63) * 64 + part * 16);
+__device__ __forceinline__ void inner_update(double *T, double *Lf, int j, int i) {
+    const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
+    const v4d Li = sub_panel(T, Lf, j, i);
 #pragma unroll
-            for (int h = 0; h < 8; ++h) {
-                const double2 w = col[h];
-                nxt[2 * h] = w.x;
-                nxt[2 * h + 1] = w.y;
-            }
-            dnxt = dsh[Q + 1 < 64 ? Q + 1 : 63];
-        }
-        if (part == OWNER) x[UQ] *= dcur;
-        const double xq = quad_bcast<OWNER>(x[UQ]);
+    for (int v = 0; v < 4; ++v) Lf[(16 * i + r) * LDT + 16 * j + gq + 4 * v] = Li[v];
+    for (int l = j + 1; l <= i; ++l) {
+        const v4d Ll = (l == i) ? Li : sub_panel(T, Lf, j, l);
+        double *Tb = T + (16 * i + r) * LDT + 16 * l + gq;
+        v4d acc;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) x[v] = fma(-xq, cur[v], x[v]);
-        TrsmQuadStep<Q + 1>::run(x, Lz, dsh, part, nxt, dnxt);
+        for (int v = 0; v < 4; ++v) acc[v] = Tb[4 * v];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = mfma16(-Ll[s], Li[s], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Tb[4 * v] = acc[v];
     }
-};
-template <>
-struct TrsmQuadStep<64> {
-    static __device__ __forceinline__ void run(double (&)[16], const double *, const double *, int,
-                                               const double (&)[16], double) {}
-};
-
-// X = A L^-T for a 64 x 64 tile by a block of 256 threads: thread (row =
-// 16*wave + lane/4, part = lane%4) starts from x = A[row][16 part ..] and
-// ends with X[row][16 part ..].  Lz: strictly lower part of L column by
-// column (Lz[q*64 + p] = L[p][q] for p > q, else 0); dsh[q] = 1 / L_qq.
-__device__ __forceinline__ void trsm_quad(double (&x)[16], const double *Lz, const double *dsh) {
-    const int part = threadIdx.x & 3;
-    double c0[16];
-    const double2 *col = reinterpret_cast<const double2 *>(Lz + part * 16);
-#pragma unroll
-    for (int h = 0; h < 8; ++h) {
-        const double2 w = col[h];
-        c0[2 * h] = w.x;
-        c0[2 * h + 1] = w.y;
-    }
-    TrsmQuadStep<0>::run(x, Lz, dsh, part, c0, dsh[0]);
 }
 
 // Step kt (-1 .. NT-2) of the right-looking factorisation by 64-wide block
-// columns, for column c = kt + 1:
-//   every tile (i, j), c <= j <= i, gets A_ij -= L_i,kt L_j,kt^T (kt >= 0);
-//   blocks 0 .. NT-c-1 serve the tiles (c + b, c) of column c: each updates
-//   the diagonal tile (c, c) as well as its own and factors it (the same
-//   arithmetic in every such block, so every copy of L_cc is identical); block
-//   0 stores L_cc in Dinv[c] (tile (c, c) of S is still being read by the
-//   others, so it is left unfactored), the others solve their panel tile
-//   L_ic = A_ic L_cc^-T;
-//   the other blocks, tiles right of column c, only store their update.
-// No block waits for another.  The inverses of the diagonal factor tiles (for
-// the triangular solves) are formed after the last step (k_chol_inverses).
-__global__ __launch_bounds__(256) void k_chol_step(CholArgs g, int kt) {
-    __shared__ __align__(16) double T[64 * 65];
-    __shared__ __align__(16) double Lc[64 * 64];
-    __shared__ double dsh[64];
+// columns, for column c = kt + 1; 512 threads per block.
+//   Tiles right of column c (c < tj <= ti): A_ij -= L_i,kt L_j,kt^T, each of
+//   the 8 waves a 16 x 32 part.
+//   Tiles of column c (blocks 0 .. NT-c-1, tile (c + b, c)): waves 0-3 update
+//   their own tile, rows 16 w each (kt >= 0); waves 4-7 update the diagonal
+//   tile (c, c) and factor it in LDS, 16-wide block column by block column
+//   (every such block does the same arithmetic, so every copy of the factor is
+//   identical).  Then waves 0-3 solve their rows of L_ic = A_ic L_cc^-T block
+//   column by block column: X_y = (A_y - sum_{r<y} X_r L_yr^T) W_yy^T, with
+//   W_yy the inverse of the 16 x 16 diagonal block.  Block 0 (the diagonal
+//   tile) runs the same solve on the identity, which gives L_cc^-1 for the
+//   triangular solves (Dinv[c]); tile (c, c) of S is not written.
+// No block waits for another.
+__global__ __launch_bounds__(512, 4) void k_chol_step(CholArgs g, int kt) {
+    // T: the diagonal tile being factored; Lf: the factor's sub-blocks.  While
+    // the update runs, the same memory holds the tile-column-kt panels.
+    __shared__ __align__(16) double sm[2 * 64 * LDT];
+    double *const T = sm, *const Lf = sm + 64 * LDT;
     const int c = kt + 1;
     const int NT = g.NT;
     const int bid = blockIdx.x;
@@ -606,136 +544,147 @@ __global__ __launch_bounds__(256) void k_chol_step(CholArgs g, int kt) {
         }
         ti = tj + rr;
     }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
-    const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
     double *S = g.S;
     const int64_t ldS = g.ldS;
-    const int64_t rb = (int64_t)ti * 64, cb = (int64_t)tj * 64;
-    const bool colc = tj == c;               // block of column c
-    const bool diag = colc && ti == c;
-    const int64_t db = (int64_t)c * 64;
-    // acc[x][y][v] is tile entry (R0 + 16x + r, C0 + 16y + gq + 4v): the
-    // products below are formed transposed (B^T A^T) so that 16 lanes hold 16
-    // consecutive rows of one column.  dac is the same for tile (c, c).
-    v4d acc[2][2], dac[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
+    const int64_t rb = (int64_t)ti * 64, cb = (int64_t)tj * 64, db = (int64_t)c * 64, kb = (int64_t)kt * 64;
+    // acc[y][v] is tile entry (16 x + r, 16 y + gq + 4 v): products are formed
+    // transposed (D = L_j L_i^T block by block), so that 16 lanes hold 16
+    // consecutive rows of one column.
+    if (tj != c) {
+        const int x = wave & 3, y0 = (wave >> 2) * 2;
+        v4d acc[2];
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                acc[x][y][v] = S[(cb + C0 + 16 * y + gq + 4 * v) * ldS + rb + R0 + 16 * x + r];
-                dac[x][y][v] = (colc && !diag) ? S[(db + C0 + 16 * y + gq + 4 * v) * ldS + db + R0 + 16 * x + r] : 0.0;
-            }
-    if (kt >= 0) {
-        const int64_t kb = (int64_t)kt * 64;
-        double av[16][2], bv[16][2], dv[16][2];
+            for (int v = 0; v < 4; ++v) acc[y][v] = S[(cb + 16 * (y0 + y) + gq + 4 * v) * ldS + rb + 16 * x + r];
+        // four matrix-core k-steps per group, the next group loaded ahead
+        double qa[2][4][2], qb[2][4];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const double *col = S + (kb + 4 * s + gq) * ldS;
-            av[s][0] = -col[rb + R0 + r];
-            av[s][1] = -col[rb + R0 + 16 + r];
-            bv[s][0] = col[cb + C0 + r];
-            bv[s][1] = col[cb + C0 + 16 + r];
-            dv[s][0] = (colc && !diag) ? -col[db + R0 + r] : 0.0;
-            dv[s][1] = (colc && !diag) ? -col[db + R0 + 16 + r] : 0.0;
-        }
+        for (int h = 0; h < 5; ++h) {
+            if (h < 4) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s)
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y) acc[x][y] = mfma16(bv[s][y], av[s][x], acc[x][y]);
-        if (colc && !diag) {
-            // the diagonal tile's update: its columns are those of column c
-#pragma unroll
-            for (int s = 0; s < 16; ++s)
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) dac[x][y] = mfma16(bv[s][y], dv[s][x], dac[x][y]);
-        }
-    }
-    if (!colc) {
-        // trailing tile: store the update
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    S[(cb + C0 + 16 * y + gq + 4 * v) * ldS + rb + R0 + 16 * x + r] = acc[x][y][v];
-        return;
-    }
-    // diagonal tile -> T (row-major, stride 65); own panel tile -> Lc (row-major, stride 64)
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = R0 + 16 * x + r, cl = C0 + 16 * y + gq + 4 * v;
-                if (diag) {
-                    T[row * 65 + cl] = acc[x][y][v];
-                } else {
-                    T[row * 65 + cl] = dac[x][y][v];
-                    Lc[row * 64 + cl] = acc[x][y][v];
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const double *col = S + (kb + 16 * h + 4 * s4 + gq) * ldS;
+                    qb[h & 1][s4] = -col[rb + 16 * x + r];
+                    qa[h & 1][s4][0] = col[cb + 16 * y0 + r];
+                    qa[h & 1][s4][1] = col[cb + 16 * y0 + 16 + r];
                 }
             }
-    __syncthreads();
-    const int qrow = 16 * wave + (lane >> 2), part = lane & 3;
-    double x16[16];
-    if (!diag) {
+            if (h > 0) {
+                const int hb = (h - 1) & 1;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) x16[v] = Lc[qrow * 64 + part * 16 + v];
-    }
-    __syncthreads();
-    if (wave == 0) potrf_wave(T, Lc, g.fail);
-    __syncthreads();
-    if (diag) {
-        // L_cc goes to Dinv[c] (k_chol_inverses inverts it there): the other
-        // blocks of this launch may still be reading tile (c, c) of S
-        double *Dc = g.Dinv + (int64_t)c * 4096;
-        for (int idx = threadIdx.x; idx < 4096; idx += 256) Dc[idx] = Lc[idx];
+                for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) acc[y] = mfma16(qa[hb][s4][y], qb[hb][s4], acc[y]);
+            }
+        }
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) S[(cb + 16 * (y0 + y) + gq + 4 * v) * ldS + rb + 16 * x + r] = acc[y][v];
         return;
     }
-    // strictly lower part of L_cc into T (column by column) and 1 / diagonal
-    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
-        const int q = idx >> 6, pp = idx & 63;
-        const double v = Lc[idx];
-        T[idx] = pp > q ? v : 0.0;
-        if (pp == q) dsh[q] = 1.0 / v;
+    const bool diag = ti == c;
+    const bool own = wave < 4;                 // waves 0-3: own tile; 4-7: tile (c, c)
+    const int x = wave & 3;
+    const int64_t tb = own ? rb : db;          // first row of the tile this wave updates
+    v4d acc[4];
+    if (own && diag) {
+        // block 0, waves 0-3: the identity, whose solve gives L_cc^-1
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[y][v] = (16 * x + r == 16 * y + gq + 4 * v) ? 1.0 : 0.0;
+    } else {
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[y][v] = S[(db + 16 * y + gq + 4 * v) * ldS + tb + 16 * x + r];
+    }
+    if (kt >= 0) {
+        // acc -= L_t,kt L_c,kt^T over the 64 columns of tile column kt.  The
+        // panels L_c,kt (P[0 ..]) and L_i,kt (P[4096 ..]; the same panel again
+        // in block 0) are staged in LDS column by column (P[k*64 + row]) with
+        // 16-byte loads.
+        double *const P = sm;
+        double2 st[8];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int idx = h * 512 + threadIdx.x, pan = idx >> 11, rem = idx & 2047, k = rem >> 5, rp = rem & 31;
+            st[h] = *reinterpret_cast<const double2 *>(S + (kb + k) * ldS + (pan ? rb : db) + 2 * rp);
+        }
+#pragma unroll
+        for (int h = 0; h < 8; ++h)
+            *reinterpret_cast<double2 *>(P + ((h * 512 + threadIdx.x) & 4095) * 2) = st[h];
+        __syncthreads();
+        if (!(own && diag)) {
+            // operands of k-step s4 + 1 are read from LDS while step s4 runs
+            const double *Pb = P + (own ? 4096 : 0) + 16 * x + r + gq * 64;
+            const double *Pa = P + r + gq * 64;
+            double ca[4], cbv = Pb[0], na[4], nb = 0.0;
+#pragma unroll
+            for (int y = 0; y < 4; ++y) ca[y] = Pa[16 * y];
+#pragma unroll
+            for (int s4 = 0; s4 < 16; ++s4) {
+                if (s4 + 1 < 16) {
+                    nb = Pb[(s4 + 1) * 256];
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) na[y] = Pa[(s4 + 1) * 256 + 16 * y];
+                }
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[y] = mfma16(ca[y], -cbv, acc[y]);
+#pragma unroll
+                for (int y = 0; y < 4; ++y) ca[y] = na[y];
+                cbv = nb;
+            }
+        }
+        __syncthreads();
+    }
+    if (!own) {
+        // the updated diagonal tile into T (lower 16 x 16 blocks)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+            if (y <= x)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) T[(16 * x + r) * LDT + 16 * y + gq + 4 * v] = acc[y][v];
     }
     __syncthreads();
-    trsm_quad(x16, T, dsh);
-#pragma unroll
-    for (int v = 0; v < 16; ++v) S[(db + part * 16 + v) * ldS + rb + qrow] = x16[v];
-}
-
-// Inverses of the NT diagonal factor tiles, in place in Dinv (which holds
-// L_tt column by column on entry), one block per tile: row j of I L^-T is
-// column j of L^-1, stored column-major (Dinv[j*64 + i] = L^-1[i][j]).
-__global__ __launch_bounds__(256) void k_chol_inverses(CholArgs g) {
-    __shared__ __align__(16) double Lz[64 * 64];
-    __shared__ double dsh[64];
-    const int t = blockIdx.x;
-    const double *Lt = g.Dinv + (int64_t)t * 4096;
-    for (int idx = threadIdx.x; idx < 4096; idx += 256) {
-        const int q = idx >> 6, pp = idx & 63;
-        const double v = Lt[idx];
-        Lz[idx] = pp > q ? v : 0.0;
-        if (pp == q) dsh[q] = 1.0 / v;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        if (wave == 4 + j) potrf_inv16(T, Lf, j, g.fail);
+        __syncthreads();
+        if (!own && x > j) inner_update(T, Lf, j, x);
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row = 16 * wave + (lane >> 2), part = lane & 3;
-    double x[16];
+    if (!own) return;
+    v4d X[4];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) x[v] = (part * 16 + v == row) ? 1.0 : 0.0;
-    trsm_quad(x, Lz, dsh);
-    double *D = g.Dinv + (int64_t)t * 4096 + row * 64 + part * 16;
+    for (int y = 0; y < 4; ++y) {
+        v4d t = acc[y];
 #pragma unroll
-    for (int v = 0; v < 16; v += 2) *reinterpret_cast<double2 *>(D + v) = make_double2(x[v], x[v + 1]);
+        for (int rr = 0; rr < y; ++rr)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) t = mfma16(-Lf[(16 * y + r) * LDT + 16 * rr + 4 * s + gq], X[rr][s], t);
+        v4d z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) z = mfma16(Lf[(16 * y + r) * LDT + 16 * y + 4 * s + gq], t[s], z);
+        X[y] = z;
+    }
+    if (diag) {
+        // X = L_cc^-T: Dinv[c] holds L_cc^-1 column-major, entry (row a, column b) at b * 64 + a
+        double *D = g.Dinv + (int64_t)c * 4096;
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) D[(16 * x + r) * 64 + 16 * y + gq + 4 * v] = X[y][v];
+        return;
+    }
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[(db + 16 * y + gq + 4 * v) * ldS + rb + 16 * x + r] = X[y][v];
 }
 
 // ------------------------------------------------------------- triangular solves
@@ -946,10 +895,8 @@ hipError_t launch_cholesky(const CholArgs &g, hipStream_t st) {
         const int c = kt + 1;
         const int R = NT - c - 1;
         const int64_t blocks = (int64_t)(NT - c) + (kt >= 0 ? (int64_t)R * (R + 1) / 2 : 0);
-        hipLaunchKernelGGL(k_chol_step, dim3((unsigned)blocks), dim3(256), 0, st, g, kt);
+        hipLaunchKernelGGL(k_chol_step, dim3((unsigned)blocks), dim3(512), 0, st, g, kt);
     }
-    if (NT == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chol_inverses, dim3((unsigned)NT), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
