@@ -261,8 +261,15 @@ nmf_status nmf_batch_create_static(nmf_ctx *const *ctxs, int32_t count, void *hi
  * or nmf_append_columns) and drops any captured graph. */
 nmf_status nmf_batch_refresh(nmf_batch *b);
 
-/* Enqueues `sweeps` stage-1 sweeps of every problem.  use_graph = 1 captures
- * the sweeps into a HIP graph on first use (per sweep count) and replays it. */
+/* Enqueues `sweeps` stage-1 sweeps of every problem.  Problems of one rank k
+ * (a K-group) share flattened launches; a batch made by nmf_batch_create()
+ * runs its K-groups concurrently, each on a side stream of its own (default
+ * priority) forked from and joined back to the batch's stream by events, so
+ * work enqueued on the batch's stream afterwards still sees every sweep.
+ * use_graph = 1 captures the sweeps into a HIP graph on first use (per sweep
+ * count; the K-groups become parallel branches) and replays it.  Batches made
+ * by nmf_batch_create_static() run their K-groups one after another on the
+ * batch's stream. */
 nmf_status nmf_batch_anls_step(nmf_batch *b, int32_t sweeps, int32_t use_graph);
 
 /* Waits for the batch's stream, then copies every context's stage-1 state

@@ -776,8 +776,43 @@ struct nmf_batch {
     int graph_sweeps = 0;
     std::vector<int> order;       // table position -> index in ctxs
     long long *poll = nullptr;    // device: [count][2] converged, sweeps
+    // K-groups are independent problems: with side streams, each group's
+    // sweeps run on a stream of their own, forked from and joined back to
+    // `stream` by events (also inside a captured graph, as parallel branches)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;   // [0]: fork, [1 + s]: join of side stream s
     std::string err;
 };
+
+static void drop_side_streams(nmf_batch *b) {
+    for (hipStream_t s : b->side) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    b->side.clear();
+    b->ev.clear();
+}
+
+// One side stream per K-group, at most kMaxSideStreams (default priority).
+constexpr int kMaxSideStreams = 8;
+static hipError_t make_side_streams(nmf_batch *b) {
+    const int ns = std::min((int)b->groups.size(), kMaxSideStreams);
+    if (ns < 2) return hipSuccess;
+    for (int q = 0; q <= ns; ++q) {
+        hipEvent_t e = nullptr;
+        const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) return r;
+        b->ev.push_back(e);
+    }
+    for (int q = 0; q < ns; ++q) {
+        hipStream_t st = nullptr;
+        const hipError_t r = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (r != hipSuccess) return r;
+        b->side.push_back(st);
+    }
+    return hipSuccess;
+}
 
 // Offset tables: NBK arrays of (members + 1) entries per group, at most
 // NBK * 2 * count entries over all groups (a group has at least one member).
@@ -896,8 +931,8 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
     return NMF_OK;
 }
 
-nmf_status nmf_batch_create(nmf_ctx *const *ctxs, int32_t count, void *ws, size_t ws_bytes, void *stream,
-                            nmf_batch **out) {
+static nmf_status batch_create(nmf_ctx *const *ctxs, int32_t count, void *ws, size_t ws_bytes, void *stream,
+                               bool concurrent, nmf_batch **out) {
     if (!out || !ctxs || count < 1) return fail(nullptr, NMF_EINVAL, "bad batch arguments");
     *out = nullptr;
     if (!ws || ws_bytes < batch_bytes(count)) return fail(nullptr, NMF_ENOMEM, "batch workspace too small");
@@ -920,8 +955,21 @@ nmf_status nmf_batch_create(nmf_ctx *const *ctxs, int32_t count, void *ws, size_
         delete b;
         return st;
     }
+    if (concurrent) {
+        const hipError_t e = make_side_streams(b);
+        if (e != hipSuccess) {
+            drop_side_streams(b);
+            delete b;
+            return hip_fail(nullptr, e, "side streams of the batch");
+        }
+    }
     *out = b;
     return NMF_OK;
+}
+
+nmf_status nmf_batch_create(nmf_ctx *const *ctxs, int32_t count, void *ws, size_t ws_bytes, void *stream,
+                            nmf_batch **out) {
+    return batch_create(ctxs, count, ws, ws_bytes, stream, true, out);
 }
 
 nmf_status nmf_batch_create_static(nmf_ctx *const *ctxs, int32_t count, void *stream, nmf_batch **out) {
@@ -934,16 +982,43 @@ nmf_status nmf_batch_create_static(nmf_ctx *const *ctxs, int32_t count, void *st
     void *ws = nullptr;
     const hipError_t e = static_scratch(&ws);
     if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress of the static batch tables");
-    return nmf_batch_create(ctxs, count, ws, kStaticBatchBytes, stream, out);
+    return batch_create(ctxs, count, ws, kStaticBatchBytes, stream, false, out);
 }
 
 static nmf_status batch_enqueue(nmf_batch *b, int sweeps) {
+    const int ns = (int)b->side.size();
+    if (ns == 0) {
+        for (int t = 0; t < sweeps; ++t)
+            for (auto &g : b->groups)
+                if (nmfk::launch_batch_sweep(g.K, g.prec, g.g, b->stream) != hipSuccess) {
+                    b->err = "batched launch failed";
+                    return NMF_EDEVICE;
+                }
+        return NMF_OK;
+    }
+    if (hipEventRecord(b->ev[0], b->stream) != hipSuccess) {
+        b->err = "batch fork event failed";
+        return NMF_EDEVICE;
+    }
+    for (int q = 0; q < ns; ++q)
+        if (hipStreamWaitEvent(b->side[q], b->ev[0], 0) != hipSuccess) {
+            b->err = "batch fork wait failed";
+            return NMF_EDEVICE;
+        }
     for (int t = 0; t < sweeps; ++t)
-        for (auto &g : b->groups)
-            if (nmfk::launch_batch_sweep(g.K, g.prec, g.g, b->stream) != hipSuccess) {
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            auto &g = b->groups[gi];
+            if (nmfk::launch_batch_sweep(g.K, g.prec, g.g, b->side[gi % ns]) != hipSuccess) {
                 b->err = "batched launch failed";
                 return NMF_EDEVICE;
             }
+        }
+    for (int q = 0; q < ns; ++q)
+        if (hipEventRecord(b->ev[1 + q], b->side[q]) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->ev[1 + q], 0) != hipSuccess) {
+            b->err = "batch join failed";
+            return NMF_EDEVICE;
+        }
     return NMF_OK;
 }
 
@@ -1007,6 +1082,7 @@ nmf_status nmf_batch_sync(nmf_batch *b) {
 nmf_status nmf_batch_destroy(nmf_batch *b) {
     if (!b) return NMF_OK;
     drop_graph(b);
+    drop_side_streams(b);
     delete b;
     return NMF_OK;
 }
