@@ -396,6 +396,40 @@ def batching_section(count, sweeps):
             "speedup": plain_ms / batch_ms, "autotuned_waves": waves}
 
 
+def grouping_section(ranks=(5, 10, 16), n=3000, m=500, warm=200, steps=50, cold=8):
+    """Passive-set-grouped first solves (Sec. II grouping) against the
+    per-problem loop: ms per sweep in the steady state (after `warm` sweeps,
+    stable warm-start sets) and over the first `cold` sweeps from X0 = 0
+    (sets churn)."""
+    import numpy as np
+    import torch
+    from paper_2101_08431_amd import synth
+    rows = []
+    for k in ranks:
+        M, X0, Y0 = synth.make(dict(kind="pdf", n=n, m=m, k=k, sigma=1e-3, sigma_relative=True), 0)
+        row = {"n": n, "m": m, "k": k}
+        for grouped in (0, 1):
+            tag = "grouped" if grouped else "per_problem"
+            ctx = make_ctx(M, X0, Y0, k)
+            ctx.set_nnls_grouping(grouped)
+            row[f"{tag}_warm_ms_per_sweep"] = time_eager_sweeps(ctx, steps, warm)
+            if grouped:
+                xm, ym = ctx.masks()
+                row["distinct_sets_x"] = int(np.unique(xm).size)
+                row["distinct_sets_y"] = int(np.unique(ym).size)
+            ctx.close()
+            ctx = make_ctx(M, np.zeros_like(X0), Y0, k)
+            ctx.set_nnls_grouping(grouped)
+            torch.cuda.synchronize()
+            row[f"{tag}_cold_ms_per_sweep"] = time_eager_sweeps(ctx, cold, 0)
+            ctx.close()
+        row["warm_speedup"] = row["per_problem_warm_ms_per_sweep"] / row["grouped_warm_ms_per_sweep"]
+        row["cold_speedup"] = row["per_problem_cold_ms_per_sweep"] / row["grouped_cold_ms_per_sweep"]
+        log(f"grouping k={k}: {row}")
+        rows.append(row)
+    return {"workload": f"pdf_{n}x{m}, ranks {list(ranks)}", "rows": rows}
+
+
 def serving_section(seconds, rate=200.0, warm=1.0, plain=True):
     """64 streams (13 at n = 8000, k = 8, the rest n = 2000, k = 4), each
     starting at m = 64; Poisson arrivals at `rate`/s, each appending 16 columns
@@ -462,6 +496,8 @@ def main():
                     help="only time stage-2 iterations on the headline workload (for profiling)")
     ap.add_argument("--batching-only", action="store_true",
                     help="only run the batching section (256 problems, for profiling)")
+    ap.add_argument("--grouping-only", action="store_true",
+                    help="only run the passive-set grouping section")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -487,6 +523,9 @@ def main():
         return
     if args.batching_only:
         print(json.dumps(batching_section(256, 20)), flush=True)
+        return
+    if args.grouping_only:
+        print(json.dumps(grouping_section()), flush=True)
         return
     M, X0, Y0 = synth.make(args.workload, 0)
     n, m = M.shape
@@ -547,6 +586,7 @@ def main():
         out["precision"] = precision_section(200)
         log("batching section")
         out["batching"] = batching_section(256, 10)
+        out["grouping"] = grouping_section()
     if not args.no_serve:
         log("serving section")
         out["serving"] = serving_section(args.serve_seconds)

@@ -214,6 +214,20 @@ nmf_status nmf_set_launch_fusion(nmf_ctx *ctx, int32_t fuse_x, int32_t fuse_y);
  * caller. */
 nmf_status nmf_get_launch_shape(const nmf_ctx *ctx, int32_t *out4);
 
+/* Passive-set grouping of the stage-1 NNLS problems (Sec. II cites the
+ * grouping of right-hand sides that share a passive set, so that one
+ * factorisation serves all of them).  on = 1: in every sweep each half first
+ * forms (G_PP)^-1 once for every distinct warm-start passive set P of its
+ * problems (at most 2048 sets for k >= 12; problems past that take the plain
+ * loop), and each problem tries z = (G_PP)^-1 b, the first solve of its
+ * warm-started Lawson-Hanson loop; it keeps z when z > 0 on P and the loop's
+ * optimality test passes, and otherwise runs the loop from the same start.
+ * The results are those of on = 0 up to the rounding of that solve.  The
+ * halves then run as separate stream and solve kernels (no one-kernel
+ * halves).  on = 0 (the default) restores the per-problem loop.  Errors:
+ * NMF_EINVAL. */
+nmf_status nmf_set_nnls_grouping(nmf_ctx *ctx, int32_t on);
+
 /* Sets the stage-1 sweep budget (options.max_anls_sweeps, >= 1) used from now
  * on, and re-arms the stop rule of Sec. IV: the next sweeps run until it holds
  * again or `max_sweeps` more sweeps are done.  Every later

@@ -75,6 +75,95 @@ struct MElem<NMF_GRAM_BF16X2> {
     }
 };
 
+// Lane `src`'s value of v in every lane (one pivot or column entry of a
+// lane-per-row factorisation).
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// ---------------------------------------------------------------- grouped first solves
+// Passive-set grouping (the grouping of right-hand sides that share a passive
+// set, cited in Sec. II): the problems of one half whose warm-start passive
+// set P is the same share one factorisation of G_PP.  Per half and sweep,
+// every problem marks its set (k_gmark), one block numbers the distinct sets
+// (k_gnumber) and one wave per set forms (G_PP)^-1 (k_ginverse).  A problem
+// then first tries z = (G_PP)^-1 b, the first solve of the warm-started
+// Lawson-Hanson loop, and keeps it when z is positive on P and the dual
+// vector passes the loop's optimality test; otherwise it runs the loop as
+// before, from the same start.  The minimiser is the loop's (it is unique),
+// up to the rounding of the solve.
+template <int K>
+__device__ __forceinline__ bool grouped_try(const AnlsParams &p, const double *G, double gmax, const double (&b)[K],
+                                            const double (&x0)[K], uint32_t old_mask, double (&xn)[K]) {
+    uint32_t barred = 0, P = 0;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        if (!(G[a * K + a] > 1e-14 * gmax)) barred |= 1u << a;
+        else if (x0[a] > 0.0) P |= 1u << a;
+    }
+    if (P != old_mask) return false;
+    const int slot = p.gslot[P];
+    if (slot < 0) return false;
+    const double *T = p.gtab + (int64_t)slot * (K * K);
+    double z[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < K; ++c) v = fma(T[a * K + c], b[c], v);
+        z[a] = ((P >> a) & 1u) ? v : 0.0;
+    }
+    bool feas = true;
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+        if (((P >> a) & 1u) && !(z[a] > 0.0)) feas = false;
+    if (!feas) return false;
+    // the optimality test of the loop, at x = z
+    double tol = 0.0, wj = 0.0;
+    int j = -1;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+        double v = b[a], s = fabs(b[a]);
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            v -= G[a * K + c] * z[c];
+            s += fabs(G[a * K + c]) * z[c];
+        }
+        tol = s > tol ? s : tol;
+        if (!(((P | barred) >> a) & 1u)) {
+            if (j < 0 || v > wj) { j = a; wj = v; }
+        }
+    }
+    tol *= 10.0 * K * 2.220446049250313e-16;
+    if (j >= 0 && wj > tol) return false;
+#pragma unroll
+    for (int a = 0; a < K; ++a) xn[a] = z[a];
+    return true;
+}
+
+// The warm-started solve of one problem, grouped first when the half has a
+// table this sweep.
+template <int K>
+__device__ __forceinline__ LhResult solve_warm(const AnlsParams &p, const double *G, double gmax,
+                                               const double (&b)[K], uint32_t old_mask, double (&xn)[K]) {
+    if (p.grouped) {
+        double x0[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) x0[a] = xn[a];
+        if (grouped_try<K>(p, G, gmax, b, x0, old_mask, xn)) {
+            LhResult r;
+            r.P = old_mask;
+            r.solves = 1;
+            r.status = 0;
+            return r;
+        }
+    }
+    return lh_warm<K>(G, gmax, b, xn);
+}
+
 // Row i of the X-half: the gradient statistics at the previous row x (E(.;0)
 // parts), and in mode 0 the warm-started solve, stored to X and the mask.
 // b is row i of B_X = M Y^T, G is G_Y in LDS.  xn receives the new row (zeros
@@ -101,7 +190,7 @@ __device__ __forceinline__ void x_row(const AnlsParams &p, const double *G, int6
             xn[a] = x[a];
             st[ST_NORM2] += x[a] * x[a];
         }
-        const LhResult r = lh_warm<K>(G, gmax, b, xn);
+        const LhResult r = solve_warm<K>(p, G, gmax, b, old_mask, xn);
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             const double d = xn[a] - x[a];
@@ -130,7 +219,7 @@ __device__ __forceinline__ void y_col(const AnlsParams &p, const double *G, int6
         yn[a] = y[a];
         st[ST_NORM2] += y[a] * y[a];
     }
-    const LhResult r = lh_warm<K>(G, gmax, b, yn);
+    const LhResult r = solve_warm<K>(p, G, gmax, b, old_mask, yn);
 #pragma unroll
     for (int a = 0; a < K; ++a) {
         const double d = yn[a] - y[a];
@@ -1009,6 +1098,105 @@ __global__ void k_batch_poll(const AnlsParams *table, int count, long long *out)
     out[2 * q + 1] = st->sweeps;
 }
 
+// ---------------------------------------------------------------- tables of the grouped solves
+// Marks the warm-start passive set of every problem of the half.
+__global__ __launch_bounds__(256) void k_gmark(AnlsParams p, int yhalf) {
+    if (sweep_stopped(p)) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (yhalf ? p.m : p.n)) return;
+    p.gpresent[yhalf ? p.ymask[i] : p.xmask[i]] = 1;
+}
+
+// Numbers the marked sets in increasing order (one block), records each
+// set's slot, and clears the marks for the next half.
+__global__ __launch_bounds__(1024) void k_gnumber(AnlsParams p, int K) {
+    __shared__ int cnt[1024];
+    if (sweep_stopped(p)) return;
+    const int NM = 1 << K, per = (NM + 1023) / 1024;
+    const int m0 = min((int)threadIdx.x * per, NM), m1 = min(m0 + per, NM);
+    int c = 0;
+    for (int q = m0; q < m1; ++q) c += p.gpresent[q] ? 1 : 0;
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = (int)threadIdx.x >= off ? cnt[threadIdx.x - off] : 0;
+        __syncthreads();
+        cnt[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int slot = cnt[threadIdx.x] - c;
+    for (int q = m0; q < m1; ++q) {
+        if (p.gpresent[q]) {
+            if (slot < p.gcap) {
+                p.gslot[q] = slot;
+                p.gmask[slot] = (uint32_t)q;
+            } else {
+                p.gslot[q] = -1;
+            }
+            ++slot;
+            p.gpresent[q] = 0;
+        }
+    }
+    if (threadIdx.x == 1023) *p.gcount = min(cnt[1023], p.gcap);
+}
+
+// (G_PP)^-1 for each numbered set, one wave per set.  G is summed from the
+// half's records exactly as the solve kernel sums it.  The matrix that is
+// factored is G on P x P and the identity elsewhere; lane r < K holds row r of
+// the factor (right-looking, one pivot broadcast per step) and, in the same
+// steps, column r of W = L^-1; the inverse is W^T W, kept on P x P.
+template <int K>
+__global__ __launch_bounds__(nnls_threads(K)) void k_ginverse(AnlsParams p, int yhalf) {
+    constexpr int NT = nnls_threads(K);
+    __shared__ double G[K * K];
+    __shared__ double lds[NT];
+    if (sweep_stopped(p)) return;
+    const int count = *p.gcount;
+    const int slot0 = blockIdx.x * (NT / 64);
+    if (slot0 >= count) return;
+    const double gacc = yhalf ? records_partial(p.gx_part, p.Rx, K * K, (int)threadIdx.x, NT)
+                              : records_partial(p.gy_part, p.Ry, K * K, (int)threadIdx.x, NT);
+    records_finish(gacc, K * K, 0, NT, G, lds);
+    const int slot = slot0 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (slot >= count) return;
+    const uint32_t P = p.gmask[slot];
+    const int r = lane < K ? lane : K - 1;
+    const bool pr = (P >> r) & 1u;
+    double a[K], w[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        a[c] = (pr && ((P >> c) & 1u)) ? G[r * K + c] : (r == c ? 1.0 : 0.0);
+        w[c] = (c == r) ? 1.0 : 0.0;
+    }
+    double dmin = 1.0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const double d = lane_bcast(a[c], c);
+        dmin = fmin(dmin, d);
+        const double s = rsqrt_newton(d > 0.0 ? d : 1.0);
+        const double l = a[c] * s;
+        a[c] = l;
+        w[c] *= s;
+#pragma unroll
+        for (int jj = c + 1; jj < K; ++jj) {
+            const double ljc = lane_bcast(l, jj);
+            a[jj] = fma(-l, ljc, a[jj]);
+            w[jj] = fma(-ljc, w[c], w[jj]);
+            asm volatile("" : "+v"(w[jj]));
+        }
+    }
+    const bool bad = !(dmin > 0.0);
+    double *T = p.gtab + (int64_t)slot * (K * K);
+#pragma unroll
+    for (int bcol = 0; bcol < K; ++bcol) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) v = fma(w[q], lane_bcast(w[q], bcol), v);
+        if (lane < K)
+            T[r * K + bcol] = bad ? __builtin_nan("") : ((pr && ((P >> bcol) & 1u)) ? v : 0.0);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 #define NMF_K_SWITCH(K, CALL)                                                        \
     switch (K) {                                                                     \
@@ -1056,8 +1244,23 @@ hipError_t launch_xstream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t 
     return hipGetLastError();
 }
 
+hipError_t launch_group_table(int K, const AnlsParams &p, int yhalf, hipStream_t s) {
+    if (K < 1 || K > KMAX) return hipErrorInvalidValue;
+    const int64_t cnt = yhalf ? p.m : p.n;
+    hipLaunchKernelGGL(k_gmark, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, yhalf);
+    hipLaunchKernelGGL(k_gnumber, dim3(1), dim3(1024), 0, s, p, K);
+    const int per = nnls_threads(K) / 64;
+    const unsigned blocks = (unsigned)((p.gcap + per - 1) / per);
+    NMF_K_SWITCH(K, hipLaunchKernelGGL(k_ginverse<KK>, dim3(blocks), dim3(nnls_threads(KK)), 0, s, p, yhalf));
+    return hipGetLastError();
+}
+
 hipError_t launch_xnnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (p.fx) return hipSuccess;   // solved inside k_xfused
+    if (p.grouped && p.mode == 0) {
+        const hipError_t e = launch_group_table(K, p, 0, s);
+        if (e != hipSuccess) return e;
+    }
     NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_xnnls<KK>, dim3(p.Nx), dim3(nnls_threads(KK)), 0, s, e0, e1, 0, p));
     return hipGetLastError();
 }
@@ -1087,6 +1290,10 @@ hipError_t launch_ystream(int K, const AnlsParams &p, hipStream_t s, hipEvent_t 
 
 hipError_t launch_ynnls(int K, const AnlsParams &p, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (p.fy) return hipSuccess;   // solved inside k_yfused
+    if (p.grouped) {
+        const hipError_t e = launch_group_table(K, p, 1, s);
+        if (e != hipSuccess) return e;
+    }
     NMF_K_SWITCH(K, hipExtLaunchKernelGGL(k_ynnls<KK>, dim3(p.Ny), dim3(nnls_threads(KK)), 0, s, e0, e1, 0, p));
     return hipGetLastError();
 }

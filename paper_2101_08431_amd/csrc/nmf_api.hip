@@ -89,8 +89,13 @@ struct Carve {
 
 struct Offsets {
     size_t M, Mlo, X, Y, xmask, ymask, bx, by, gx, gy, xst, yst, cntf, tcnt, status, red, io, bad;
+    size_t gpres, gslot, gmask, gcount, gtab;   // tables of the grouped first solves
     size_t ipm_base, total;
 };
+
+// Slots of the grouped-solve table: every passive set for small K, else
+// the first 2048 distinct sets of a half (later ones take the plain loop).
+constexpr int64_t group_slots(int K) { return K <= 11 ? (int64_t)1 << K : 2048; }
 
 Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
     const Plan P = plan_shape(n, m_cap, m_cap, K, o.x_splits, o.y_splits);
@@ -121,6 +126,12 @@ Offsets layout(int64_t n, int64_t m_cap, int K, const nmf_options &o) {
     L.red = c.take<double>(2 * kRedBlocks);
     L.io = c.take<double>((size_t)K * (n + m_cap));
     L.bad = c.take<unsigned>(4);
+    const int64_t gcap = group_slots(K);
+    L.gpres = c.take<uint8_t>((size_t)1 << K);
+    L.gslot = c.take<int>((size_t)1 << K);
+    L.gmask = c.take<uint32_t>((size_t)gcap);
+    L.gcount = c.take<int>(1);
+    L.gtab = c.take<double>((size_t)gcap * K * K);
     L.ipm_base = align_up(c.off, 256);
     size_t ipm = o.with_ipm ? nmfk::ipm_workspace_bytes(n, m_cap, K) : 0;
     L.total = L.ipm_base + ipm;
@@ -143,6 +154,7 @@ struct nmf_ctx {
     unsigned *bad = nullptr;
     int stage = 1;
     int fuse_x = -1, fuse_y = -1;   // nmf_set_launch_fusion
+    int grouped = 0;                // nmf_set_nnls_grouping
     double mnorm2 = 0.0;
     double ms1 = 0.0, ms2 = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -168,7 +180,9 @@ static nmf_status hip_fail(nmf_ctx *c, hipError_t e, const char *what) {
     } while (0)
 
 static void refresh_shape(nmf_ctx *c) {
-    c->plan = plan_shape(c->n, c->m, c->m_cap, c->K, c->opt.x_splits, c->opt.y_splits, c->fuse_x, c->fuse_y);
+    // the grouped first solves run in the separate solve kernels
+    c->plan = plan_shape(c->n, c->m, c->m_cap, c->K, c->opt.x_splits, c->opt.y_splits, c->grouped ? 0 : c->fuse_x,
+                         c->grouped ? 0 : c->fuse_y);
     AnlsParams &p = c->p;
     p.n = c->n;
     p.m = c->m;
@@ -312,6 +326,12 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
     p.cnt_fin = (unsigned *)(w + L.cntf);
     p.tile_cnt = (unsigned *)(w + L.tcnt);
     p.st = (DevStatus *)(w + L.status);
+    p.gcap = (int)group_slots(k);
+    p.gpresent = (uint8_t *)(w + L.gpres);
+    p.gslot = (int *)(w + L.gslot);
+    p.gmask = (uint32_t *)(w + L.gmask);
+    p.gcount = (int *)(w + L.gcount);
+    p.gtab = (double *)(w + L.gtab);
     c->red = (double *)(w + L.red);
     c->io = (double *)(w + L.io);
     c->bad = (unsigned *)(w + L.bad);
@@ -340,6 +360,7 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
     // small regions start at zero (counters must be zero before the first sweep)
     CHK(hipMemsetAsync(w + L.bx, 0, L.io - L.bx, s));
     CHK(hipMemsetAsync(w + L.X, 0, L.bx - L.X, s));
+    CHK(hipMemsetAsync(w + L.gpres, 0, (size_t)1 << k, s));   // no passive set marked
     CHK(hipMemcpy2DAsync((void *)p.M, (size_t)p.ldM * 8, M, (size_t)ldm * 8, (size_t)n * 8, (size_t)m,
                          hipMemcpyDefault, s));
     CHK(nmfk::launch_check_finite(p.M, n, m, p.ldM, c->red, kRedBlocks, s));
@@ -596,6 +617,21 @@ nmf_status nmf_set_launch_fusion(nmf_ctx *c, int32_t fuse_x, int32_t fuse_y) {
     if (fuse_x < -1 || fuse_x > 1 || fuse_y < -1 || fuse_y > 1) return fail(c, NMF_EINVAL, "fusion mode not -1, 0 or 1");
     c->fuse_x = fuse_x;
     c->fuse_y = fuse_y;
+    refresh_shape(c);
+    if (c->stage == 1) {
+        // the Gram records follow the kernel split of each half: rebuild them
+        HIPCHK(c, nmfk::launch_gram_x_init(c->K, c->p, c->stream));
+        HIPCHK(c, nmfk::launch_gram_y_init(c->K, c->p, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_set_nnls_grouping(nmf_ctx *c, int32_t on) {
+    if (!c) return NMF_EINVAL;
+    if (on != 0 && on != 1) return fail(c, NMF_EINVAL, "grouping not 0 or 1");
+    c->grouped = on;
+    c->p.grouped = on;
     refresh_shape(c);
     if (c->stage == 1) {
         // the Gram records follow the kernel split of each half: rebuild them
@@ -903,6 +939,7 @@ nmf_status nmf_batch_refresh(nmf_batch *b) {
         for (int q : g.members) {
             AnlsParams p = b->ctxs[q]->p;
             p.mode = 0;
+            p.grouped = 0;   // the batched sweeps build no grouping tables
             tab.push_back(p);
             b->order.push_back(q);
             g.g.single = p;

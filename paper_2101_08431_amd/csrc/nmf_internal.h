@@ -77,6 +77,14 @@ struct AnlsParams {
                        // and Tm when the half is one kernel
     unsigned *tile_cnt; // [Tn + Tm_max] arrival counters of the one-kernel halves' tiles
     int mode;          // X: 0 = solve, 1 = measure E only; Y: 0 = sweep, 2 = appended columns
+    // passive-set grouping of the first solve (nmf_set_nnls_grouping)
+    int grouped;       // 1: the NNLS kernels try the table of their half first
+    int gcap;          // slots of the table: min(2^K, 2048)
+    uint8_t *gpresent; // [2^K] sets present in this half (cleared by k_gnumber)
+    int *gslot;        // [2^K] slot of each present set, -1 past gcap
+    uint32_t *gmask;   // [gcap] set of each slot
+    int *gcount;       // slots in use
+    double *gtab;      // [gcap][K][K] (G_PP)^-1, zero outside P x P (NaN if G_PP broke down)
 };
 
 // Launchers (anls.hip).  All enqueue on `s` and return hipSuccess or an error.
@@ -108,6 +116,10 @@ hipError_t launch_make_lowprec(const AnlsParams &p, int64_t j0, int64_t j1, hipS
 hipError_t launch_rearm(DevStatus *st, int budget, hipStream_t s);
 // out[2q] = converged, out[2q+1] = sweeps of the problem of table[q], q < count.
 hipError_t launch_batch_poll(const AnlsParams *table, int count, long long *out, hipStream_t s);
+// The table of the grouped first solves of one half (yhalf 0: X, 1: Y),
+// enqueued by launch_xnnls / launch_ynnls before the solve kernel when
+// p.grouped is set.
+hipError_t launch_group_table(int K, const AnlsParams &p, int yhalf, hipStream_t s);
 hipError_t launch_copy_columns_warm(int K, const AnlsParams &p, int64_t j_from, int64_t j0,
                                     int64_t j1, hipStream_t s);
 
