@@ -156,7 +156,7 @@ def roofline(ctx, n, m, k, shape, workload, sweeps=100):
             "sweep": {"bytes": sweep_bytes, "ms": sweep_ms, "achieved": sweep_gbs, "frac": sweep_gbs / HBM_PEAK_GBS}}
 
 
-def full_solve(name, seeds, tol, cap):
+def full_solve(name, seeds, tol, cap, mixed=0):
     import torch
     from paper_2101_08431_amd import NMF, default_options, synth
     from paper_2101_08431_amd._lib import NMFError
@@ -164,6 +164,7 @@ def full_solve(name, seeds, tol, cap):
     for seed in seeds:
         M, X0, Y0 = synth.make(name, seed)
         ctx = NMF(M, X0.shape[1], X0, Y0, options=default_options(eps_tol=tol, max_ipm_iters=cap))
+        ctx.set_ipm_precision(mixed, 2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         note = None
@@ -186,7 +187,7 @@ def full_solve(name, seeds, tol, cap):
         ctx.close()
     import statistics
     conv = [r["ms"] for r in out if r["converged"]]
-    return {"workload": name, "tol": tol, "ipm_cap": cap, "runs": out,
+    return {"workload": name, "tol": tol, "ipm_cap": cap, "mixed_precision": mixed, "runs": out,
             "converged": f"{len(conv)}/{len(out)}",
             "median_ms_converged": statistics.median(conv) if conv else None,
             "max_ms_converged": max(conv) if conv else None}
@@ -195,7 +196,7 @@ def full_solve(name, seeds, tol, cap):
 FP64_PEAK_TFS = 78.6
 
 
-def ipm_section(name="pdf_3000x500_k5", seed=1, iters=10, sweeps=300):
+def ipm_section(name="pdf_3000x500_k5", seed=1, iters=10, sweeps=300, mixed=0):
     """Stage-2 timing (Alg. 3 inner iterations: direction, line search,
     update): the seed's problem after `sweeps` stage-1 sweeps, the transition
     and one iteration untimed, then `iters` iterations with the dense steps
@@ -209,6 +210,7 @@ def ipm_section(name="pdf_3000x500_k5", seed=1, iters=10, sweeps=300):
     n, m = M.shape
     k = X0.shape[1]
     ctx = NMF(M, k, X0, Y0, options=default_options(eps_tol=1e-8, eps_stol=-1.0, max_anls_sweeps=1 << 30))
+    ctx.set_ipm_precision(mixed, 2)
     ctx.anls_step(sweeps, report=False)
     ctx.ipm_step(1)
     st, ms, cnt = ctx.ipm_profile(iters)
@@ -225,7 +227,7 @@ def ipm_section(name="pdf_3000x500_k5", seed=1, iters=10, sweeps=300):
     ex_flop = (N * (N + 1) // 2) * n * k * 2            # sum_i V_i^T V_i, lower triangle
     def tfs(f, t):
         return f / (t * 1e-3) / 1e12 if t > 0 else None
-    out = {"workload": name, "seed": seed, "stage1_sweeps": sweeps, "iterations": iters,
+    out = {"workload": name, "seed": seed, "stage1_sweeps": sweeps, "iterations": iters, "mixed_precision": mixed,
            "ms_per_iteration": wall, "ms_per_iteration_profiled": ms[4], "schur_order": N,
            "E0_after": rep["E0"],
            "dense_steps_ms": {"gauss_newton_schur": ms[0], "exact_schur": ms[1], "cholesky": ms[2],
@@ -242,9 +244,23 @@ def ipm_section(name="pdf_3000x500_k5", seed=1, iters=10, sweeps=300):
                      "frac": (tfs(chol_flop, ms[2]) or 0.0) / FP64_PEAK_TFS},
     }
     if cnt[1]:
+        # the FP32 form runs on FP32 matrix cores (157.3 TFLOP/s dense)
+        pk = 157.3 if mixed else FP64_PEAK_TFS
         out["roofline"]["exact_schur"] = {"kernel": "k_schur_exact (+ k_linv, k_residual_rows)", "bound": "mfma",
-                                          "achieved": tfs(ex_flop, ms[1]), "peak": FP64_PEAK_TFS,
-                                          "unit": "TFLOP/s", "frac": (tfs(ex_flop, ms[1]) or 0.0) / FP64_PEAK_TFS}
+                                          "dtype": "f32" if mixed else "f64",
+                                          "achieved": tfs(ex_flop, ms[1]), "peak": pk,
+                                          "unit": "TFLOP/s", "frac": (tfs(ex_flop, ms[1]) or 0.0) / pk}
+    return out
+
+
+def mixed_section():
+    """Mixed-precision interior point (exact-Hessian Schur formation on FP32
+    matrix cores, FP64 refinement): the profiled iterations of ipm_section in
+    both precisions, and full solves to E(.;0) <= 1e-8 of seed 0 (few
+    exact-Hessian steps) and seed 7 (mostly exact-Hessian steps) in both."""
+    out = {"ipm_fp64": ipm_section(mixed=0), "ipm_mixed": ipm_section(mixed=1)}
+    for mixed in (0, 1):
+        out[f"solve_{'mixed' if mixed else 'fp64'}"] = full_solve("pdf_3000x500_k5", (0, 7), 1e-8, 5000, mixed)
     return out
 
 
@@ -498,6 +514,8 @@ def main():
                     help="only run the batching section (256 problems, for profiling)")
     ap.add_argument("--grouping-only", action="store_true",
                     help="only run the passive-set grouping section")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only run the mixed-precision interior-point section")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -526,6 +544,9 @@ def main():
         return
     if args.grouping_only:
         print(json.dumps(grouping_section()), flush=True)
+        return
+    if args.mixed_only:
+        print(json.dumps(mixed_section()), flush=True)
         return
     M, X0, Y0 = synth.make(args.workload, 0)
     n, m = M.shape
@@ -587,6 +608,7 @@ def main():
         log("batching section")
         out["batching"] = batching_section(256, 10)
         out["grouping"] = grouping_section()
+        out["mixed_precision"] = mixed_section()
     if not args.no_serve:
         log("serving section")
         out["serving"] = serving_section(args.serve_seconds)

@@ -228,6 +228,18 @@ nmf_status nmf_get_launch_shape(const nmf_ctx *ctx, int32_t *out4);
  * NMF_EINVAL. */
 nmf_status nmf_set_nnls_grouping(nmf_ctx *ctx, int32_t on);
 
+/* Mixed-precision interior point (the dense Schur algebra is the cost that
+ * Sec. III-B says grows with m).  mixed = 1: the exact-Hessian Schur
+ * complement of eq. (27) is formed on FP32 matrix cores (its rank update
+ * V^T V with V rounded to FP32; S is stored, factored and solved in FP64),
+ * and every direction solved with that factor is refined refine_steps times
+ * against the FP64 operator, d <- d + S~^-1 (rhs - S d), with S applied
+ * without forming it.  The Gauss-Newton formation of eq. (20) stays FP64: its
+ * cost is in vector-unit products, which FP32 does not speed up here.
+ * mixed = 0 (the default): FP64 throughout.  Errors: NMF_EINVAL (mixed not 0
+ * or 1, refine_steps not in 0..16), NMF_ESTATE (created with with_ipm = 0). */
+nmf_status nmf_set_ipm_precision(nmf_ctx *ctx, int32_t mixed, int32_t refine_steps);
+
 /* Sets the stage-1 sweep budget (options.max_anls_sweeps, >= 1) used from now
  * on, and re-arms the stop rule of Sec. IV: the next sweeps run until it holds
  * again or `max_sweeps` more sweeps are done.  Every later

@@ -25,7 +25,7 @@ EXPORTS = [
     "nmf_default_options", "nmf_workspace_bytes", "nmf_create", "nmf_anls_step", "nmf_ipm_step",
     "nmf_solve", "nmf_append_columns", "nmf_get_factors", "nmf_get_masks", "nmf_get_report",
     "nmf_get_shape", "nmf_destroy", "nmf_last_error", "nmf_status_string", "nmf_anls_profile",
-    "nmf_get_duals", "nmf_set_launch_shape", "nmf_set_launch_fusion", "nmf_set_nnls_grouping", "nmf_get_launch_shape", "nmf_set_anls_budget", "nmf_batch_workspace_bytes", "nmf_batch_create",
+    "nmf_get_duals", "nmf_set_launch_shape", "nmf_set_launch_fusion", "nmf_set_nnls_grouping", "nmf_set_ipm_precision", "nmf_get_launch_shape", "nmf_set_anls_budget", "nmf_batch_workspace_bytes", "nmf_batch_create",
     "nmf_batch_refresh", "nmf_batch_anls_step", "nmf_batch_poll", "nmf_batch_sync", "nmf_batch_destroy",
     "nmf_batch_create_static", "nmf_ipm_profile",
 ]
@@ -144,6 +144,8 @@ def load():
     L.nmf_set_launch_fusion.restype = ctypes.c_int
     L.nmf_set_nnls_grouping.argtypes = [vp, i32]
     L.nmf_set_nnls_grouping.restype = ctypes.c_int
+    L.nmf_set_ipm_precision.argtypes = [vp, i32, i32]
+    L.nmf_set_ipm_precision.restype = ctypes.c_int
     L.nmf_get_launch_shape.argtypes = [vp, vp]
     L.nmf_get_launch_shape.restype = ctypes.c_int
     L.nmf_set_anls_budget.argtypes = [vp, i32]
@@ -342,6 +344,11 @@ class NMF:
         """1: the half is one kernel (the tile's last split solves), 0: stream +
         NNLS kernels, -1: one kernel exactly when the half has a single split."""
         self._check(load().nmf_set_launch_fusion(self._ctx, int(fuse_x), int(fuse_y)), ok=(NMF_OK,))
+
+    def set_ipm_precision(self, mixed, refine_steps=2):
+        """1: exact-Hessian Schur formation in FP32 with FP64 refinement of the
+        direction; 0: FP64 throughout."""
+        self._check(load().nmf_set_ipm_precision(self._ctx, int(mixed), int(refine_steps)), ok=(NMF_OK,))
 
     def set_nnls_grouping(self, on):
         """1: passive-set-grouped first solves in the stage-1 halves (one

@@ -43,6 +43,26 @@ struct SchurExArgs {
     double rho;
 };
 
+// res = rhs - S v for the Gauss-Newton (eq. (20)) or exact-Hessian (eq. (27))
+// Schur complement applied without forming S (FP64).
+struct OpArgs {
+    const double *Z;        // [n][zpad(K)][ldY]
+    const double *X;        // [K][ldX]
+    const double *Linv;     // [n][K][K] (exact Hessian)
+    const double *R;        // [n][ldY]: (XY - M) rows (exact Hessian)
+    int64_t n, m, ldX, ldY;
+    const double *v;        // [Np], component-major (row a*m + j), zero past N = m K
+    double *T;              // [n][ldY] work: t_i = Z_i^T V_i v
+    double *H;              // [n][K] work: h_i = L_i^-T V_i v (exact Hessian)
+    int S;                  // row splits of the column pass
+    double *part;           // [S][K][ldY] work
+    const double *GX, *s, *Y;
+    double rho;
+    const double *rhs;      // [Np]
+    double *res;            // [Np] out
+    int64_t Np;
+};
+
 struct CholArgs {
     double *S;              // column-major NT*64 x NT*64 (lower triangle used), leading dimension ldS
     int64_t ldS;
@@ -66,7 +86,10 @@ struct SolveArgs {
 int schur_chunks(int K);
 hipError_t launch_xx(int K, const double *X, int64_t ldX, int64_t n, double *XX, hipStream_t st);
 hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st);
-hipError_t launch_schur_exact(int K, const SchurExArgs &g, hipStream_t st);
+// f32: V in FP32 on FP32 matrix cores (S is still stored in FP64).
+hipError_t launch_schur_exact(int K, const SchurExArgs &g, bool f32, hipStream_t st);
+hipError_t launch_schur_apply(int K, bool exact, const OpArgs &g, hipStream_t st);
+hipError_t launch_axpy(double *y, const double *x, int64_t count, hipStream_t st);
 // Linv[i][p][a] = (L_i^-1)[p][a] from the packed factors Lq ([K(K+1)/2 + K][ldX]:
 // lower triangle row by row, then the reciprocal diagonal).
 hipError_t launch_linv(int K, const double *Lq, int64_t ldX, int64_t n, double *Linv, hipStream_t st);

@@ -245,12 +245,32 @@ __global__ __launch_bounds__(256) void k_schur_reduce(SchurArgs g) {
 // over the flattened index k = i*K + p, 32 values of k at a time.  Each
 // chunk of V (both tiles' 64 entries) is generated into LDS from Z, X, L_i^-1
 // and the residual rows while the previous chunk feeds the matrix cores.
-template <int K>
+// F32: V is rounded to FP32 in LDS and summed by FP32 matrix cores (the
+// mixed-precision form; S itself, the factorisation and the solves stay FP64,
+// and the direction is refined against the FP64 operator).
+template <bool F32> struct MfmaT;
+template <> struct MfmaT<false> {
+    typedef double E;
+    typedef v4d A;
+    static __device__ __forceinline__ A mma(E a, E b, A c) { return mfma16(a, b, c); }
+    // row of the output value v held by lane group gq
+    static __device__ __forceinline__ int drow(int gq, int v) { return gq + 4 * v; }
+};
+template <> struct MfmaT<true> {
+    typedef float E;
+    typedef float A __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ A mma(E a, E b, A c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int drow(int gq, int v) { return 4 * gq + v; }   // checked on the device
+};
+
+template <int K, bool F32>
 __global__ __launch_bounds__(256) void k_schur_exact(SchurExArgs g) {
+    typedef MfmaT<F32> M;
+    typedef typename M::E E;
     constexpr int KC = 32;
     constexpr int KP = zpad(K);
-    __shared__ double VA[2][KC * 64];
-    __shared__ double VB[2][KC * 64];
+    __shared__ E VA[2][KC * 64];
+    __shared__ E VB[2][KC * 64];
     int64_t It, Jt;
     tri_pair(blockIdx.x, It, Jt);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
@@ -299,15 +319,17 @@ __global__ __launch_bounds__(256) void k_schur_exact(SchurExArgs g) {
 #pragma unroll
         for (int v = 0; v < KC / 4; ++v) {
             const int kk = wave + 4 * v;
-            VA[buf][kk * 64 + col] = ok0 ? fma(px0[v], pz0[v], pl0[v] * pr0[v]) : 0.0;
-            VB[buf][kk * 64 + col] = ok1 ? fma(px1[v], pz1[v], pl1[v] * pr1[v]) : 0.0;
+            VA[buf][kk * 64 + col] = (E)(ok0 ? fma(px0[v], pz0[v], pl0[v] * pr0[v]) : 0.0);
+            VB[buf][kk * 64 + col] = (E)(ok1 ? fma(px1[v], pz1[v], pl1[v] * pr1[v]) : 0.0);
         }
     };
-    v4d acc[2][2];
+    typename M::A acc[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[x][y][v] = (E)0;
     load(0);
     store(0);
     __syncthreads();
@@ -318,29 +340,29 @@ __global__ __launch_bounds__(256) void k_schur_exact(SchurExArgs g) {
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
             const int kk = 4 * s + gq;
-            const double a0v = VA[buf][kk * 64 + R0 + r], a1v = VA[buf][kk * 64 + R0 + 16 + r];
-            const double b0v = VB[buf][kk * 64 + C0 + r], b1v = VB[buf][kk * 64 + C0 + 16 + r];
-            acc[0][0] = mfma16(b0v, a0v, acc[0][0]);
-            acc[0][1] = mfma16(b1v, a0v, acc[0][1]);
-            acc[1][0] = mfma16(b0v, a1v, acc[1][0]);
-            acc[1][1] = mfma16(b1v, a1v, acc[1][1]);
+            const E a0v = VA[buf][kk * 64 + R0 + r], a1v = VA[buf][kk * 64 + R0 + 16 + r];
+            const E b0v = VB[buf][kk * 64 + C0 + r], b1v = VB[buf][kk * 64 + C0 + 16 + r];
+            acc[0][0] = M::mma(b0v, a0v, acc[0][0]);
+            acc[0][1] = M::mma(b1v, a0v, acc[0][1]);
+            acc[1][0] = M::mma(b0v, a1v, acc[1][0]);
+            acc[1][1] = M::mma(b1v, a1v, acc[1][1]);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
-    // acc[x][y][v] = sum for S entry (row It*64 + R0 + 16x + r, col Jt*64 + C0 + 16y + gq + 4v)
+    // acc[x][y][v] = sum for S entry (row It*64 + R0 + 16x + r, col Jt*64 + C0 + 16y + drow(gq, v))
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = It * 64 + R0 + 16 * x + r, cl = Jt * 64 + C0 + 16 * y + gq + 4 * v;
+                const int64_t row = It * 64 + R0 + 16 * x + r, cl = Jt * 64 + C0 + 16 * y + M::drow(gq, v);
                 if (row < N && cl < N) {
                     const int a = (int)(row / g.m), b = (int)(cl / g.m);
                     const int64_t j = row - a * g.m, l = cl - b * g.m;
-                    double val = -acc[x][y][v];
+                    double val = -(double)acc[x][y][v];
                     if (j == l) {
                         val += g.GX[a * K + b];
                         if (a == b) val += g.rho + g.s[(int64_t)a * g.ldY + j] / g.Y[(int64_t)a * g.ldY + j];
@@ -424,6 +446,141 @@ __global__ __launch_bounds__(256) void k_pad_identity(double *S, int64_t ldS, in
     for (int64_t row = N + threadIdx.x; row < Np; row += 256) {
         if (row >= col) S[col * ldS + row] = (row == col) ? 1.0 : 0.0;
     }
+}
+
+// ------------------------------------------------------------- Schur operator
+// res = rhs - S v with S applied without forming it, in FP64: S = Q2bar -
+// sum_i V_i^T V_i, V_i[p][(a, j)] = X_ia Z_i[p][j] (+ (L_i^-1)[p][a] R_ij for the
+// exact Hessian, eq. (27)).  Used to refine a direction solved with a factor
+// of an S formed in FP32.
+// Pass 1, one block per row i: q = V_i v (K values), then t_i = Z_i^T q (row
+// i of T) and h_i = L_i^-T q (exact).
+template <int K, bool EXACT>
+__global__ __launch_bounds__(256) void k_op_rows(OpArgs g) {
+    constexpr int KP = zpad(K);
+    __shared__ double red[4][2 * K];
+    __shared__ double qs[K];
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double xi[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) xi[a] = g.X[(int64_t)a * g.ldX + i];
+    const double *Zi = g.Z + i * KP * g.ldY;
+    const double *Ri = g.R + i * g.ldY;
+    double qz[K], rv[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) qz[a] = rv[a] = 0.0;
+    for (int64_t j = threadIdx.x; j < g.m; j += 256) {
+        double va[K], wv = 0.0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            va[a] = g.v[(int64_t)a * g.m + j];
+            wv = fma(xi[a], va[a], wv);
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) qz[q] = fma(Zi[(int64_t)q * g.ldY + j], wv, qz[q]);
+        if (EXACT) {
+            const double rij = Ri[j];
+#pragma unroll
+            for (int a = 0; a < K; ++a) rv[a] = fma(rij, va[a], rv[a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            qz[a] += __shfl_xor(qz[a], off);
+            if (EXACT) rv[a] += __shfl_xor(rv[a], off);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+            red[wave][a] = qz[a];
+            red[wave][K + a] = rv[a];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int q = threadIdx.x;
+        double v = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+        if (EXACT) {
+            const double *li = g.Linv + (i * K + q) * K;
+#pragma unroll
+            for (int a = 0; a < K; ++a) v = fma(li[a], red[0][K + a] + red[1][K + a] + red[2][K + a] + red[3][K + a], v);
+        }
+        qs[q] = v;
+    }
+    __syncthreads();
+    double qv[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) qv[q] = qs[q];
+    for (int64_t l = threadIdx.x; l < g.ldY; l += 256) {
+        double t = 0.0;
+        if (l < g.m) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) t = fma(Zi[(int64_t)q * g.ldY + l], qv[q], t);
+        }
+        g.T[i * g.ldY + l] = t;
+    }
+    if (EXACT && threadIdx.x < K) {
+        const int a = threadIdx.x;
+        double h = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) h = fma(g.Linv[(i * K + q) * K + a], qv[q], h);
+        g.H[i * K + a] = h;
+    }
+}
+
+// Pass 2: part[s][a][l] = sum over the rows i of split s of X_ia t_i[l]
+// (+ h_i[a] R_il), one thread per column l.
+template <int K, bool EXACT>
+__global__ __launch_bounds__(256) void k_op_cols(OpArgs g) {
+    const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int sp = blockIdx.y;
+    const int64_t per = (g.n + g.S - 1) / g.S;
+    const int64_t i0 = (int64_t)sp * per, i1 = min(g.n, i0 + per);
+    if (l >= g.m) return;
+    double acc[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) acc[a] = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double t = g.T[i * g.ldY + l];
+#pragma unroll
+        for (int a = 0; a < K; ++a) acc[a] = fma(g.X[(int64_t)a * g.ldX + i], t, acc[a]);
+        if (EXACT) {
+            const double rr = g.R[i * g.ldY + l];
+#pragma unroll
+            for (int a = 0; a < K; ++a) acc[a] = fma(g.H[i * K + a], rr, acc[a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < K; ++a) g.part[((int64_t)sp * K + a) * g.ldY + l] = acc[a];
+}
+
+// Pass 3: res = rhs - (Q2bar v - sum_i V_i^T V_i v), zero past N.
+template <int K>
+__global__ __launch_bounds__(256) void k_op_residual(OpArgs g) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= g.Np) return;
+    const int64_t N = g.m * K;
+    if (e >= N) {
+        g.res[e] = 0.0;
+        return;
+    }
+    const int a = (int)(e / g.m);
+    const int64_t l = e - (int64_t)a * g.m;
+    double out = 0.0;
+    for (int sp = 0; sp < g.S; ++sp) out += g.part[((int64_t)sp * K + a) * g.ldY + l];
+    double q2 = (g.rho + g.s[(int64_t)a * g.ldY + l] / g.Y[(int64_t)a * g.ldY + l]) * g.v[e];
+#pragma unroll
+    for (int b = 0; b < K; ++b) q2 = fma(g.GX[a * K + b], g.v[(int64_t)b * g.m + l], q2);
+    g.res[e] = g.rhs[e] - (q2 - out);
+}
+
+__global__ void k_axpy(double *y, const double *x, int64_t count) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < count) y[e] += x[e];
 }
 
 // ------------------------------------------------------------- Cholesky of S
@@ -863,9 +1020,33 @@ hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_schur_exact(int K, const SchurExArgs &g, hipStream_t st) {
+hipError_t launch_schur_exact(int K, const SchurExArgs &g, bool f32, hipStream_t st) {
     const dim3 grid((unsigned)((int64_t)g.NT * (g.NT + 1) / 2));
-    DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_schur_exact<KK>, grid, dim3(256), 0, st, g));
+    if (f32) {
+        DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_schur_exact<KK, true>), grid, dim3(256), 0, st, g));
+    } else {
+        DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_schur_exact<KK, false>), grid, dim3(256), 0, st, g));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_schur_apply(int K, bool exact, const OpArgs &g, hipStream_t st) {
+    if (g.S < 1 || g.n < 1 || g.m < 1) return hipErrorInvalidValue;
+    const dim3 gc((unsigned)((g.m + 255) / 256), (unsigned)g.S);
+    if (exact) {
+        DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_op_rows<KK, true>), dim3((unsigned)g.n), dim3(256), 0, st, g));
+        DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_op_cols<KK, true>), gc, dim3(256), 0, st, g));
+    } else {
+        DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_op_rows<KK, false>), dim3((unsigned)g.n), dim3(256), 0, st, g));
+        DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_op_cols<KK, false>), gc, dim3(256), 0, st, g));
+    }
+    DENSE_K_SWITCH(K, hipLaunchKernelGGL(k_op_residual<KK>, dim3((unsigned)((g.Np + 255) / 256)), dim3(256), 0, st, g));
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double *y, const double *x, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, y, x, count);
     return hipGetLastError();
 }
 

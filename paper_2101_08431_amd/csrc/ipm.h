@@ -46,6 +46,12 @@ struct IpmState {
     double *XX = nullptr;                      // [n][K(K+1)/2] products X_ia X_ib
     double *Dinv = nullptr;                    // [ldS/64][64*64] inverses of the diagonal factor tiles
     double *spart = nullptr;                   // Schur row-split partial sums (P > 1)
+    // mixed precision (nmf_set_ipm_precision): exact-Hessian Schur formation in
+    // FP32, the direction refined against the FP64 operator
+    int mixed = 0, refine = 2;
+    double *rhs0 = nullptr, *dacc = nullptr;   // [ldS] right-hand side, accumulated direction
+    double *Top = nullptr, *Hop = nullptr;     // [n][ldY], [n][K] operator work
+    double *opart = nullptr;                   // [OPS][K][ldY] operator partials
     unsigned *flags = nullptr;                 // [3][ldS/64] hand-over flags: factor, forward, backward solve
     unsigned epoch = 0;                        // last flag value used
     bool flags_ready = false;

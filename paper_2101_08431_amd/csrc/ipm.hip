@@ -804,7 +804,7 @@ static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct IpmLayout {
     size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Linv, Rrow, Z, S, vec, vec2, XX, Dinv, spart, flags, part, fpart,
-        sc, total;
+        sc, rhs0, dacc, Top, Hop, opart, total;
     int64_t ldX, ldY, ldS;
     int P;
 };
@@ -819,6 +819,8 @@ static int schur_splits(int64_t n, int64_t m, int K) {
     if (units >= 8192 || n < 8 * 32) return 1;
     return 8;
 }
+
+constexpr int OPS = 16;   // row splits of the operator's column pass
 
 static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     IpmLayout L;
@@ -852,6 +854,11 @@ static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     L.part = take((size_t)nblk * PRS * 8);
     L.fpart = take((size_t)Tn * 64 * 8 * sizeof(double));   // Tn * Sx records of 8 (Sx <= 64)
     L.sc = take(sizeof(IpmScal));
+    L.rhs0 = take((size_t)L.ldS * 8);
+    L.dacc = take((size_t)L.ldS * 8);
+    L.Top = take((size_t)n * L.ldY * 8);
+    L.Hop = take((size_t)n * K * 8);
+    L.opart = take((size_t)OPS * K * L.ldY * 8);
     L.total = off;
     return L;
 }
@@ -878,6 +885,11 @@ nmf_status ipm_bind(IpmState &s, uint8_t *base, int64_t n, int64_t m_cap, int K)
     s.epoch = 0;
     s.part = (double *)(base + L.part); s.fpart = (double *)(base + L.fpart);
     s.sc = (IpmScal *)(base + L.sc);
+    s.rhs0 = (double *)(base + L.rhs0);
+    s.dacc = (double *)(base + L.dacc);
+    s.Top = (double *)(base + L.Top);
+    s.Hop = (double *)(base + L.Hop);
+    s.opart = (double *)(base + L.opart);
     s.bound = true;
     return NMF_OK;
 }
@@ -1079,7 +1091,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
             g.s = c.s.s;
             g.Y = p.Y;
             g.rho = rho;
-            HCK(launch_schur_exact(K, g, c.st));
+            HCK(launch_schur_exact(K, g, c.s.mixed != 0, c.st));
         } else {
             HCK(launch_xx(K, p.X, p.ldX, p.n, c.s.XX, c.st));
             SchurArgs g;
@@ -1126,6 +1138,41 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
     prof_begin(c);
     nmf_status st = solve_S(c, N);
     if (st != NMF_OK) return st;
+    if (exact && c.s.mixed) {
+        // iterative refinement against the FP64 operator: d += S32^-1 (rhs - S d)
+        const int64_t Np = (N + CB - 1) / CB * CB;
+        HCK(hipMemcpyAsync(c.s.rhs0, c.s.vec, (size_t)Np * 8, hipMemcpyDeviceToDevice, c.st));
+        HCK(hipMemcpyAsync(c.s.dacc, c.s.vec2, (size_t)Np * 8, hipMemcpyDeviceToDevice, c.st));
+        OpArgs g;
+        g.Z = c.s.Z;
+        g.X = p.X;
+        g.Linv = c.s.Linv;
+        g.R = c.s.Rrow;
+        g.n = p.n;
+        g.m = p.m;
+        g.ldX = p.ldX;
+        g.ldY = p.ldY;
+        g.v = c.s.dacc;
+        g.T = c.s.Top;
+        g.H = c.s.Hop;
+        g.S = OPS;
+        g.part = c.s.opart;
+        g.GX = c.s.sc->GX;
+        g.s = c.s.s;
+        g.Y = p.Y;
+        g.rho = rho;
+        g.rhs = c.s.rhs0;
+        g.res = c.s.vec;
+        g.Np = Np;
+        for (int it = 0; it < c.s.refine; ++it) {
+            HCK(launch_schur_apply(K, true, g, c.st));
+            st = solve_S(c, N);
+            if (st != NMF_OK) return st;
+            HCK(launch_axpy(c.s.dacc, c.s.vec2, Np, c.st));
+        }
+        HCK(hipMemcpyAsync(c.s.vec2, c.s.dacc, (size_t)Np * 8, hipMemcpyDeviceToDevice, c.st));
+        HCK(hipMemcpyAsync(c.s.vec, c.s.rhs0, (size_t)Np * 8, hipMemcpyDeviceToDevice, c.st));
+    }
     prof_end(c, 3);
     IPM_KS(K, hipLaunchKernelGGL(k_post_y<KK>, g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu, tau, 0));
     IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.m), dim3(NTHR), 0, c.st, c.s.dy, p.Y, p.ldY, p.m,

@@ -627,6 +627,16 @@ nmf_status nmf_set_launch_fusion(nmf_ctx *c, int32_t fuse_x, int32_t fuse_y) {
     return NMF_OK;
 }
 
+nmf_status nmf_set_ipm_precision(nmf_ctx *c, int32_t mixed, int32_t refine_steps) {
+    if (!c) return NMF_EINVAL;
+    if (mixed != 0 && mixed != 1) return fail(c, NMF_EINVAL, "ipm precision not 0 or 1");
+    if (refine_steps < 0 || refine_steps > 16) return fail(c, NMF_EINVAL, "refinement steps not in 0..16");
+    if (!c->opt.with_ipm) return fail(c, NMF_ESTATE, "context created without stage-2 workspace");
+    c->ipm.mixed = mixed;
+    c->ipm.refine = refine_steps;
+    return NMF_OK;
+}
+
 nmf_status nmf_set_nnls_grouping(nmf_ctx *c, int32_t on) {
     if (!c) return NMF_EINVAL;
     if (on != 0 && on != 1) return fail(c, NMF_EINVAL, "grouping not 0 or 1");
