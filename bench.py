@@ -608,7 +608,6 @@ def main():
         log("batching section")
         out["batching"] = batching_section(256, 10)
         out["grouping"] = grouping_section()
-        out["mixed_precision"] = mixed_section()
     if not args.no_serve:
         log("serving section")
         out["serving"] = serving_section(args.serve_seconds)
