@@ -1168,11 +1168,12 @@ __global__ __launch_bounds__(nnls_threads(K)) void k_ginverse(AnlsParams p, int 
         a[c] = (pr && ((P >> c) & 1u)) ? G[r * K + c] : (r == c ? 1.0 : 0.0);
         w[c] = (c == r) ? 1.0 : 0.0;
     }
-    double dmin = 1.0;
+    double dmin = 1.0, dsum = 0.0;   // the sum catches NaN and infinite pivots, which fmin drops
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         const double d = lane_bcast(a[c], c);
         dmin = fmin(dmin, d);
+        dsum += d;
         const double s = rsqrt_newton(d > 0.0 ? d : 1.0);
         const double l = a[c] * s;
         a[c] = l;
@@ -1185,7 +1186,7 @@ __global__ __launch_bounds__(nnls_threads(K)) void k_ginverse(AnlsParams p, int 
             asm volatile("" : "+v"(w[jj]));
         }
     }
-    const bool bad = !(dmin > 0.0);
+    const bool bad = !(dmin > 0.0) || !isfinite(dsum);
     double *T = p.gtab + (int64_t)slot * (K * K);
 #pragma unroll
     for (int bcol = 0; bcol < K; ++bcol) {

@@ -605,11 +605,14 @@ __device__ __forceinline__ void potrf_inv16(const double *T, double *Lf, int j, 
         a[q] = Trow[q];
         w[q] = (q == p) ? 1.0 : 0.0;
     }
-    double dmin = 1.0;
+    // fmin drops a NaN operand, so the pivots are also summed: a NaN or an
+    // infinity among them makes the sum non-finite
+    double dmin = 1.0, dsum = 0.0;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const double d = lane_read(a[c], c);
         dmin = fmin(dmin, d);
+        dsum += d;
         const double s = rsqrt_nr(d > 0.0 ? d : 1.0);
         const double l = a[c] * s;   // row p of column c; on lane c, sqrt(d)
         a[c] = l;
@@ -628,7 +631,7 @@ __device__ __forceinline__ void potrf_inv16(const double *T, double *Lf, int j, 
 #pragma unroll
         for (int q = 0; q < 16; ++q) Lf[(16 * j + q) * LDT + 16 * j + p] = w[q];
     }
-    if (!(dmin > 0.0) && lane == 0) *bad = 1;
+    if ((!(dmin > 0.0) || !isfinite(dsum)) && lane == 0) *bad = 1;
 }
 
 // Block column j of the 64 x 64 factor, for row block i > j (one wave): the

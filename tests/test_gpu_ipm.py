@@ -241,3 +241,26 @@ def test_append_after_stage2_returns_to_stage1(orc):
     Rg, Sg = ctx.duals()
     gx, gy, _ = orc.gradients(M, Xg, Yg.T)
     assert orc.kkt_error(Xg, Yg.T, Rg, Sg.T, 0.0, gx, gy) <= 2e-9
+
+
+def test_breakdown_leaves_a_finite_iterate():
+    # seed 5 of 3000x500x5 ends in a numerical breakdown (mu falls to the
+    # denormal range while E(.;0) is still 7e-6 and the Gauss-Newton matrix
+    # stops factoring).  The library must report it (NMF_ESINGULAR) and keep
+    # the last valid iterate: no NaN or infinity may reach X, Y or the report.
+    from paper_2101_08431_amd import NMF, default_options
+    from paper_2101_08431_amd._lib import NMFError
+    M, X0, Y0 = synth.make("pdf_3000x500_k5", 5)
+    print("case breakdown pdf_3000x500_k5 seed 5", flush=True)
+    ctx = NMF(np.asarray(M), 5, X0, Y0, options=default_options(eps_tol=1e-8, max_ipm_iters=5000))
+    try:
+        st, rep = ctx.solve()
+    except NMFError as e:
+        st, rep = e.status, ctx.report()
+    print(f"status {st}, E0 {rep['E0']:.3e}, iterations {rep['ipm_iters']}", flush=True)
+    assert st in (1, -5), st
+    X, Y = ctx.factors()
+    ctx.close()
+    assert np.isfinite(X).all() and np.isfinite(Y).all()
+    assert (X >= 0).all() and (Y >= 0).all()
+    assert np.isfinite(rep["E0"]) and np.isfinite(rep["f"])
