@@ -27,8 +27,8 @@ struct SchurArgs {
 };
 
 // Exact-Hessian Schur complement (eq. (27)): S = Q2bar - sum_i V_i^T V_i with
-// V_i[p][(a, j)] = X_ia Z_i[p][j] + (L_i^-1)[p][a] R_ij, R = XY - M; the sum
-// runs over the flattened (i, p) index on matrix cores.
+// V_i[p][(a, j)] = X_ia Z_i[p][j] + (L_i^-1)[p][a] R_ij, R = XY - M; V is
+// written out row by row (k = i K + p) and the sum runs over k on matrix cores.
 struct SchurExArgs {
     const double *Z;        // [n][zpad(K)][ldY]
     const double *X;        // [K][ldX]
@@ -86,8 +86,11 @@ struct SolveArgs {
 int schur_chunks(int K);
 hipError_t launch_xx(int K, const double *X, int64_t ldX, int64_t n, double *XX, hipStream_t st);
 hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st);
-// f32: V in FP32 on FP32 matrix cores (S is still stored in FP64).
-hipError_t launch_schur_exact(int K, const SchurExArgs &g, bool f32, hipStream_t st);
+// The exact-Hessian Schur complement with V written out (k_vgen) in slabs of
+// `slab` rows into V ([slab][ldV] doubles, or floats when f32; ldV >= NT*64, a
+// multiple of 64) and summed by a matrix-core rank update per slab (k_syrk_v).
+hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t ldV, int64_t slab, bool f32,
+                                   hipStream_t st);
 hipError_t launch_schur_apply(int K, bool exact, const OpArgs &g, hipStream_t st);
 hipError_t launch_axpy(double *y, const double *x, int64_t count, hipStream_t st);
 // Linv[i][p][a] = (L_i^-1)[p][a] from the packed factors Lq ([K(K+1)/2 + K][ldX]:

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "dense.h"
 
 namespace nmfk {
@@ -240,14 +242,10 @@ __global__ __launch_bounds__(256) void k_schur_reduce(SchurArgs g) {
     schur_store<K>(g, jt, lt, a, b, val);
 }
 
-// Exact-Hessian Schur complement as one symmetric rank update on matrix
-// cores: tile (I, J) of S (64 x 64, I >= J) sums V[k][rows I] V[k][cols J]
-// over the flattened index k = i*K + p, 32 values of k at a time.  Each
-// chunk of V (both tiles' 64 entries) is generated into LDS from Z, X, L_i^-1
-// and the residual rows while the previous chunk feeds the matrix cores.
-// F32: V is rounded to FP32 in LDS and summed by FP32 matrix cores (the
-// mixed-precision form; S itself, the factorisation and the solves stay FP64,
-// and the direction is refined against the FP64 operator).
+// Element type, matrix-core step and output layout of the exact-Hessian rank
+// update: FP64, or FP32 for the mixed-precision form (V rounded to FP32; S
+// itself, the factorisation and the solves stay FP64, and the direction is
+// refined against the FP64 operator).
 template <bool F32> struct MfmaT;
 template <> struct MfmaT<false> {
     typedef double E;
@@ -263,64 +261,70 @@ template <> struct MfmaT<true> {
     static __device__ __forceinline__ int drow(int gq, int v) { return 4 * gq + v; }   // checked on the device
 };
 
+// Rows [k0, k1) of the exact-Hessian factor (eq. (27)) written out once:
+// V[k - k0][(a, j)] = X_ia Z_i[p][j] + (L_i^-1)[p][a] R_ij for k = i*K + p,
+// columns in component-major order (a*m + j), zero from N = m K to ldV;
+// rounded to FP32 for the mixed-precision form.
+template <int K, typename E>
+__global__ __launch_bounds__(256) void k_vgen(SchurExArgs g, int64_t k0, int64_t k1, E *V, int64_t ldV) {
+    const int64_t k = k0 + blockIdx.y;
+    if (k >= k1) return;
+    const int64_t i = k / K;
+    const int p = (int)(k - i * K);
+    const int64_t N = g.m * K;
+    const double *zr = g.Z + (i * zpad(K) + p) * g.ldY;
+    const double *rr = g.R + i * g.ldY;
+    const double *li = g.Linv + (i * K + p) * K;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < ldV; c += (int64_t)gridDim.x * 256) {
+        double v = 0.0;
+        if (c < N) {
+            const int a = (int)(c / g.m);
+            const int64_t j = c - (int64_t)a * g.m;
+            v = fma(g.X[(int64_t)a * g.ldX + i], zr[j], li[a] * rr[j]);
+        }
+        V[(k - k0) * ldV + c] = (E)v;
+    }
+}
+
+// S (tile (I, J), I >= J) minus the sum over `rows` rows k of V of
+// V[k][rows I] V[k][cols J] on matrix cores (FP64, or FP32 for the
+// mixed-precision form): V read from memory (written once by k_vgen), not
+// regenerated by every tile.
+// Chunks of 32 rows are staged in LDS with 16-byte loads, the next chunk
+// loaded while the current one is multiplied.  first: S = Q2bar - sum;
+// otherwise S -= sum (later slabs of rows).
 template <int K, bool F32>
-__global__ __launch_bounds__(256) void k_schur_exact(SchurExArgs g) {
+__global__ __launch_bounds__(256) void k_syrk_v(SchurExArgs g, const typename MfmaT<F32>::E *V, int64_t ldV,
+                                                int64_t rows, int first) {
     typedef MfmaT<F32> M;
     typedef typename M::E E;
     constexpr int KC = 32;
-    constexpr int KP = zpad(K);
-    __shared__ E VA[2][KC * 64];
-    __shared__ E VB[2][KC * 64];
+    constexpr int PER = 16 / (int)sizeof(E);          // elements per 16-byte load
+    constexpr int NLD = 2 * KC * 64 / PER / 256;      // loads per thread and chunk
+    constexpr int TSH = KC * 64 / PER;                // loads per tile and chunk
+    constexpr int RSH = 64 / PER;                     // loads per row of a tile
+    __shared__ __align__(16) E VA[2][KC * 64];
+    __shared__ __align__(16) E VB[2][KC * 64];
     int64_t It, Jt;
     tri_pair(blockIdx.x, It, Jt);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
     const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
     const int64_t N = g.m * K;
-    // this thread generates column `col` of both tiles for k rows kk = wave + 4v
-    const int col = lane;
-    const int64_t rho0 = It * 64 + col, rho1 = Jt * 64 + col;
-    const bool ok0 = rho0 < N, ok1 = rho1 < N;
-    const int a0 = ok0 ? (int)(rho0 / g.m) : 0, a1 = ok1 ? (int)(rho1 / g.m) : 0;
-    const int64_t j0 = ok0 ? rho0 - a0 * g.m : 0, j1 = ok1 ? rho1 - a1 * g.m : 0;
-    const int64_t nk = g.n * K;
-    // raw operands of one chunk for this thread (k rows kk = wave + 4v), loaded
-    // a chunk ahead and combined into V when written to LDS
-    double px0[KC / 4], pz0[KC / 4], pl0[KC / 4], pr0[KC / 4];
-    double px1[KC / 4], pz1[KC / 4], pl1[KC / 4], pr1[KC / 4];
+    uint4 ld[NLD];
     auto load = [&](int64_t k0) {
-        // k = k0 + wave + 4v: i and p advance by 4 in k per v
-        int64_t k = k0 + wave;
-        int64_t i = k / K;
-        int pq = (int)(k - i * K);
 #pragma unroll
-        for (int v = 0; v < KC / 4; ++v) {
-            const bool live = k < nk;
-            const int64_t ic = live ? i : 0;
-            const double *zr = g.Z + (ic * KP + pq) * g.ldY;
-            const double *rr = g.R + ic * g.ldY;
-            const double *li = g.Linv + (ic * K + pq) * K;
-            px0[v] = live ? g.X[(int64_t)a0 * g.ldX + ic] : 0.0;
-            pz0[v] = zr[j0];
-            pl0[v] = live ? li[a0] : 0.0;
-            pr0[v] = rr[j0];
-            px1[v] = live ? g.X[(int64_t)a1 * g.ldX + ic] : 0.0;
-            pz1[v] = zr[j1];
-            pl1[v] = live ? li[a1] : 0.0;
-            pr1[v] = rr[j1];
-            k += 4;
-            pq += 4;
-            while (pq >= K) {
-                pq -= K;
-                ++i;
-            }
+        for (int h = 0; h < NLD; ++h) {
+            const int idx = h * 256 + threadIdx.x, tile = idx / TSH, rem = idx % TSH, kk = rem / RSH, cq = rem % RSH;
+            const int64_t kr = k0 + kk;
+            ld[h] = kr < rows ? *reinterpret_cast<const uint4 *>(V + kr * ldV + (tile ? Jt : It) * 64 + PER * cq)
+                              : make_uint4(0u, 0u, 0u, 0u);
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < KC / 4; ++v) {
-            const int kk = wave + 4 * v;
-            VA[buf][kk * 64 + col] = (E)(ok0 ? fma(px0[v], pz0[v], pl0[v] * pr0[v]) : 0.0);
-            VB[buf][kk * 64 + col] = (E)(ok1 ? fma(px1[v], pz1[v], pl1[v] * pr1[v]) : 0.0);
+        for (int h = 0; h < NLD; ++h) {
+            const int idx = h * 256 + threadIdx.x, tile = idx / TSH, rem = idx % TSH;
+            *reinterpret_cast<uint4 *>((tile ? VB[buf] : VA[buf]) + rem * PER) = ld[h];
         }
     };
     typename M::A acc[2][2];
@@ -334,8 +338,8 @@ __global__ __launch_bounds__(256) void k_schur_exact(SchurExArgs g) {
     store(0);
     __syncthreads();
     int buf = 0;
-    for (int64_t k0 = 0; k0 < nk; k0 += KC) {
-        const bool more = k0 + KC < nk;
+    for (int64_t k0 = 0; k0 < rows; k0 += KC) {
+        const bool more = k0 + KC < rows;
         if (more) load(k0 + KC);
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
@@ -351,7 +355,6 @@ __global__ __launch_bounds__(256) void k_schur_exact(SchurExArgs g) {
         __syncthreads();
         buf ^= 1;
     }
-    // acc[x][y][v] = sum for S entry (row It*64 + R0 + 16x + r, col Jt*64 + C0 + 16y + drow(gq, v))
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -360,14 +363,20 @@ __global__ __launch_bounds__(256) void k_schur_exact(SchurExArgs g) {
             for (int v = 0; v < 4; ++v) {
                 const int64_t row = It * 64 + R0 + 16 * x + r, cl = Jt * 64 + C0 + 16 * y + M::drow(gq, v);
                 if (row < N && cl < N) {
-                    const int a = (int)(row / g.m), b = (int)(cl / g.m);
-                    const int64_t j = row - a * g.m, l = cl - b * g.m;
-                    double val = -(double)acc[x][y][v];
-                    if (j == l) {
-                        val += g.GX[a * K + b];
-                        if (a == b) val += g.rho + g.s[(int64_t)a * g.ldY + j] / g.Y[(int64_t)a * g.ldY + j];
+                    double *dst = g.S + cl * g.ldS + row;
+                    const double sum = (double)acc[x][y][v];
+                    if (first) {
+                        const int a = (int)(row / g.m), b = (int)(cl / g.m);
+                        const int64_t j = row - a * g.m, l = cl - b * g.m;
+                        double val = -sum;
+                        if (j == l) {
+                            val += g.GX[a * K + b];
+                            if (a == b) val += g.rho + g.s[(int64_t)a * g.ldY + j] / g.Y[(int64_t)a * g.ldY + j];
+                        }
+                        *dst = val;
+                    } else {
+                        *dst -= sum;
                     }
-                    g.S[cl * g.ldS + row] = val;
                 }
             }
 }
@@ -1023,12 +1032,26 @@ hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_schur_exact(int K, const SchurExArgs &g, bool f32, hipStream_t st) {
+hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t ldV, int64_t slab, bool f32,
+                                   hipStream_t st) {
+    const int64_t nk = g.n * K;
+    if (slab < 32 || slab > 65535 || ldV < (int64_t)g.NT * 64 || ldV % 64 != 0) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((int64_t)g.NT * (g.NT + 1) / 2));
-    if (f32) {
-        DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_schur_exact<KK, true>), grid, dim3(256), 0, st, g));
-    } else {
-        DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_schur_exact<KK, false>), grid, dim3(256), 0, st, g));
+    for (int64_t k0 = 0; k0 < nk; k0 += slab) {
+        const int64_t k1 = std::min(nk, k0 + slab);
+        const dim3 gv((unsigned)std::min<int64_t>((ldV + 255) / 256, 64), (unsigned)(k1 - k0));
+        const int first = k0 == 0 ? 1 : 0;
+        if (f32) {
+            float *Vf = (float *)V;
+            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_vgen<KK, float>), gv, dim3(256), 0, st, g, k0, k1, Vf, ldV));
+            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, true>), grid, dim3(256), 0, st, g, (const float *)Vf, ldV,
+                                                 k1 - k0, first));
+        } else {
+            double *Vd = (double *)V;
+            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_vgen<KK, double>), gv, dim3(256), 0, st, g, k0, k1, Vd, ldV));
+            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, false>), grid, dim3(256), 0, st, g, (const double *)Vd,
+                                                 ldV, k1 - k0, first));
+        }
     }
     return hipGetLastError();
 }

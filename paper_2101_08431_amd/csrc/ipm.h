@@ -52,6 +52,8 @@ struct IpmState {
     double *rhs0 = nullptr, *dacc = nullptr;   // [ldS] right-hand side, accumulated direction
     double *Top = nullptr, *Hop = nullptr;     // [n][ldY], [n][K] operator work
     double *opart = nullptr;                   // [OPS][K][ldY] operator partials
+    double *Vex = nullptr;                     // [vrows][ldS] rows of the exact-Hessian factor V
+    int64_t vrows = 0;
     unsigned *flags = nullptr;                 // [3][ldS/64] hand-over flags: factor, forward, backward solve
     unsigned epoch = 0;                        // last flag value used
     bool flags_ready = false;

@@ -29,6 +29,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "dense.h"
@@ -804,7 +805,8 @@ static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct IpmLayout {
     size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Linv, Rrow, Z, S, vec, vec2, XX, Dinv, spart, flags, part, fpart,
-        sc, rhs0, dacc, Top, Hop, opart, total;
+        sc, rhs0, dacc, Top, Hop, opart, Vex, total;
+    int64_t vrows;
     int64_t ldX, ldY, ldS;
     int P;
 };
@@ -821,6 +823,14 @@ static int schur_splits(int64_t n, int64_t m, int K) {
 }
 
 constexpr int OPS = 16;   // row splits of the operator's column pass
+
+// Rows of the exact-Hessian factor V written out at a time (V holds n K rows
+// of ldS entries): all of them up to 2 GiB, else slabs of that size.
+static int64_t vex_rows(int64_t n, int K, int64_t ldS) {
+    const int64_t nk = n * K;
+    const int64_t cap = std::max<int64_t>(32, ((int64_t)2 << 30) / (ldS * 8));
+    return std::min<int64_t>(std::min<int64_t>(nk, cap), 65535);
+}
 
 static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     IpmLayout L;
@@ -859,6 +869,8 @@ static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     L.Top = take((size_t)n * L.ldY * 8);
     L.Hop = take((size_t)n * K * 8);
     L.opart = take((size_t)OPS * K * L.ldY * 8);
+    L.vrows = vex_rows(n, K, L.ldS);
+    L.Vex = take((size_t)L.vrows * L.ldS * 8);
     L.total = off;
     return L;
 }
@@ -890,6 +902,8 @@ nmf_status ipm_bind(IpmState &s, uint8_t *base, int64_t n, int64_t m_cap, int K)
     s.Top = (double *)(base + L.Top);
     s.Hop = (double *)(base + L.Hop);
     s.opart = (double *)(base + L.opart);
+    s.Vex = (double *)(base + L.Vex);
+    s.vrows = L.vrows;
     s.bound = true;
     return NMF_OK;
 }
@@ -1091,7 +1105,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
             g.s = c.s.s;
             g.Y = p.Y;
             g.rho = rho;
-            HCK(launch_schur_exact(K, g, c.s.mixed != 0, c.st));
+            HCK(launch_schur_exact_rows(K, g, c.s.Vex, c.s.ldS, c.s.vrows, c.s.mixed != 0, c.st));
         } else {
             HCK(launch_xx(K, p.X, p.ldX, p.n, c.s.XX, c.st));
             SchurArgs g;
