@@ -286,52 +286,58 @@ __global__ __launch_bounds__(256) void k_vgen(SchurExArgs g, int64_t k0, int64_t
     }
 }
 
-// S (tile (I, J), I >= J) minus the sum over `rows` rows k of V of
-// V[k][rows I] V[k][cols J] on matrix cores (FP64, or FP32 for the
-// mixed-precision form): V read from memory (written once by k_vgen), not
-// regenerated by every tile.
-// Chunks of 32 rows are staged in LDS with 16-byte loads, the next chunk
-// loaded while the current one is multiplied.  first: S = Q2bar - sum;
+// S (tile (I, J) of 128 x 128, I >= J) minus the sum over `rows` rows k of
+// V of V[k][rows I] V[k][cols J] on matrix cores (FP64, or FP32 for the
+// mixed-precision form), V read from memory (written once by k_vgen).  512
+// threads: wave w owns rows 32 (w / 2) and columns 64 (w % 2) of the tile
+// (2 x 4 blocks of 16 x 16).  Chunks of 16 rows of V are staged in LDS with
+// 16-byte loads, the next chunk loaded while the current one is multiplied.
+// 128-wide tiles read each V element half as often as 64-wide ones (16
+// flop/byte in FP64).  On a diagonal tile the waves wholly above the diagonal
+// skip the products (their entries are never read).  first: S = Q2bar - sum;
 // otherwise S -= sum (later slabs of rows).
 template <int K, bool F32>
-__global__ __launch_bounds__(256) void k_syrk_v(SchurExArgs g, const typename MfmaT<F32>::E *V, int64_t ldV,
+__global__ __launch_bounds__(512) void k_syrk_v(SchurExArgs g, const typename MfmaT<F32>::E *V, int64_t ldV,
                                                 int64_t rows, int first) {
     typedef MfmaT<F32> M;
     typedef typename M::E E;
-    constexpr int KC = 32;
+    constexpr int TW = 128;                           // tile width
+    constexpr int KC = 16;                            // rows of V per chunk
     constexpr int PER = 16 / (int)sizeof(E);          // elements per 16-byte load
-    constexpr int NLD = 2 * KC * 64 / PER / 256;      // loads per thread and chunk
-    constexpr int TSH = KC * 64 / PER;                // loads per tile and chunk
-    constexpr int RSH = 64 / PER;                     // loads per row of a tile
-    __shared__ __align__(16) E VA[2][KC * 64];
-    __shared__ __align__(16) E VB[2][KC * 64];
+    constexpr int TSH = KC * TW / PER;                // loads per tile and chunk
+    constexpr int RSH = TW / PER;                     // loads per row of a tile
+    constexpr int NLD = 2 * TSH / 512;                // loads per thread and chunk
+    __shared__ __align__(16) E VA[2][KC * TW];
+    __shared__ __align__(16) E VB[2][KC * TW];
     int64_t It, Jt;
     tri_pair(blockIdx.x, It, Jt);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
-    const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 32;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
+    const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 64;
+    const bool work = !(It == Jt && R0 + 32 <= C0);   // wave-uniform
     const int64_t N = g.m * K;
     uint4 ld[NLD];
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int h = 0; h < NLD; ++h) {
-            const int idx = h * 256 + threadIdx.x, tile = idx / TSH, rem = idx % TSH, kk = rem / RSH, cq = rem % RSH;
-            const int64_t kr = k0 + kk;
-            ld[h] = kr < rows ? *reinterpret_cast<const uint4 *>(V + kr * ldV + (tile ? Jt : It) * 64 + PER * cq)
-                              : make_uint4(0u, 0u, 0u, 0u);
+            const int idx = h * 512 + threadIdx.x, tile = idx / TSH, rem = idx % TSH, kk = rem / RSH, cq = rem % RSH;
+            const int64_t kr = k0 + kk, col = (tile ? Jt : It) * TW + PER * cq;
+            ld[h] = (kr < rows && col < ldV) ? *reinterpret_cast<const uint4 *>(V + kr * ldV + col)
+                                             : make_uint4(0u, 0u, 0u, 0u);
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int h = 0; h < NLD; ++h) {
-            const int idx = h * 256 + threadIdx.x, tile = idx / TSH, rem = idx % TSH;
+            const int idx = h * 512 + threadIdx.x, tile = idx / TSH, rem = idx % TSH;
             *reinterpret_cast<uint4 *>((tile ? VB[buf] : VA[buf]) + rem * PER) = ld[h];
         }
     };
-    typename M::A acc[2][2];
+    typename M::A acc[2][4];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < 4; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[x][y][v] = (E)0;
     load(0);
@@ -341,27 +347,33 @@ __global__ __launch_bounds__(256) void k_syrk_v(SchurExArgs g, const typename Mf
     for (int64_t k0 = 0; k0 < rows; k0 += KC) {
         const bool more = k0 + KC < rows;
         if (more) load(k0 + KC);
+        if (work) {
 #pragma unroll
-        for (int s = 0; s < KC / 4; ++s) {
-            const int kk = 4 * s + gq;
-            const E a0v = VA[buf][kk * 64 + R0 + r], a1v = VA[buf][kk * 64 + R0 + 16 + r];
-            const E b0v = VB[buf][kk * 64 + C0 + r], b1v = VB[buf][kk * 64 + C0 + 16 + r];
-            acc[0][0] = M::mma(b0v, a0v, acc[0][0]);
-            acc[0][1] = M::mma(b1v, a0v, acc[0][1]);
-            acc[1][0] = M::mma(b0v, a1v, acc[1][0]);
-            acc[1][1] = M::mma(b1v, a1v, acc[1][1]);
+            for (int s = 0; s < KC / 4; ++s) {
+                const int kk = 4 * s + gq;
+                E av[2], bv[4];
+#pragma unroll
+                for (int x = 0; x < 2; ++x) av[x] = VA[buf][kk * TW + R0 + 16 * x + r];
+#pragma unroll
+                for (int y = 0; y < 4; ++y) bv[y] = VB[buf][kk * TW + C0 + 16 * y + r];
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] = M::mma(bv[y], av[x], acc[x][y]);
+            }
         }
         if (more) store(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
+    if (!work) return;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < 4; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = It * 64 + R0 + 16 * x + r, cl = Jt * 64 + C0 + 16 * y + M::drow(gq, v);
+                const int64_t row = It * TW + R0 + 16 * x + r, cl = Jt * TW + C0 + 16 * y + M::drow(gq, v);
                 if (row < N && cl < N) {
                     double *dst = g.S + cl * g.ldS + row;
                     const double sum = (double)acc[x][y][v];
@@ -1036,7 +1048,8 @@ hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t
                                    hipStream_t st) {
     const int64_t nk = g.n * K;
     if (slab < 32 || slab > 65535 || ldV < (int64_t)g.NT * 64 || ldV % 64 != 0) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((int64_t)g.NT * (g.NT + 1) / 2));
+    const int64_t T2 = (g.NT + 1) / 2;   // 128-wide tiles
+    const dim3 grid((unsigned)(T2 * (T2 + 1) / 2));
     for (int64_t k0 = 0; k0 < nk; k0 += slab) {
         const int64_t k1 = std::min(nk, k0 + slab);
         const dim3 gv((unsigned)std::min<int64_t>((ldV + 255) / 256, 64), (unsigned)(k1 - k0));
@@ -1044,12 +1057,12 @@ hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t
         if (f32) {
             float *Vf = (float *)V;
             DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_vgen<KK, float>), gv, dim3(256), 0, st, g, k0, k1, Vf, ldV));
-            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, true>), grid, dim3(256), 0, st, g, (const float *)Vf, ldV,
+            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, true>), grid, dim3(512), 0, st, g, (const float *)Vf, ldV,
                                                  k1 - k0, first));
         } else {
             double *Vd = (double *)V;
             DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_vgen<KK, double>), gv, dim3(256), 0, st, g, k0, k1, Vd, ldV));
-            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, false>), grid, dim3(256), 0, st, g, (const double *)Vd,
+            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, false>), grid, dim3(512), 0, st, g, (const double *)Vd,
                                                  ldV, k1 - k0, first));
         }
     }
