@@ -1079,6 +1079,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
     IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, c.s.V, p.ldX, p.n, c.s.part));
     HCK(finish(c, c.s.part, PRS, p.Bx, K * K, 0u, c.s.sc->XtV));
     const bool reuse = !exact && c.s.S_gn_valid;
+    bool formed = false;
     if (!reuse) {
         static const int zero = 0;
         HCK(hipMemcpyAsync(&c.s.sc->chol_fail, &zero, sizeof(int), hipMemcpyHostToDevice, c.st));
@@ -1131,14 +1132,10 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
         nmf_status st = cholesky(c, N);
         if (st != NMF_OK) return st;
         prof_end(c, 2);
-        int fail = 0;
-        HCK(hipMemcpyAsync(&fail, &c.s.sc->chol_fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
-        HCK(hipStreamSynchronize(c.st));
-        c.s.S_gn_valid = false;
-        if (fail) {
-            d.ok = false;
-            return NMF_OK;
-        }
+        // the factorisation's failure flag is read with the direction's
+        // scalars (one host round trip less): a failed factor yields a
+        // direction that is discarded
+        formed = true;
         c.s.S_gn_valid = !exact;
     }
     if (exact) {
@@ -1203,9 +1200,16 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
                                            p.By));
     }
     HCK(finish(c, c.s.part, PRS, p.By + p.Bx, 3, 0x6u, c.s.sc->out));
+    int fail = 0;
+    if (formed) HCK(hipMemcpyAsync(&fail, &c.s.sc->chol_fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
     double h[3];
-    st = read_out(c, h, 3);
+    st = read_out(c, h, 3);   // synchronises the stream: `fail` is final here
     if (st != NMF_OK) return st;
+    if (fail) {
+        c.s.S_gn_valid = false;
+        d.ok = false;
+        return NMF_OK;
+    }
     d.ok = true;
     d.slope = h[0];
     d.a1 = h[1] < 1.0 ? h[1] : 1.0;
