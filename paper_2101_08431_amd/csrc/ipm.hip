@@ -663,8 +663,10 @@ __global__ __launch_bounds__(STHR) void k_ls_quartic(AnlsParams p, IpmArgs ia, d
 // Barrier sums for NTRIAL steps a_t = a_base / 2^t:
 // record[t] = sum over the block's entries of log1p(a_t d / v).
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_ls_barrier(AnlsParams p, IpmArgs ia, double a_base) {
+__global__ __launch_bounds__(NTHR) void k_ls_barrier(AnlsParams p, IpmArgs ia, const double *a1dev, double a_base) {
     __shared__ double lds[NTHR];
+    // first batch: a_base = min(a1, 1) from the direction's step limit on the device
+    if (a1dev) a_base = a1dev[0] < 1.0 ? a1dev[0] : 1.0;
     const Side sd = side_of<K>(p, ia, true);
     double acc[NTRIAL];
 #pragma unroll
@@ -1064,12 +1066,18 @@ nmf_status solve_S(Ctx &c, int64_t N) {
 struct Dir {
     bool ok;        // false: Cholesky of S failed
     double slope, a1, a2;
+    bool formed = false;   // S was formed and factored for this direction (its failure flag is pending)
 };
+
+// Slots of IpmScal::out for the scalars of one inner iteration, read in one
+// copy: the direction's (slope, step limits), the line search's quartic
+// coefficients and the first batch of barrier trials.
+constexpr int OUT_DIR = 0, OUT_QUART = 8, OUT_BAR = 16;
 
 // Newton direction of eq. (12) at the current point with barrier parameter
 // mu (0 for the predictor) and the Hessian eq. (26) (exact = false) or eq.
 // (27) (exact = true).  Leaves dx, dy, dr, ds and the step-rule quantities.
-nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
+nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool defer = false) {
     const AnlsParams &p = c.p;
     const int K = c.K;
     const int64_t N = p.m * K;
@@ -1199,7 +1207,13 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
         IPM_KS(K, hipLaunchKernelGGL((k_post_x<KK, false>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, tau,
                                            p.By));
     }
-    HCK(finish(c, c.s.part, PRS, p.By + p.Bx, 3, 0x6u, c.s.sc->out));
+    HCK(finish(c, c.s.part, PRS, p.By + p.Bx, 3, 0x6u, c.s.sc->out + OUT_DIR));
+    if (defer) {
+        // the caller reads the scalars and the failure flag with the line
+        // search's (probe())
+        d.formed = formed;
+        return NMF_OK;
+    }
     int fail = 0;
     if (formed) HCK(hipMemcpyAsync(&fail, &c.s.sc->chol_fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
     double h[3];
@@ -1219,22 +1233,55 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
 
 // Armijo backtracking (eq. (13)) on the closed-form quartic plus barrier sums.
 // Returns the accepted step in *al.
-nmf_status line_search(Ctx &c, const Dir &d, double mu, double *al) {
+// Enqueues the line search's quartic (k_ls_quartic) and its first batch of
+// NTRIAL barrier trials from the deferred direction's step limit, then reads
+// the direction's scalars, its factorisation flag, the quartic and the trials
+// in one host round trip.
+nmf_status probe(Ctx &c, Dir &d, double *q, double *bar) {
     const AnlsParams &p = c.p;
     double *lspart = c.s.fpart;   // reused: Tn*Sx records of 8
     IPM_KS(c.K, hipLaunchKernelGGL(k_ls_quartic<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, c.ia, lspart));
-    HCK(finish(c, lspart, 8, p.Tn * p.Sx, 6, 0u, c.s.sc->out));
-    double q[6];
-    nmf_status st = read_out(c, q, 6);
+    HCK(finish(c, lspart, 8, p.Tn * p.Sx, 6, 0u, c.s.sc->out + OUT_QUART));
+    IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia,
+                                   (const double *)(c.s.sc->out + OUT_DIR + 1), 0.0));
+    HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out + OUT_BAR));
+    int fail = 0;
+    if (d.formed) HCK(hipMemcpyAsync(&fail, &c.s.sc->chol_fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
+    double h[OUT_BAR + NTRIAL];
+    nmf_status st = read_out(c, h, OUT_BAR + NTRIAL);   // synchronises: `fail` is final here
     if (st != NMF_OK) return st;
+    for (int t = 0; t < 6; ++t) q[t] = h[OUT_QUART + t];
+    for (int t = 0; t < NTRIAL; ++t) bar[t] = h[OUT_BAR + t];
+    if (fail) {
+        c.s.S_gn_valid = false;
+        d.ok = false;
+        return NMF_OK;
+    }
+    d.ok = true;
+    d.slope = h[OUT_DIR];
+    d.a1 = h[OUT_DIR + 1] < 1.0 ? h[OUT_DIR + 1] : 1.0;
+    d.a2 = h[OUT_DIR + 2] < 1.0 ? h[OUT_DIR + 2] : 1.0;
+    return NMF_OK;
+}
+
+// Armijo backtracking (eq. (13)) on the closed-form quartic q plus batched
+// barrier sums; the first batch (bar) comes from probe().  Returns the
+// accepted step in *al.
+nmf_status line_search(Ctx &c, const Dir &d, double mu, const double *q, const double *bar0, double *al) {
+    const AnlsParams &p = c.p;
     const int maxb = c.o.max_backtracks;
     for (int t0 = 0; t0 <= maxb; t0 += NTRIAL) {
-        const double abase = d.a1 / ldexp(1.0, t0);
-        IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, abase));
-        HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out));
-        double bar[NTRIAL];
-        st = read_out(c, bar, NTRIAL);
-        if (st != NMF_OK) return st;
+        double barv[NTRIAL];
+        const double *bar = bar0;
+        if (t0 > 0) {
+            const double abase = d.a1 / ldexp(1.0, t0);
+            IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia,
+                                           (const double *)nullptr, abase));
+            HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out));
+            nmf_status st = read_out(c, barv, NTRIAL);
+            if (st != NMF_OK) return st;
+            bar = barv;
+        }
         for (int t = 0; t < NTRIAL && t0 + t <= maxb; ++t) {
             const double a = d.a1 / ldexp(1.0, t0 + t);
             const double dq = 0.5 * (2.0 * a * q[1] + a * a * (q[2] + 2.0 * q[3]) + 2.0 * a * a * a * q[4] +
@@ -1271,8 +1318,11 @@ nmf_status inner_iteration(Ctx &c) {
     d.ok = false;
     bool have = false;
     nmf_status st;
+    double q[6], bar[NTRIAL];
     if (s.flag == 1 && c.o.exact_hessian_switch) {
-        st = direction(c, mu, true, c.o.tau, d);
+        st = direction(c, mu, true, c.o.tau, d, true);
+        if (st != NMF_OK) return st;
+        st = probe(c, d, q, bar);
         if (st != NMF_OK) return st;
         if (d.ok && d.slope < 0.0) {
             have = true;
@@ -1283,7 +1333,11 @@ nmf_status inner_iteration(Ctx &c) {
         }
     }
     if (!have) {
-        st = direction(c, mu, false, c.o.tau, d);
+        d = Dir();
+        d.ok = false;
+        st = direction(c, mu, false, c.o.tau, d, true);
+        if (st != NMF_OK) return st;
+        st = probe(c, d, q, bar);
         if (st != NMF_OK) return st;
         if (!d.ok) {
             s.err = "Cholesky factorisation of the Gauss-Newton Schur matrix failed";
@@ -1291,7 +1345,7 @@ nmf_status inner_iteration(Ctx &c) {
         }
     }
     double al = 0.0;
-    st = line_search(c, d, mu, &al);
+    st = line_search(c, d, mu, q, bar, &al);
     if (st != NMF_OK) return st;
     s.iters += 1;
     s.at_mu += 1;
