@@ -690,8 +690,8 @@ __device__ __forceinline__ void inner_update(double *T, double *Lf, int j, int i
 
 // Step kt (-1 .. NT-2) of the right-looking factorisation by 64-wide block
 // columns, for column c = kt + 1; 512 threads per block.
-//   Tiles right of column c (c < tj <= ti): A_ij -= L_i,kt L_j,kt^T, each of
-//   the 8 waves a 16 x 32 part.
+//   Tiles right of column c (c < tj <= ti): A_ij -= L_i,kt L_j,kt^T, in 2 x 2
+//   groups of tiles per block, each of the 8 waves a 32 x 64 part.
 //   Tiles of column c (blocks 0 .. NT-c-1, tile (c + b, c)): waves 0-3 update
 //   their own tile, rows 16 w each (kt >= 0); waves 4-7 update the diagonal
 //   tile (c, c) and factor it in LDS, 16-wide block column by block column
@@ -711,62 +711,71 @@ __global__ __launch_bounds__(512, 4) void k_chol_step(CholArgs g, int kt) {
     const int NT = g.NT;
     const int bid = blockIdx.x;
     const int npanel = NT - c;
-    int ti, tj;
-    if (bid < npanel) {
-        ti = c + bid;
-        tj = c;
-    } else {
-        // trailing tiles c < tj <= ti < NT, column by column
-        int rr = bid - npanel;
-        tj = c + 1;
-        while (rr >= NT - tj) {
-            rr -= NT - tj;
-            ++tj;
-        }
-        ti = tj + rr;
-    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
     double *S = g.S;
     const int64_t ldS = g.ldS;
-    const int64_t rb = (int64_t)ti * 64, cb = (int64_t)tj * 64, db = (int64_t)c * 64, kb = (int64_t)kt * 64;
-    // acc[y][v] is tile entry (16 x + r, 16 y + gq + 4 v): products are formed
+    const int64_t db = (int64_t)c * 64, kb = (int64_t)kt * 64;
+    // acc[..][v] is tile entry (16 x + r, 16 y + gq + 4 v): products are formed
     // transposed (D = L_j L_i^T block by block), so that 16 lanes hold 16
     // consecutive rows of one column.
-    if (tj != c) {
-        const int x = wave & 3, y0 = (wave >> 2) * 2;
-        v4d acc[2];
+    if (bid >= npanel) {
+        // trailing tiles c < tj <= ti < NT in 2 x 2 groups (128 x 128: each
+        // panel entry is loaded for two tiles), groups column by column; wave w
+        // updates rows 32 (w % 4) and columns 64 (w / 4) of the group, which lie
+        // in one tile (skipped past the last tile or above the diagonal)
+        const int G = (NT - c) / 2;   // groups per side: ceil((NT - c - 1) / 2)
+        int rr = bid - npanel, GJ = 0;
+        while (rr >= G - GJ) {
+            rr -= G - GJ;
+            ++GJ;
+        }
+        const int GI = GJ + rr;
+        const int R0 = (wave & 3) * 32, C0 = (wave >> 2) * 64;
+        const int ti = c + 1 + 2 * GI + (R0 >> 6), tj = c + 1 + 2 * GJ + (C0 >> 6);
+        if (ti >= NT || tj >= NT || ti < tj) return;
+        const int64_t rb = (int64_t)ti * 64 + (R0 & 63), cb = (int64_t)tj * 64;
+        v4d acc[2][4];
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[y][v] = S[(cb + 16 * (y0 + y) + gq + 4 * v) * ldS + rb + 16 * x + r];
-        // four matrix-core k-steps per group, the next group loaded ahead
-        double qa[2][4][2], qb[2][4];
+            for (int y = 0; y < 4; ++y)
 #pragma unroll
-        for (int h = 0; h < 5; ++h) {
-            if (h < 4) {
+                for (int v = 0; v < 4; ++v) acc[x][y][v] = S[(cb + 16 * y + gq + 4 * v) * ldS + rb + 16 * x + r];
+        // two matrix-core k-steps per group, the next group loaded ahead
+        double qa[2][2][4], qb[2][2][2];
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    const double *col = S + (kb + 16 * h + 4 * s4 + gq) * ldS;
-                    qb[h & 1][s4] = -col[rb + 16 * x + r];
-                    qa[h & 1][s4][0] = col[cb + 16 * y0 + r];
-                    qa[h & 1][s4][1] = col[cb + 16 * y0 + 16 + r];
+        for (int h = 0; h < 9; ++h) {
+            if (h < 8) {
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const double *col = S + (kb + 8 * h + 4 * s2 + gq) * ldS;
+#pragma unroll
+                    for (int x = 0; x < 2; ++x) qb[h & 1][s2][x] = -col[rb + 16 * x + r];
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) qa[h & 1][s2][y] = col[cb + 16 * y + r];
                 }
             }
             if (h > 0) {
                 const int hb = (h - 1) & 1;
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4)
+                for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-                    for (int y = 0; y < 2; ++y) acc[y] = mfma16(qa[hb][s4][y], qb[hb][s4], acc[y]);
+                    for (int x = 0; x < 2; ++x)
+#pragma unroll
+                        for (int y = 0; y < 4; ++y) acc[x][y] = mfma16(qa[hb][s2][y], qb[hb][s2][x], acc[x][y]);
             }
         }
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) S[(cb + 16 * (y0 + y) + gq + 4 * v) * ldS + rb + 16 * x + r] = acc[y][v];
+            for (int y = 0; y < 4; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) S[(cb + 16 * y + gq + 4 * v) * ldS + rb + 16 * x + r] = acc[x][y][v];
         return;
     }
+    const int ti = c + bid;
+    const int64_t rb = (int64_t)ti * 64;
     const bool diag = ti == c;
     const bool own = wave < 4;                 // waves 0-3: own tile; 4-7: tile (c, c)
     const int x = wave & 3;
@@ -1113,8 +1122,8 @@ hipError_t launch_cholesky(const CholArgs &g, hipStream_t st) {
     const int NT = g.NT;
     for (int kt = -1; kt <= NT - 2; ++kt) {
         const int c = kt + 1;
-        const int R = NT - c - 1;
-        const int64_t blocks = (int64_t)(NT - c) + (kt >= 0 ? (int64_t)R * (R + 1) / 2 : 0);
+        const int G = (NT - c) / 2;   // 2 x 2 groups of trailing tiles per side
+        const int64_t blocks = (int64_t)(NT - c) + (kt >= 0 ? (int64_t)G * (G + 1) / 2 : 0);
         hipLaunchKernelGGL(k_chol_step, dim3((unsigned)blocks), dim3(512), 0, st, g, kt);
     }
     return hipGetLastError();
