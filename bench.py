@@ -405,10 +405,17 @@ def batching_section(count, sweeps):
     e1.record(b.stream)
     b.sync()
     batch_ms = e0.elapsed_time(e1) / sweeps
+    # the same batched sweeps launched eagerly (no graph)
+    e0.record(b.stream)
+    b.step(sweeps, graph=False)
+    e1.record(b.stream)
+    b.sync()
+    eager_ms = e0.elapsed_time(e1) / sweeps
     b.close()
     return {"problems": count, "column_solves_per_sweep": solves,
             "plain_ms_per_sweep": plain_ms, "plain_solves_per_s": solves / (plain_ms * 1e-3),
             "batched_ms_per_sweep": batch_ms, "batched_solves_per_s": solves / (batch_ms * 1e-3),
+            "batched_eager_ms_per_sweep": eager_ms,
             "speedup": plain_ms / batch_ms, "autotuned_waves": waves}
 
 
