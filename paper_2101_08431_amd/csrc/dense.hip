@@ -607,25 +607,24 @@ __global__ void k_axpy(double *y, const double *x, int64_t count) {
 // ------------------------------------------------------------- Cholesky of S
 constexpr int LDT = 65;   // LDS row stride (doubles) of a 64 x 64 tile
 
-// Inverse W = L^-1 of the factor L of the 16 x 16 diagonal block j of the
-// tile T (row-major, stride LDT), by one wave.  Lane p = lane % 16 holds row p
-// of the block in a[]: step c takes pivot c from lane c, scales column c and
-// applies it to the rows below (right-looking); lanes above row c compute
-// values of the upper triangle that nothing reads, so no step needs a lane
-// mask.  The same steps run the forward substitution L w = e_p for column p
-// of W in w[] (entry c is final at step c), reusing the broadcast column
-// entries.  W goes to the same block of Lf; L itself is not kept.  A pivot
-// that is not positive sets *bad (the factor is then not used) and is
-// replaced by 1.
-__device__ __forceinline__ void potrf_inv16(const double *T, double *Lf, int j, int *bad) {
-    const int lane = threadIdx.x & 63, p = lane & 15;
+// Block column j of the factor of the 64 x 64 tile T (row-major, stride LDT)
+// as one tall panel (rows 16 j .. 63, columns 16 j .. 16 j + 15), by one wave:
+// lane p holds row 16 j + p in a[]; step c takes pivot c from lane c, scales
+// column c and applies it to the row's later columns (right-looking), so the
+// rows below the diagonal block (the sub-panels L_ij, i > j) come out of the
+// same broadcasts as the diagonal block L_jj.  Lanes above a step's row
+// compute values of the upper triangle that nothing reads, so no step needs a
+// lane mask.  The column goes to Lf (L_jj with zeros above its diagonal).  A
+// pivot that is not positive, or not finite, sets *bad (the factor is then
+// not used) and is replaced by 1.
+__device__ __forceinline__ void potrf_panel16(const double *T, double *Lf, int j, int *bad) {
+    const int lane = threadIdx.x & 63;
+    const int rows = 64 - 16 * j;
+    const int p = lane < rows ? lane : rows - 1;
     const double *Trow = T + (16 * j + p) * LDT + 16 * j;
-    double a[16], w[16];
+    double a[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        a[q] = Trow[q];
-        w[q] = (q == p) ? 1.0 : 0.0;
-    }
+    for (int q = 0; q < 16; ++q) a[q] = Trow[q];
     // fmin drops a NaN operand, so the pivots are also summed: a NaN or an
     // infinity among them makes the sum non-finite
     double dmin = 1.0, dsum = 0.0;
@@ -637,52 +636,53 @@ __device__ __forceinline__ void potrf_inv16(const double *T, double *Lf, int j, 
         const double s = rsqrt_nr(d > 0.0 ? d : 1.0);
         const double l = a[c] * s;   // row p of column c; on lane c, sqrt(d)
         a[c] = l;
-        w[c] *= s;
 #pragma unroll
-        for (int jj = c + 1; jj < 16; ++jj) {
-            const double ljc = lane_read(l, jj);   // L[jj][c]
-            a[jj] = fma(-l, ljc, a[jj]);
-            w[jj] = fma(-ljc, w[c], w[jj]);
-            // pins the update of w to this step (otherwise it sinks to the
-            // end of the loop and every broadcast value has to be kept)
-            asm volatile("" : "+v"(w[jj]));
-        }
+        for (int jj = c + 1; jj < 16; ++jj) a[jj] = fma(-l, lane_read(l, jj), a[jj]);
     }
-    if (lane < 16) {
+    if (lane < rows) {
+        double *Lrow = Lf + (16 * j + p) * LDT + 16 * j;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) Lf[(16 * j + q) * LDT + 16 * j + p] = w[q];
+        for (int q = 0; q < 16; ++q) Lrow[q] = (p >= 16 || q <= p) ? a[q] : 0.0;
     }
     if ((!(dmin > 0.0) || !isfinite(dsum)) && lane == 0) *bad = 1;
 }
 
-// Block column j of the 64 x 64 factor, for row block i > j (one wave): the
-// sub-panels L_lj = T_lj W_jj^T for j < l <= i (L_ij stored in Lf; the others
-// are recomputed here, bit-identical to their owners' copies, so that no
-// second barrier is needed), then T_il -= L_ij L_lj^T for j < l <= i.  The
-// products are formed transposed (D[q][p] = X[p][q]), so that a product's
-// output registers are the next product's operands as they stand.
-__device__ __forceinline__ v4d sub_panel(const double *T, const double *Lf, int j, int l) {
-    const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
-    v4d d = {0.0, 0.0, 0.0, 0.0};
+// W = L_jj^-1 for the 16 x 16 diagonal block j of the factor in Lf (lower,
+// zeros above), by one wave: lane q < 16 solves L w = e_q by forward
+// substitution (the entries of L are read by every lane alike, one LDS
+// broadcast each).  W goes to the diagonal block j of T, which the
+// factorisation no longer reads.
+__device__ __forceinline__ void inverse16(double *T, const double *Lf, int j) {
+    const int q = threadIdx.x & 15;
+    const double *L = Lf + (16 * j) * LDT + 16 * j;
+    double w[16];
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-        d = mfma16(Lf[(16 * j + r) * LDT + 16 * j + 4 * s + gq], T[(16 * l + r) * LDT + 16 * j + 4 * s + gq], d);
-    return d;
+    for (int p = 0; p < 16; ++p) {
+        double v = (p == q) ? 1.0 : 0.0;
+#pragma unroll
+        for (int r = 0; r < p; ++r) v = fma(-L[p * LDT + r], w[r], v);
+        w[p] = v / L[p * LDT + p];
+    }
+    if ((threadIdx.x & 63) < 16) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) T[(16 * j + p) * LDT + 16 * j + q] = w[p];
+    }
 }
 
-__device__ __forceinline__ void inner_update(double *T, double *Lf, int j, int i) {
+// T_il -= L_ij L_lj^T for j < l <= i (one wave, row block i), with the
+// sub-panels from Lf.  The product is formed transposed (D[q][p] = X[p][q]).
+__device__ __forceinline__ void panel_update(double *T, const double *Lf, int j, int i) {
     const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
-    const v4d Li = sub_panel(T, Lf, j, i);
+    double li[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Lf[(16 * i + r) * LDT + 16 * j + gq + 4 * v] = Li[v];
+    for (int s = 0; s < 4; ++s) li[s] = Lf[(16 * i + r) * LDT + 16 * j + 4 * s + gq];
     for (int l = j + 1; l <= i; ++l) {
-        const v4d Ll = (l == i) ? Li : sub_panel(T, Lf, j, l);
         double *Tb = T + (16 * i + r) * LDT + 16 * l + gq;
         v4d acc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] = Tb[4 * v];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = mfma16(-Ll[s], Li[s], acc);
+        for (int s = 0; s < 4; ++s) acc = mfma16(-Lf[(16 * l + r) * LDT + 16 * j + 4 * s + gq], li[s], acc);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Tb[4 * v] = acc[v];
     }
@@ -843,10 +843,13 @@ __global__ __launch_bounds__(512, 4) void k_chol_step(CholArgs g, int kt) {
     __syncthreads();
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {
-        if (wave == 4 + j) potrf_inv16(T, Lf, j, g.fail);
+        if (wave == 4 + j) potrf_panel16(T, Lf, j, g.fail);
         __syncthreads();
-        if (!own && x > j) inner_update(T, Lf, j, x);
+        if (!own && x > j) panel_update(T, Lf, j, x);
+        __syncthreads();
     }
+    // inverses of the four diagonal blocks, one per panel wave, into T
+    if (own) inverse16(T, Lf, x);
     __syncthreads();
     if (!own) return;
     v4d X[4];
@@ -859,7 +862,7 @@ __global__ __launch_bounds__(512, 4) void k_chol_step(CholArgs g, int kt) {
             for (int s = 0; s < 4; ++s) t = mfma16(-Lf[(16 * y + r) * LDT + 16 * rr + 4 * s + gq], X[rr][s], t);
         v4d z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) z = mfma16(Lf[(16 * y + r) * LDT + 16 * y + 4 * s + gq], t[s], z);
+        for (int s = 0; s < 4; ++s) z = mfma16(T[(16 * y + r) * LDT + 16 * y + 4 * s + gq], t[s], z);
         X[y] = z;
     }
     if (diag) {
