@@ -628,14 +628,22 @@ __device__ __forceinline__ void potrf_panel16(const double *T, double *Lf, int j
     // fmin drops a NaN operand, so the pivots are also summed: a NaN or an
     // infinity among them makes the sum non-finite
     double dmin = 1.0, dsum = 0.0;
+    double d = lane_read(a[0], 0);
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-        const double d = lane_read(a[c], c);
         dmin = fmin(dmin, d);
         dsum += d;
         const double s = rsqrt_nr(d > 0.0 ? d : 1.0);
         const double l = a[c] * s;   // row p of column c; on lane c, sqrt(d)
         a[c] = l;
+        if (c + 1 < 16) {
+            // the next pivot first: lane c+1 updates its own diagonal entry with
+            // its own l (the value every other lane receives by broadcast), so
+            // the chain of pivots carries one broadcast per step
+            const int c1 = c + 1 < 16 ? c + 1 : 15;
+            const double dn = fma(-l, l, a[c1]);
+            d = lane_read(dn, c1);
+        }
 #pragma unroll
         for (int jj = c + 1; jj < 16; ++jj) a[jj] = fma(-l, lane_read(l, jj), a[jj]);
     }
