@@ -523,6 +523,8 @@ def main():
                     help="only run the passive-set grouping section")
     ap.add_argument("--mixed-only", action="store_true",
                     help="only run the mixed-precision interior-point section")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only run the stage-2 section at 10000x2000x10")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 10 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -554,6 +556,9 @@ def main():
         return
     if args.mixed_only:
         print(json.dumps(mixed_section()), flush=True)
+        return
+    if args.large_only:
+        print(json.dumps(ipm_large_section()), flush=True)
         return
     M, X0, Y0 = synth.make(args.workload, 0)
     n, m = M.shape

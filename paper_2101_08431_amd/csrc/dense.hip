@@ -104,21 +104,39 @@ __device__ __forceinline__ void schur_store(const SchurArgs &g, int64_t jt, int6
     }
 }
 
+// Work split of the Gauss-Newton formation for rank K: the K(K+1)/2 products
+// (a, b) are summed in `nch` chunks (one wave per tile pair and chunk), Z
+// operands of `ru` rows are prefetched, and X_ia X_ib of `ch` rows are staged
+// per block.  Chosen as the fewest chunks whose accumulators, prefetched
+// operands and staging registers fit 256 registers per lane (two waves per
+// SIMD hide each other's load and matrix-core latency; at K = 10 that is 1.56x
+// faster than one wave per SIMD with half the chunks), with `ch` rows of
+// products at most 4 registers per thread.
+struct GnPlan { int nch, ru, ch; };
+constexpr GnPlan kGnPlan[17] = {
+    {1, 4, 64}, {1, 4, 64}, {1, 4, 64}, {1, 4, 64}, {1, 4, 64}, {1, 4, 64}, {1, 2, 48}, {2, 4, 36}, {2, 2, 28},
+    {3, 2, 20}, {4, 2, 16}, {4, 2, 12}, {5, 2, 12}, {6, 2, 8}, {7, 2, 8}, {8, 2, 8}, {8, 2, 4}};
+
 // One wave per unit (tile pair, (a,b) chunk); the four waves of a block
 // share a row split, whose rows i they sum of X_ia X_ib C_i[J, L], C_i[J, L]
 // from KS matrix-core steps over the (zero-padded) components of Z_i.  The
 // X_ia X_ib of CH rows at a time are staged in LDS (one copy per block,
-// broadcast reads); the Z operands of the next RU rows are loaded while the
-// current RU rows are summed.
+// broadcast reads; the next chunk's are loaded into registers while the
+// current chunk is summed, two LDS buffers, one barrier per chunk); the Z
+// operands of the next RU rows are loaded while the current RU rows are summed,
+// across chunk boundaries, and the matrix-core product of the next row is
+// issued before the vector updates of the current one.
 template <int K>
 __global__ __launch_bounds__(256) void k_schur_gn(SchurArgs g) {
     constexpr int NL = K * (K + 1) / 2;
-    constexpr int NCH = (NL + 35) / 36;
+    constexpr int NCH = kGnPlan[K].nch;
     constexpr int CS = (NL + NCH - 1) / NCH;
     constexpr int KS = zpad(K) / 4;
-    constexpr int RU = 4;
-    constexpr int CH = 32;
-    __shared__ double xs[CH * NL];
+    constexpr int RU = kGnPlan[K].ru;
+    constexpr int CH = kGnPlan[K].ch;
+    constexpr int XR = (CH * NL + 255) / 256;
+    static_assert(CH % RU == 0, "row groups must not straddle chunks");
+    __shared__ double xs[2][CH * NL];
     const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int p = (int)(blockIdx.x % g.P);
@@ -144,57 +162,90 @@ __global__ __launch_bounds__(256) void k_schur_gn(SchurArgs g) {
     for (int t = 0; t < CS; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[t][v] = 0.0;
-    for (int64_t c0 = i0; c0 < i1; c0 += CH) {
-        const int nr = (int)min((int64_t)CH, i1 - c0);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < nr * NL; idx += 256) xs[idx] = g.XX[c0 * NL + idx];
-        __syncthreads();
-        if (!active) continue;
+    if (i0 < i1) {   // block-uniform
+        {
+            const int nr = (int)min((int64_t)CH, i1 - i0);
+            for (int idx = threadIdx.x; idx < nr * NL; idx += 256) xs[0][idx] = g.XX[i0 * NL + idx];
+        }
+        // operands of the current and the next RU rows (rows clamped into
+        // the split: loads stay in range)
         double av[RU][KS], bv[RU][KS], an[RU][KS], bn[RU][KS];
+        if (active) {
 #pragma unroll
-        for (int uu = 0; uu < RU; ++uu) {
-            const double *zi = g.Z + (c0 + min(uu, nr - 1)) * zstride;
+            for (int uu = 0; uu < RU; ++uu) {
+                const double *zi = g.Z + min(i0 + uu, i1 - 1) * zstride;
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                av[uu][s] = zi[offA[s]];
-                bv[uu][s] = zi[offB[s]];
+                for (int s = 0; s < KS; ++s) {
+                    av[uu][s] = zi[offA[s]];
+                    bv[uu][s] = zi[offB[s]];
+                }
             }
         }
-        for (int rb = 0; rb < nr; rb += RU) {
-            // next group (rows clamped into the chunk: loads stay in range)
+        __syncthreads();
+        int buf = 0;
+        for (int64_t c0 = i0; c0 < i1; c0 += CH) {
+            const int nr = (int)min((int64_t)CH, i1 - c0);
+            const int64_t c1 = c0 + CH;
+            const int nr1 = (int)max((int64_t)0, min((int64_t)CH, i1 - c1));
+            double xn[XR];
 #pragma unroll
-            for (int uu = 0; uu < RU; ++uu) {
-                const double *zi = g.Z + (c0 + min(rb + RU + uu, nr - 1)) * zstride;
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    an[uu][s] = zi[offA[s]];
-                    bn[uu][s] = zi[offB[s]];
-                }
+            for (int q = 0; q < XR; ++q) {
+                const int idx = (int)threadIdx.x + 256 * q;
+                xn[q] = idx < nr1 * NL ? g.XX[c1 * NL + idx] : 0.0;
             }
+            if (active) {
+                const double *xb = xs[buf];
+                for (int rb = 0; rb < nr; rb += RU) {
 #pragma unroll
-            for (int uu = 0; uu < RU; ++uu) {
-                if (rb + uu < nr) {   // wave-uniform
-                    v4d c = {0.0, 0.0, 0.0, 0.0};
+                    for (int uu = 0; uu < RU; ++uu) {
+                        const double *zi = g.Z + min(c0 + rb + RU + uu, i1 - 1) * zstride;
 #pragma unroll
-                    for (int s = 0; s < KS; ++s) c = mfma16(av[uu][s], bv[uu][s], c);
-                    const double *xr = xs + (rb + uu) * NL + t0;
-#pragma unroll
-                    for (int t = 0; t < CS; ++t) {
-                        if (t0 + t < NL) {
-                            const double w = xr[t];
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) acc[t][v] = fma(c[v], w, acc[t][v]);
+                        for (int s = 0; s < KS; ++s) {
+                            an[uu][s] = zi[offA[s]];
+                            bn[uu][s] = zi[offB[s]];
                         }
                     }
+                    v4d cn = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int s = 0; s < KS; ++s) cn = mfma16(av[0][s], bv[0][s], cn);
+#pragma unroll
+                    for (int uu = 0; uu < RU; ++uu) {
+                        const v4d c = cn;
+                        if (uu + 1 < RU) {
+                            cn = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                            for (int s = 0; s < KS; ++s) cn = mfma16(av[uu + 1][s], bv[uu + 1][s], cn);
+                        }
+                        if (rb + uu < nr) {   // wave-uniform
+                            const double *xr = xb + (rb + uu) * NL + t0;
+#pragma unroll
+                            for (int t = 0; t < CS; ++t) {
+                                if (t0 + t < NL) {
+                                    const double w = xr[t];
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) acc[t][v] = fma(c[v], w, acc[t][v]);
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int uu = 0; uu < RU; ++uu)
+#pragma unroll
+                        for (int s = 0; s < KS; ++s) {
+                            av[uu][s] = an[uu][s];
+                            bv[uu][s] = bn[uu][s];
+                        }
                 }
             }
+            // the other buffer was last read in the previous chunk, before
+            // the barrier that ended it
+            buf ^= 1;
 #pragma unroll
-            for (int uu = 0; uu < RU; ++uu)
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    av[uu][s] = an[uu][s];
-                    bv[uu][s] = bn[uu][s];
-                }
+            for (int q = 0; q < XR; ++q) {
+                const int idx = (int)threadIdx.x + 256 * q;
+                if (idx < nr1 * NL) xs[buf][idx] = xn[q];
+            }
+            __syncthreads();
         }
     }
     if (!active) return;
@@ -1042,8 +1093,7 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_lb(SolveArgs g) {
     }
 
 int schur_chunks(int K) {
-    const int NL = K * (K + 1) / 2;
-    return (NL + 35) / 36;
+    return (K >= 1 && K <= 16) ? kGnPlan[K].nch : 1;
 }
 
 hipError_t launch_xx(int K, const double *X, int64_t ldX, int64_t n, double *XX, hipStream_t st) {

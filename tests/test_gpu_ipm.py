@@ -78,6 +78,28 @@ def test_first_iterations_match_oracle(orc, name, seed, iters):
     assert rel(Rg, res.r) <= 1e-8 and rel(Sg.T, res.s) <= 1e-8
 
 
+@pytest.mark.parametrize("k", [6, 7, 8, 9, 12, 16])
+def test_first_iteration_across_ranks_matches_oracle(orc, k):
+    # the Gauss-Newton formation splits the K(K+1)/2 products (a, b) into a
+    # rank-dependent number of chunks, prefetch depth and staging height;
+    # these ranks cover every such plan (m = 70: a ragged last tile)
+    spec = dict(kind="pdf", n=150, m=70, k=k, sigma=1e-3, sigma_relative=True)
+    M, X, Yt = start_point(orc, spec, 3, sweeps=40)
+    print(f"case ipm first iteration pdf 150x70 k={k}", flush=True)
+    ctx = gpu_ctx(M, X, Yt, eps_tol=1e-10)
+    ctx.ipm_step(1)
+    Xg, Yg = ctx.factors()
+    Rg, Sg = ctx.duals()
+    ctx.close()
+    X1, Y1, r1, s1, mu1, rho1 = orc.transition(M, X, Yt, 1e-10)
+    res = orc.ipm(M, X1, Y1, r1, s1, mu1, rho1, orc.IPMOptions(eps_tol=1e-10, max_inner=1))
+    assert res.inner == 1
+    print(f"k={k} agreement: X {rel(Xg, res.X):.2e} Y {rel(Yg.T, res.Yt):.2e} "
+          f"R {rel(Rg, res.r):.2e} S {rel(Sg.T, res.s):.2e}", flush=True)
+    assert rel(Xg, res.X) <= 1e-8 and rel(Yg.T, res.Yt) <= 1e-8
+    assert rel(Rg, res.r) <= 1e-8 and rel(Sg.T, res.s) <= 1e-8
+
+
 @pytest.mark.parametrize("seed", [0, 1, 4])
 def test_full_solve_200x50x3_matches_oracle(orc, seed):
     M, X, Yt = start_point(orc, "pdf_200x50_k3", seed)
