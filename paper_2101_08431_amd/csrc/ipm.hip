@@ -108,16 +108,16 @@ __global__ __launch_bounds__(NTHR) void k_finish(const double *part, int stride,
     }
 }
 
-// out[a*ld + e] = sum_s part[(s*K + a)*ld + e], e < count.
+// out[a*ld + e] = sum_s part[(s*K + a)*ld + e], e < count; component a =
+// blockIdx.y (one thread per entry, the splits summed in order).
 __global__ __launch_bounds__(NTHR) void k_sum_splits(const double *part, int S, int K, int64_t ld, int64_t count,
                                                      double *out) {
     const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
+    const int a = (int)blockIdx.y;
     if (e >= count) return;
-    for (int a = 0; a < K; ++a) {
-        double v = 0.0;
-        for (int s = 0; s < S; ++s) v += part[((int64_t)s * K + a) * ld + e];
-        out[(int64_t)a * ld + e] = v;
-    }
+    double v = 0.0;
+    for (int s = 0; s < S; ++s) v += part[((int64_t)s * K + a) * ld + e];
+    out[(int64_t)a * ld + e] = v;
 }
 
 // ---------------------------------------------------------------- residual streams
@@ -662,29 +662,34 @@ __global__ __launch_bounds__(STHR) void k_ls_quartic(AnlsParams p, IpmArgs ia, d
 
 // Barrier sums for NTRIAL steps a_t = a_base / 2^t:
 // record[t] = sum over the block's entries of log1p(a_t d / v).
+// Trials t = blockIdx.y * LS_TG + (0 .. LS_TG - 1), step a_base 2^-t (exact
+// scalings); block b writes trial t of its entries to part[b * PRS + t].
+constexpr int LS_TG = 2;
+static_assert(NTRIAL % LS_TG == 0, "trial groups");
 template <int K>
 __global__ __launch_bounds__(NTHR) void k_ls_barrier(AnlsParams p, IpmArgs ia, const double *a1dev, double a_base) {
     __shared__ double lds[NTHR];
     // first batch: a_base = min(a1, 1) from the direction's step limit on the device
     if (a1dev) a_base = a1dev[0] < 1.0 ? a1dev[0] : 1.0;
+    const int t0 = (int)blockIdx.y * LS_TG;
     const Side sd = side_of<K>(p, ia, true);
-    double acc[NTRIAL];
+    double acc[LS_TG];
 #pragma unroll
-    for (int t = 0; t < NTRIAL; ++t) acc[t] = 0.0;
+    for (int t = 0; t < LS_TG; ++t) acc[t] = 0.0;
     if (sd.ok) {
 #pragma unroll
         for (int a = 0; a < K; ++a) {
             const int64_t o = (int64_t)a * sd.ld + sd.e;
             const double q = sd.d[o] / sd.v[o];
-            double at = a_base;
+            double at = ldexp(a_base, -t0);
 #pragma unroll
-            for (int t = 0; t < NTRIAL; ++t) {
+            for (int t = 0; t < LS_TG; ++t) {
                 acc[t] += log1p(at * q);
                 at *= 0.5;
             }
         }
     }
-    block_reduce_fn<NTRIAL>([&](int idx) { return acc[idx]; }, ia.part + (size_t)blockIdx.x * PRS, lds);
+    block_reduce_fn<LS_TG>([&](int idx) { return acc[idx]; }, ia.part + (size_t)blockIdx.x * PRS + t0, lds);
 }
 
 template <int K>
@@ -951,11 +956,11 @@ hipError_t point_products(Ctx &c) {
     hipError_t e;
     IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_rstream_x<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, p.Y,
                                           p.bx_part, c.s.fpart));
-    hipLaunchKernelGGL(k_sum_splits, g1(p.n), dim3(NTHR), 0, c.st, p.bx_part, p.Sx, c.K, p.ldX, p.n, c.s.gx);
+    hipLaunchKernelGGL(k_sum_splits, dim3(g1(p.n).x, (unsigned)(c.K)), dim3(NTHR), 0, c.st, p.bx_part, p.Sx, c.K, p.ldX, p.n, c.s.gx);
     if ((e = finish(c, c.s.fpart, 1, p.Tn * p.Sx, 1, 0u, &c.s.sc->f)) != hipSuccess) return e;
     IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_rstream_y<KK>, dim3(p.Tm, p.Sy), dim3(STHR), 0, c.st, p, p.X,
                                           p.by_part));
-    hipLaunchKernelGGL(k_sum_splits, g1(p.m), dim3(NTHR), 0, c.st, p.by_part, p.Sy, c.K, p.ldY, p.m, c.s.gy);
+    hipLaunchKernelGGL(k_sum_splits, dim3(g1(p.m).x, (unsigned)(c.K)), dim3(NTHR), 0, c.st, p.by_part, p.Sy, c.K, p.ldY, p.m, c.s.gy);
     IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, p.X, p.ldX, p.n, c.s.part));
     if ((e = finish(c, c.s.part, PRS, p.Bx, c.K * c.K, 0u, c.s.sc->GX)) != hipSuccess) return e;
     IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_outer<KK>, g1(p.m), dim3(NTHR), 0, c.st, p.Y, p.Y, p.ldY, p.m, c.s.part));
@@ -1149,7 +1154,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
     if (exact) {
         IPM_KS(K, hipLaunchKernelGGL(k_rstream_y<KK>, dim3(p.Tm, p.Sy), dim3(STHR), 0, c.st, p, c.s.V,
                                            p.by_part));
-        hipLaunchKernelGGL(k_sum_splits, g1(p.m), dim3(NTHR), 0, c.st, p.by_part, p.Sy, K, p.ldY, p.m, c.s.tY);
+        hipLaunchKernelGGL(k_sum_splits, dim3(g1(p.m).x, (unsigned)(K)), dim3(NTHR), 0, c.st, p.by_part, p.Sy, K, p.ldY, p.m, c.s.tY);
         IPM_KS(K, hipLaunchKernelGGL((k_rhs<KK, true>), g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu));
     } else {
         IPM_KS(K, hipLaunchKernelGGL((k_rhs<KK, false>), g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu));
@@ -1200,7 +1205,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
     if (exact) {
         IPM_KS(K, hipLaunchKernelGGL(k_rstream_x<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, c.s.dy,
                                            p.bx_part, (double *)nullptr));
-        hipLaunchKernelGGL(k_sum_splits, g1(p.n), dim3(NTHR), 0, c.st, p.bx_part, p.Sx, K, p.ldX, p.n, c.s.tX);
+        hipLaunchKernelGGL(k_sum_splits, dim3(g1(p.n).x, (unsigned)(K)), dim3(NTHR), 0, c.st, p.bx_part, p.Sx, K, p.ldX, p.n, c.s.tX);
         IPM_KS(K, hipLaunchKernelGGL((k_post_x<KK, true>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, tau,
                                            p.By));
     } else {
@@ -1242,7 +1247,7 @@ nmf_status probe(Ctx &c, Dir &d, double *q, double *bar) {
     double *lspart = c.s.fpart;   // reused: Tn*Sx records of 8
     IPM_KS(c.K, hipLaunchKernelGGL(k_ls_quartic<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, c.ia, lspart));
     HCK(finish(c, lspart, 8, p.Tn * p.Sx, 6, 0u, c.s.sc->out + OUT_QUART));
-    IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia,
+    IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By, NTRIAL / LS_TG), dim3(NTHR), 0, c.st, p, c.ia,
                                    (const double *)(c.s.sc->out + OUT_DIR + 1), 0.0));
     HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out + OUT_BAR));
     int fail = 0;
@@ -1275,7 +1280,7 @@ nmf_status line_search(Ctx &c, const Dir &d, double mu, const double *q, const d
         const double *bar = bar0;
         if (t0 > 0) {
             const double abase = d.a1 / ldexp(1.0, t0);
-            IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia,
+            IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By, NTRIAL / LS_TG), dim3(NTHR), 0, c.st, p, c.ia,
                                            (const double *)nullptr, abase));
             HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out));
             nmf_status st = read_out(c, barv, NTRIAL);
