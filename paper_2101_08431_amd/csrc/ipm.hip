@@ -30,6 +30,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <vector>
 
 #include "dense.h"
@@ -944,6 +945,14 @@ hipError_t finish(Ctx &c, const double *part, int stride, int nblk, int nval, un
     return hipGetLastError();
 }
 
+// The k_finish outputs, f and the failure words (the end of the scalar
+// block) in one device-to-host transfer and one synchronisation.
+nmf_status read_tail(Ctx &c, IpmScal &h) {
+    HCK(hipMemcpyAsync(h.out, c.s.sc->out, sizeof(IpmScal) - offsetof(IpmScal, out), hipMemcpyDeviceToHost, c.st));
+    HCK(hipStreamSynchronize(c.st));
+    return NMF_OK;
+}
+
 nmf_status read_out(Ctx &c, double *host, int nval) {
     HCK(hipMemcpyAsync(host, c.s.sc->out, sizeof(double) * nval, hipMemcpyDeviceToHost, c.st));
     HCK(hipStreamSynchronize(c.st));
@@ -974,18 +983,15 @@ nmf_status kkt(Ctx &c, double mu) {
     const AnlsParams &p = c.p;
     IPM_KS(c.K, hipLaunchKernelGGL(k_kkt<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, mu));
     HCK(finish(c, c.s.part, PRS, p.Bx + p.By, 4, 0u, c.s.sc->out));
-    double h[4];
-    nmf_status st = read_out(c, h, 4);
+    IpmScal hs;
+    nmf_status st = read_tail(c, hs);
     if (st != NMF_OK) return st;
-    struct { double f; int chol_fail, solve_fail; } tail;
-    static_assert(sizeof(tail) == sizeof(double) + 2 * sizeof(int), "IpmScal tail layout");
-    HCK(hipMemcpyAsync(&tail, &c.s.sc->f, sizeof(tail), hipMemcpyDeviceToHost, c.st));
-    HCK(hipStreamSynchronize(c.st));
-    if (tail.solve_fail) {
+    if (hs.solve_fail) {
         c.s.err = "a block of a triangular solve waited too long for the tile before it";
         return NMF_EDEVICE;
     }
-    const double f = tail.f;
+    const double *h = hs.out;
+    const double f = hs.f;
     c.s.S1 = h[0];
     c.s.SR = h[3];
     c.s.C0 = h[1];
@@ -1017,8 +1023,9 @@ void prof_end(Ctx &c, int slot) {
 nmf_status ensure_flags(Ctx &c) {
     if (c.s.flags_ready) return NMF_OK;
     HCK(launch_fill_u32(c.s.flags, 3 * (c.s.ldS / CB), 0u, c.st));
-    static const int zero = 0;
-    HCK(hipMemcpyAsync(&c.s.sc->solve_fail, &zero, sizeof(int), hipMemcpyHostToDevice, c.st));
+    // failure words are cleared by a fill kernel: no host memory, nothing
+    // that waits for the stream
+    HCK(launch_fill_u32((unsigned *)&c.s.sc->solve_fail, 1, 0u, c.st));
     c.s.flags_ready = true;
     c.s.epoch = 0;
     return NMF_OK;
@@ -1078,6 +1085,7 @@ struct Dir {
 // copy: the direction's (slope, step limits), the line search's quartic
 // coefficients and the first batch of barrier trials.
 constexpr int OUT_DIR = 0, OUT_QUART = 8, OUT_BAR = 16;
+static_assert(OUT_BAR + NTRIAL <= 4 * PARTW, "the finish outputs fit the scalar block");
 
 // Newton direction of eq. (12) at the current point with barrier parameter
 // mu (0 for the predictor) and the Hessian eq. (26) (exact = false) or eq.
@@ -1094,8 +1102,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
     const bool reuse = !exact && c.s.S_gn_valid;
     bool formed = false;
     if (!reuse) {
-        static const int zero = 0;
-        HCK(hipMemcpyAsync(&c.s.sc->chol_fail, &zero, sizeof(int), hipMemcpyHostToDevice, c.st));
+        HCK(launch_fill_u32((unsigned *)&c.s.sc->chol_fail, 1, 0u, c.st));
         IPM_KS(K, hipLaunchKernelGGL(k_zmat<KK>, dim3((unsigned)((p.n + ZRB - 1) / ZRB)), dim3(NTHR), 0, c.st,
                                            p, c.ia));
         const int64_t nt = (p.m + TJ - 1) / TJ;
@@ -1219,12 +1226,11 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
         d.formed = formed;
         return NMF_OK;
     }
-    int fail = 0;
-    if (formed) HCK(hipMemcpyAsync(&fail, &c.s.sc->chol_fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
-    double h[3];
-    st = read_out(c, h, 3);   // synchronises the stream: `fail` is final here
+    IpmScal hs;
+    st = read_tail(c, hs);
     if (st != NMF_OK) return st;
-    if (fail) {
+    const double *h = hs.out + OUT_DIR;
+    if (formed && hs.chol_fail) {
         c.s.S_gn_valid = false;
         d.ok = false;
         return NMF_OK;
@@ -1250,14 +1256,13 @@ nmf_status probe(Ctx &c, Dir &d, double *q, double *bar) {
     IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By, NTRIAL / LS_TG), dim3(NTHR), 0, c.st, p, c.ia,
                                    (const double *)(c.s.sc->out + OUT_DIR + 1), 0.0));
     HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out + OUT_BAR));
-    int fail = 0;
-    if (d.formed) HCK(hipMemcpyAsync(&fail, &c.s.sc->chol_fail, sizeof(int), hipMemcpyDeviceToHost, c.st));
-    double h[OUT_BAR + NTRIAL];
-    nmf_status st = read_out(c, h, OUT_BAR + NTRIAL);   // synchronises: `fail` is final here
+    IpmScal hs;
+    nmf_status st = read_tail(c, hs);
     if (st != NMF_OK) return st;
+    const double *h = hs.out;
     for (int t = 0; t < 6; ++t) q[t] = h[OUT_QUART + t];
     for (int t = 0; t < NTRIAL; ++t) bar[t] = h[OUT_BAR + t];
-    if (fail) {
+    if (d.formed && hs.chol_fail) {
         c.s.S_gn_valid = false;
         d.ok = false;
         return NMF_OK;
