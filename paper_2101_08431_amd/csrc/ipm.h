@@ -54,6 +54,7 @@ struct IpmState {
     double *opart = nullptr;                   // [OPS][K][ldY] operator partials
     double *Vex = nullptr;                     // [vrows][ldS] rows of the exact-Hessian factor V
     int64_t vrows = 0;
+    IpmScal *hsc = nullptr;                    // pinned host copy of the scalar block (owner: the context)
     unsigned *flags = nullptr;                 // [3][ldS/64] hand-over flags: factor, forward, backward solve
     unsigned epoch = 0;                        // last flag value used
     bool flags_ready = false;

@@ -947,9 +947,14 @@ hipError_t finish(Ctx &c, const double *part, int stride, int nblk, int nval, un
 
 // The k_finish outputs, f and the failure words (the end of the scalar
 // block) in one device-to-host transfer and one synchronisation.
+// Through the context's pinned buffer when it has one (a direct DMA, no
+// staging copy).
 nmf_status read_tail(Ctx &c, IpmScal &h) {
-    HCK(hipMemcpyAsync(h.out, c.s.sc->out, sizeof(IpmScal) - offsetof(IpmScal, out), hipMemcpyDeviceToHost, c.st));
+    const size_t bytes = sizeof(IpmScal) - offsetof(IpmScal, out);
+    IpmScal *dst = c.s.hsc ? c.s.hsc : &h;
+    HCK(hipMemcpyAsync(dst->out, c.s.sc->out, bytes, hipMemcpyDeviceToHost, c.st));
     HCK(hipStreamSynchronize(c.st));
+    if (dst != &h) memcpy(h.out, dst->out, bytes);
     return NMF_OK;
 }
 

@@ -158,6 +158,7 @@ struct nmf_ctx {
     double mnorm2 = 0.0;
     double ms1 = 0.0, ms2 = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevStatus *hstat = nullptr;   // pinned host copy of the device status (read back after sweeps)
     DevStatus last1;   // stage-1 status at the hand-over to stage 2
     nmfk::IpmState ipm;
     std::string err;
@@ -430,6 +431,18 @@ nmf_status nmf_create(const double *M, int64_t n, int64_t m, int64_t ldm, int32_
             return bail(st);
         }
     }
+    // small pinned read-back buffers (the host waits on these copies after
+    // every batch of sweeps and twice per interior-point iteration); without
+    // them the copies go through pageable memory
+    if (hipHostMalloc((void **)&c->hstat, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        c->hstat = nullptr;
+        (void)hipGetLastError();
+    }
+    if (o.with_ipm &&
+        hipHostMalloc((void **)&c->ipm.hsc, sizeof(nmfk::IpmScal), hipHostMallocDefault) != hipSuccess) {
+        c->ipm.hsc = nullptr;
+        (void)hipGetLastError();
+    }
 #undef CHK
     *out = c;
     return NMF_OK;
@@ -439,13 +452,17 @@ nmf_status nmf_destroy(nmf_ctx *c) {
     if (!c) return NMF_OK;
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->hstat) (void)hipHostFree(c->hstat);
+    if (c->ipm.hsc) (void)hipHostFree(c->ipm.hsc);
     delete c;
     return NMF_OK;
 }
 
 static nmf_status read_status(nmf_ctx *c, DevStatus &ds) {
-    HIPCHK(c, hipMemcpyAsync(&ds, c->p.st, sizeof(ds), hipMemcpyDeviceToHost, c->stream));
+    DevStatus *dst = c->hstat ? c->hstat : &ds;
+    HIPCHK(c, hipMemcpyAsync(dst, c->p.st, sizeof(ds), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (dst != &ds) ds = *dst;
     return NMF_OK;
 }
 
