@@ -21,6 +21,7 @@ struct IpmScal {
     double GY[KMAX * KMAX];    // Y Y^T at the current point
     double XtV[KMAX * KMAX];   // X^T V, V_i = Q1bar_i^-1 b1_i
     double T[KMAX * KMAX];     // dY Y^T
+    unsigned fin_cnt, fin_pad; // arrivals of the blocks of a kernel that reduces its own records
     double out[4 * PARTW];     // outputs of the last k_finish calls
     double f;                  // 1/2 ||XY - M||^2 at the current point
     int chol_fail;

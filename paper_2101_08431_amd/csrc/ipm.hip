@@ -83,10 +83,11 @@ __device__ __forceinline__ void block_reduce_fn(F &&fn, double *out, double *lds
     }
 }
 
-// out[q] = sum (or min, bit q of minmask) over nblk records part[b*stride + q].
-__global__ __launch_bounds__(NTHR) void k_finish(const double *part, int stride, int nblk, int nval,
-                                                 unsigned minmask, double *out) {
-    __shared__ double scr[NTHR];
+// out[q] = sum (or min, bit q of minmask) over nblk records part[b*stride + q],
+// by NTHR threads: thread (q, g) reduces records g, g + G, ... (G = NTHR /
+// nval), then thread q reduces the G partial results in order.
+__device__ __forceinline__ void finish_body(const double *part, int stride, int nblk, int nval, unsigned minmask,
+                                            double *out, double *scr) {
     const int G = NTHR / nval;
     const int q = threadIdx.x % nval, g = threadIdx.x / nval;
     const bool mn = (minmask >> q) & 1u;
@@ -107,6 +108,33 @@ __global__ __launch_bounds__(NTHR) void k_finish(const double *part, int stride,
         }
         out[threadIdx.x] = acc;
     }
+}
+
+__global__ __launch_bounds__(NTHR) void k_finish(const double *part, int stride, int nblk, int nval,
+                                                 unsigned minmask, double *out) {
+    __shared__ double scr[NTHR];
+    finish_body(part, stride, nblk, nval, minmask, out, scr);
+}
+
+// The same reduction done by the last block of the kernel that wrote the
+// records (one launch fewer); out == nullptr: none.  cnt counts the arriving
+// blocks and wraps to zero for the next kernel.
+struct FinArgs {
+    const double *part;
+    double *out;
+    unsigned *cnt;
+    int stride, nblk, nval;
+    unsigned minmask;
+};
+
+// Called by every thread of a kernel launched with NTHR threads per block,
+// after the block's record is written (by wave 0, which fences it).
+__device__ __forceinline__ void finish_last(const FinArgs &f) {
+    if (!f.out) return;
+    __shared__ unsigned flag;
+    __shared__ double scr[NTHR];
+    if (!last_arrival(f.cnt, gridDim.x * gridDim.y, &flag)) return;
+    finish_body(f.part, f.stride, f.nblk, f.nval, f.minmask, f.out, scr);
 }
 
 // out[a*ld + e] = sum_s part[(s*K + a)*ld + e], e < count; component a =
@@ -256,7 +284,7 @@ __global__ __launch_bounds__(STHR) void k_rstream_y(AnlsParams p, const double *
 // e < count, A and B component-major with leading dimension ld.
 template <int K>
 __global__ __launch_bounds__(NTHR) void k_outer(const double *A, const double *B, int64_t ld, int64_t count,
-                                                double *part) {
+                                                double *part, FinArgs fa) {
     __shared__ double lds[NTHR];
     const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
     double a[K], b[K];
@@ -267,6 +295,7 @@ __global__ __launch_bounds__(NTHR) void k_outer(const double *A, const double *B
     }
     block_reduce_fn<K * K>([&](int idx) { return a[idx / K] * b[idx % K]; }, part + (size_t)blockIdx.x * PRS,
                            lds);
+    finish_last(fa);
 }
 
 // ---------------------------------------------------------------- point kernels
@@ -296,7 +325,7 @@ __device__ __forceinline__ Side side_of(const AnlsParams &p, const IpmArgs &ia, 
 // KKT sums at the current point: [0] sum (g - dual)^2, [1] sum (dual v)^2,
 // [2] sum (dual v - mu)^2, [3] sum dual v.
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_kkt(AnlsParams p, IpmArgs ia, double mu) {
+__global__ __launch_bounds__(NTHR) void k_kkt(AnlsParams p, IpmArgs ia, double mu, FinArgs fa) {
     __shared__ double lds[NTHR];
     const Side sd = side_of<K>(p, ia, false);
     double s1 = 0.0, c0 = 0.0, cm = 0.0, sr = 0.0;
@@ -314,6 +343,7 @@ __global__ __launch_bounds__(NTHR) void k_kkt(AnlsParams p, IpmArgs ia, double m
     }
     const double vals[4] = {s1, c0, cm, sr};
     block_reduce_fn<4>([&](int idx) { return vals[idx]; }, ia.part + (size_t)blockIdx.x * PRS, lds);
+    finish_last(fa);
 }
 
 // Transition helpers.  mode 0: [0] = -max v ; mode 1: [0] = -max |g|, per side
@@ -542,7 +572,8 @@ __global__ __launch_bounds__(NTHR) void k_post_y(AnlsParams p, IpmArgs ia, doubl
 // Row side: dx_i = V_i - Q1bar_i^-1 (X_i (dY Y^T) [+ (R dY^T)_i]), dr, and the
 // same three records.
 template <int K, bool EXACT>
-__global__ __launch_bounds__(NTHR) void k_post_x(AnlsParams p, IpmArgs ia, double mu, double tau, int recbase) {
+__global__ __launch_bounds__(NTHR) void k_post_x(AnlsParams p, IpmArgs ia, double mu, double tau, int recbase,
+                                                 FinArgs fa) {
     constexpr int NL = K * (K + 1) / 2;
     __shared__ double T[K * K];
     __shared__ double lds[NTHR];
@@ -605,6 +636,7 @@ __global__ __launch_bounds__(NTHR) void k_post_x(AnlsParams p, IpmArgs ia, doubl
         for (int w = 1; w < NTHR / 64; ++w) m = mins[threadIdx.x][w] < m ? mins[threadIdx.x][w] : m;
         rec[1 + threadIdx.x] = m;
     }
+    finish_last(fa);
 }
 
 // ---------------------------------------------------------------- line search
@@ -668,7 +700,8 @@ __global__ __launch_bounds__(STHR) void k_ls_quartic(AnlsParams p, IpmArgs ia, d
 constexpr int LS_TG = 2;
 static_assert(NTRIAL % LS_TG == 0, "trial groups");
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_ls_barrier(AnlsParams p, IpmArgs ia, const double *a1dev, double a_base) {
+__global__ __launch_bounds__(NTHR) void k_ls_barrier(AnlsParams p, IpmArgs ia, const double *a1dev, double a_base,
+                                                     FinArgs fa) {
     __shared__ double lds[NTHR];
     // first batch: a_base = min(a1, 1) from the direction's step limit on the device
     if (a1dev) a_base = a1dev[0] < 1.0 ? a1dev[0] : 1.0;
@@ -691,6 +724,7 @@ __global__ __launch_bounds__(NTHR) void k_ls_barrier(AnlsParams p, IpmArgs ia, c
         }
     }
     block_reduce_fn<LS_TG>([&](int idx) { return acc[idx]; }, ia.part + (size_t)blockIdx.x * PRS + t0, lds);
+    finish_last(fa);
 }
 
 template <int K>
@@ -716,7 +750,7 @@ __global__ __launch_bounds__(NTHR) void k_update(AnlsParams p, IpmArgs ia, doubl
 
 // Predictor probe, eq. (8): [0] sum (v + a1 d)(dual + a2 ddual).
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_muaff(AnlsParams p, IpmArgs ia, double a1, double a2) {
+__global__ __launch_bounds__(NTHR) void k_muaff(AnlsParams p, IpmArgs ia, double a1, double a2, FinArgs fa) {
     __shared__ double lds[NTHR];
     const Side sd = side_of<K>(p, ia, true);
     const double *dd = (int)blockIdx.x < p.Bx ? ia.dr : ia.ds;
@@ -730,6 +764,7 @@ __global__ __launch_bounds__(NTHR) void k_muaff(AnlsParams p, IpmArgs ia, double
     }
     const double vals[1] = {acc};
     block_reduce_fn<1>([&](int idx) { return vals[idx]; }, ia.part + (size_t)blockIdx.x * PRS, lds);
+    finish_last(fa);
 }
 
 // Stage-1 masks from the signs (used when the context returns to stage 1).
@@ -945,6 +980,19 @@ hipError_t finish(Ctx &c, const double *part, int stride, int nblk, int nval, un
     return hipGetLastError();
 }
 
+// The k_finish reduction folded into the kernel that writes the records.
+FinArgs fin(Ctx &c, const double *part, int stride, int nblk, int nval, unsigned minmask, double *out) {
+    FinArgs f;
+    f.part = part;
+    f.out = out;
+    f.cnt = &c.s.sc->fin_cnt;
+    f.stride = stride;
+    f.nblk = nblk;
+    f.nval = nval;
+    f.minmask = minmask;
+    return f;
+}
+
 // The k_finish outputs, f and the failure words (the end of the scalar
 // block) in one device-to-host transfer and one synchronisation.
 // Through the context's pinned buffer when it has one (a direct DMA, no
@@ -975,10 +1023,10 @@ hipError_t point_products(Ctx &c) {
     IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_rstream_y<KK>, dim3(p.Tm, p.Sy), dim3(STHR), 0, c.st, p, p.X,
                                           p.by_part));
     hipLaunchKernelGGL(k_sum_splits, dim3(g1(p.m).x, (unsigned)(c.K)), dim3(NTHR), 0, c.st, p.by_part, p.Sy, c.K, p.ldY, p.m, c.s.gy);
-    IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, p.X, p.ldX, p.n, c.s.part));
-    if ((e = finish(c, c.s.part, PRS, p.Bx, c.K * c.K, 0u, c.s.sc->GX)) != hipSuccess) return e;
-    IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_outer<KK>, g1(p.m), dim3(NTHR), 0, c.st, p.Y, p.Y, p.ldY, p.m, c.s.part));
-    if ((e = finish(c, c.s.part, PRS, p.By, c.K * c.K, 0u, c.s.sc->GY)) != hipSuccess) return e;
+    IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, p.X, p.ldX, p.n, c.s.part,
+                                          fin(c, c.s.part, PRS, p.Bx, c.K * c.K, 0u, c.s.sc->GX)));
+    IPM_K_SWITCH(c.K, hipLaunchKernelGGL(k_outer<KK>, g1(p.m), dim3(NTHR), 0, c.st, p.Y, p.Y, p.ldY, p.m, c.s.part,
+                                          fin(c, c.s.part, PRS, p.By, c.K * c.K, 0u, c.s.sc->GY)));
     return hipGetLastError();
 }
 
@@ -986,8 +1034,9 @@ hipError_t point_products(Ctx &c) {
 // E0, Emu and f.
 nmf_status kkt(Ctx &c, double mu) {
     const AnlsParams &p = c.p;
-    IPM_KS(c.K, hipLaunchKernelGGL(k_kkt<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, mu));
-    HCK(finish(c, c.s.part, PRS, p.Bx + p.By, 4, 0u, c.s.sc->out));
+    IPM_KS(c.K, hipLaunchKernelGGL(k_kkt<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, mu,
+                                   fin(c, c.s.part, PRS, p.Bx + p.By, 4, 0u, c.s.sc->out)));
+    HCK(hipGetLastError());
     IpmScal hs;
     nmf_status st = read_tail(c, hs);
     if (st != NMF_OK) return st;
@@ -1031,6 +1080,7 @@ nmf_status ensure_flags(Ctx &c) {
     // failure words are cleared by a fill kernel: no host memory, nothing
     // that waits for the stream
     HCK(launch_fill_u32((unsigned *)&c.s.sc->solve_fail, 1, 0u, c.st));
+    HCK(launch_fill_u32(&c.s.sc->fin_cnt, 1, 0u, c.st));
     c.s.flags_ready = true;
     c.s.epoch = 0;
     return NMF_OK;
@@ -1102,8 +1152,8 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
     const double rho = c.s.rho;
     // factors of Q1bar, V = Q1bar^-1 b1, X^T V
     IPM_KS(K, hipLaunchKernelGGL(k_factor<KK>, g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, rho));
-    IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, c.s.V, p.ldX, p.n, c.s.part));
-    HCK(finish(c, c.s.part, PRS, p.Bx, K * K, 0u, c.s.sc->XtV));
+    IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.n), dim3(NTHR), 0, c.st, p.X, c.s.V, p.ldX, p.n, c.s.part,
+                                 fin(c, c.s.part, PRS, p.Bx, K * K, 0u, c.s.sc->XtV)));
     const bool reuse = !exact && c.s.S_gn_valid;
     bool formed = false;
     if (!reuse) {
@@ -1212,19 +1262,19 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
     prof_end(c, 3);
     IPM_KS(K, hipLaunchKernelGGL(k_post_y<KK>, g1(p.m), dim3(NTHR), 0, c.st, p, c.ia, mu, tau, 0));
     IPM_KS(K, hipLaunchKernelGGL(k_outer<KK>, g1(p.m), dim3(NTHR), 0, c.st, c.s.dy, p.Y, p.ldY, p.m,
-                                       c.s.part + (size_t)(p.By + p.Bx) * PRS));
-    HCK(finish(c, c.s.part + (size_t)(p.By + p.Bx) * PRS, PRS, p.By, K * K, 0u, c.s.sc->T));
+                                 c.s.part + (size_t)(p.By + p.Bx) * PRS,
+                                 fin(c, c.s.part + (size_t)(p.By + p.Bx) * PRS, PRS, p.By, K * K, 0u, c.s.sc->T)));
     if (exact) {
         IPM_KS(K, hipLaunchKernelGGL(k_rstream_x<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, c.s.dy,
                                            p.bx_part, (double *)nullptr));
         hipLaunchKernelGGL(k_sum_splits, dim3(g1(p.n).x, (unsigned)(K)), dim3(NTHR), 0, c.st, p.bx_part, p.Sx, K, p.ldX, p.n, c.s.tX);
         IPM_KS(K, hipLaunchKernelGGL((k_post_x<KK, true>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, tau,
-                                           p.By));
+                                     p.By, fin(c, c.s.part, PRS, p.By + p.Bx, 3, 0x6u, c.s.sc->out + OUT_DIR)));
     } else {
         IPM_KS(K, hipLaunchKernelGGL((k_post_x<KK, false>), g1(p.n), dim3(NTHR), 0, c.st, p, c.ia, mu, tau,
-                                           p.By));
+                                     p.By, fin(c, c.s.part, PRS, p.By + p.Bx, 3, 0x6u, c.s.sc->out + OUT_DIR)));
     }
-    HCK(finish(c, c.s.part, PRS, p.By + p.Bx, 3, 0x6u, c.s.sc->out + OUT_DIR));
+    HCK(hipGetLastError());
     if (defer) {
         // the caller reads the scalars and the failure flag with the line
         // search's (probe())
@@ -1259,8 +1309,9 @@ nmf_status probe(Ctx &c, Dir &d, double *q, double *bar) {
     IPM_KS(c.K, hipLaunchKernelGGL(k_ls_quartic<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, c.ia, lspart));
     HCK(finish(c, lspart, 8, p.Tn * p.Sx, 6, 0u, c.s.sc->out + OUT_QUART));
     IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By, NTRIAL / LS_TG), dim3(NTHR), 0, c.st, p, c.ia,
-                                   (const double *)(c.s.sc->out + OUT_DIR + 1), 0.0));
-    HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out + OUT_BAR));
+                                   (const double *)(c.s.sc->out + OUT_DIR + 1), 0.0,
+                                   fin(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out + OUT_BAR)));
+    HCK(hipGetLastError());
     IpmScal hs;
     nmf_status st = read_tail(c, hs);
     if (st != NMF_OK) return st;
@@ -1290,9 +1341,10 @@ nmf_status line_search(Ctx &c, const Dir &d, double mu, const double *q, const d
         const double *bar = bar0;
         if (t0 > 0) {
             const double abase = d.a1 / ldexp(1.0, t0);
-            IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By, NTRIAL / LS_TG), dim3(NTHR), 0, c.st, p, c.ia,
-                                           (const double *)nullptr, abase));
-            HCK(finish(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out));
+            IPM_KS(c.K, hipLaunchKernelGGL(k_ls_barrier<KK>, dim3(p.Bx + p.By, NTRIAL / LS_TG), dim3(NTHR), 0, c.st, p,
+                                           c.ia, (const double *)nullptr, abase,
+                                           fin(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out)));
+            HCK(hipGetLastError());
             nmf_status st = read_out(c, barv, NTRIAL);
             if (st != NMF_OK) return st;
             bar = barv;
@@ -1378,8 +1430,9 @@ nmf_status mu_update(Ctx &c) {
         s.err = "Cholesky factorisation of the predictor Schur matrix failed";
         return NMF_ESINGULAR;
     }
-    IPM_KS(c.K, hipLaunchKernelGGL(k_muaff<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, d.a1, d.a2));
-    HCK(finish(c, s.part, PRS, p.Bx + p.By, 1, 0u, s.sc->out));
+    IPM_KS(c.K, hipLaunchKernelGGL(k_muaff<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, d.a1, d.a2,
+                                   fin(c, s.part, PRS, p.Bx + p.By, 1, 0u, s.sc->out)));
+    HCK(hipGetLastError());
     double h[1];
     st = read_out(c, h, 1);
     if (st != NMF_OK) return st;
