@@ -66,7 +66,10 @@ def make_ctx(M, X0, Y0, k, **opt):
 
 
 def time_graph_sweeps(ctx, steps, warmup):
-    """ms per sweep of graph-replayed sweeps (a batch of one problem)."""
+    """ms per sweep of graph-replayed sweeps (a batch of one problem: the
+    batch form's table-driven kernels), the wall time of the timed replay, and
+    ms per sweep of the same batch form launched eagerly (which separates the
+    cost of the batch kernels from that of graph replay)."""
     import torch
     from paper_2101_08431_amd import Batch
     b = Batch([ctx])
@@ -83,8 +86,16 @@ def time_graph_sweeps(ctx, steps, warmup):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     dev = e0.elapsed_time(e1)
+    b.step(warmup, graph=False)
+    b.sync()
+    e0.record(b.stream)
+    b.step(steps, graph=False)
+    e1.record(b.stream)
+    b.sync()
+    torch.cuda.synchronize()
+    dev_eager = e0.elapsed_time(e1)
     b.close()
-    return dev / steps, wall
+    return dev / steps, wall, dev_eager / steps
 
 
 def time_eager_sweeps(ctx, steps, warmup):
@@ -360,7 +371,7 @@ def precision_section(steps):
         X, Y = ctx.factors()
         err = max(np.abs(X - ref["X"]).max(), np.abs(Y.T - ref["Yt"]).max()) / scale
         f = oracle.objective(M, X, Y.T.copy())
-        ms, _ = time_graph_sweeps(ctx, steps, 5)
+        ms, _, _ = time_graph_sweeps(ctx, steps, 5)
         ms4 = ctx.anls_profile(20)
         res[name] = {"ms_per_sweep": ms, "solves_per_s": (n + m) / (ms * 1e-3),
                      "stream_ms": [ms4[0], ms4[2]],
@@ -580,7 +591,7 @@ def main():
         log(f"autotuned launch plan (x splits, y splits, X one kernel, Y one kernel) = {ctx.launch_plan()}; "
             "fastest: " + ", ".join(f"{kk}: {v * 1e3:.1f} us" for kk, v in list(autotune.last_timings.items())[:6]))
     shape = ctx.launch_plan()
-    ms_graph, wall_ms = time_graph_sweeps(ctx, args.steps, args.warmup)
+    ms_graph, wall_ms, ms_batch_eager = time_graph_sweeps(ctx, args.steps, args.warmup)
     ms_eager = time_eager_sweeps(ctx, args.steps, args.warmup)
     mode = "graph" if ms_graph <= ms_eager else "eager"
     ms_step = min(ms_graph, ms_eager)
@@ -595,7 +606,7 @@ def main():
                    "step": "one ANLS sweep (X stream + row NNLS, then Y stream + column NNLS, each half "
                            "two kernels or one), n + m NNLS solves",
                    "launch": mode, "graph_ms_per_step": ms_graph, "eager_ms_per_step": ms_eager,
-                   "graph_wall_ms_timed": wall_ms,
+                   "graph_wall_ms_timed": wall_ms, "batch_form_eager_ms_per_step": ms_batch_eager,
                    "launch_plan": {"x_splits": shape[0], "y_splits": shape[1], "x_one_kernel": shape[2],
                                    "y_one_kernel": shape[3]}},
         "roofline": rl,
