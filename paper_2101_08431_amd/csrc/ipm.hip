@@ -40,6 +40,13 @@
 namespace nmfk {
 
 constexpr int PRS = KMAX * KMAX;   // stride of block records in `part`
+// Slots of the scalar block's `out`: the direction's slope and step limits,
+// the line-search quartic and first barrier batch, the Armijo choice made on
+// the device ([0] accepted, [1] a1, [2] a2, [3] backtracks) and the KKT sums
+// of the point it leads to.
+constexpr int OUT_DIR = 0, OUT_QUART = 8, OUT_BAR = 16;
+constexpr int OUT_SEL = OUT_BAR + NTRIAL, OUT_KKT = OUT_SEL + 4;
+static_assert(OUT_KKT + 4 <= 4 * PARTW, "the finish outputs fit the scalar block");
 constexpr int CB = 64;             // dense Cholesky / triangular-solve tile
 constexpr int TJ = 16;             // Schur tile: 16 x 16 (j, l) pairs
 constexpr int ZRB = 8;             // rows per block of the Z kernel
@@ -727,8 +734,15 @@ __global__ __launch_bounds__(NTHR) void k_ls_barrier(AnlsParams p, IpmArgs ia, c
     finish_last(fa);
 }
 
+// sel != nullptr: the step comes from the device's Armijo choice (sel[0] = 0:
+// none accepted, the point is left as it is).
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_update(AnlsParams p, IpmArgs ia, double a1, double a2) {
+__global__ __launch_bounds__(NTHR) void k_update(AnlsParams p, IpmArgs ia, double a1, double a2, const double *sel) {
+    if (sel) {
+        if (sel[0] == 0.0) return;
+        a1 = sel[1];
+        a2 = sel[2];
+    }
     const int64_t e = (int64_t)blockIdx.x * NTHR + threadIdx.x;
     if (e < p.n) {
 #pragma unroll
@@ -744,6 +758,42 @@ __global__ __launch_bounds__(NTHR) void k_update(AnlsParams p, IpmArgs ia, doubl
             const int64_t o = (int64_t)a * p.ldY + e;
             p.Y[o] += a1 * ia.dy[o];
             ia.s[o] += a2 * ia.ds[o];
+        }
+    }
+}
+
+// The first batch of the Armijo rule of eq. (13) on the device, with the
+// arithmetic of the host's line search (no contraction): the step limits and
+// slope of the direction (out[OUT_DIR..]), the quartic (out[OUT_QUART..]) and
+// the barrier sums of the first NTRIAL trials (out[OUT_BAR..]); writes the
+// choice to out[OUT_SEL..].  Nothing is accepted when the factorisation that
+// produced the direction failed.
+__global__ void k_armijo(IpmScal *sc, double mu, double eta, int maxb, int formed) {
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0) return;
+    const double *h = sc->out;
+    double *sel = sc->out + OUT_SEL;
+    sel[0] = 0.0;
+    sel[1] = 0.0;
+    sel[2] = 0.0;
+    sel[3] = 0.0;
+    if (formed && sc->chol_fail) return;
+    const double slope = h[OUT_DIR];
+    const double a1 = h[OUT_DIR + 1] < 1.0 ? h[OUT_DIR + 1] : 1.0;
+    const double a2 = h[OUT_DIR + 2] < 1.0 ? h[OUT_DIR + 2] : 1.0;
+    const double *q = h + OUT_QUART;
+    const double *bar = h + OUT_BAR;
+    for (int t = 0; t < NTRIAL && t <= maxb; ++t) {
+        const double a = a1 / ldexp(1.0, t);
+        const double dq = 0.5 * (2.0 * a * q[1] + a * a * (q[2] + 2.0 * q[3]) + 2.0 * a * a * a * q[4] +
+                                 a * a * a * a * q[5]);
+        const double dphi = dq - mu * bar[t];
+        if (dphi <= eta * a * slope) {
+            sel[0] = 1.0;
+            sel[1] = a;
+            sel[2] = a2;
+            sel[3] = (double)t;
+            return;
         }
     }
 }
@@ -1032,19 +1082,21 @@ hipError_t point_products(Ctx &c) {
 
 // KKT sums at the current point for barrier parameter mu; fills S1, C0, Cmu,
 // E0, Emu and f.
-nmf_status kkt(Ctx &c, double mu) {
+nmf_status kkt_enqueue(Ctx &c, double mu, int slot) {
     const AnlsParams &p = c.p;
     IPM_KS(c.K, hipLaunchKernelGGL(k_kkt<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, mu,
-                                   fin(c, c.s.part, PRS, p.Bx + p.By, 4, 0u, c.s.sc->out)));
+                                   fin(c, c.s.part, PRS, p.Bx + p.By, 4, 0u, c.s.sc->out + slot)));
     HCK(hipGetLastError());
-    IpmScal hs;
-    nmf_status st = read_tail(c, hs);
-    if (st != NMF_OK) return st;
+    return NMF_OK;
+}
+
+// Reads the KKT sums (slot `slot` of the scalar block read back in hs).
+nmf_status kkt_parse(Ctx &c, const IpmScal &hs, int slot) {
     if (hs.solve_fail) {
         c.s.err = "a block of a triangular solve waited too long for the tile before it";
         return NMF_EDEVICE;
     }
-    const double *h = hs.out;
+    const double *h = hs.out + slot;
     const double f = hs.f;
     c.s.S1 = h[0];
     c.s.SR = h[3];
@@ -1054,6 +1106,15 @@ nmf_status kkt(Ctx &c, double mu) {
     c.s.E0 = fmax(sqrt(h[0]), sqrt(h[1]));
     c.s.Emu = fmax(sqrt(h[0]), sqrt(h[2]));
     return NMF_OK;
+}
+
+nmf_status kkt(Ctx &c, double mu) {
+    nmf_status st = kkt_enqueue(c, mu, 0);
+    if (st != NMF_OK) return st;
+    IpmScal hs;
+    st = read_tail(c, hs);
+    if (st != NMF_OK) return st;
+    return kkt_parse(c, hs, 0);
 }
 
 // Device time of the work enqueued between prof_begin and prof_end (a
@@ -1139,8 +1200,6 @@ struct Dir {
 // Slots of IpmScal::out for the scalars of one inner iteration, read in one
 // copy: the direction's (slope, step limits), the line search's quartic
 // coefficients and the first batch of barrier trials.
-constexpr int OUT_DIR = 0, OUT_QUART = 8, OUT_BAR = 16;
-static_assert(OUT_BAR + NTRIAL <= 4 * PARTW, "the finish outputs fit the scalar block");
 
 // Newton direction of eq. (12) at the current point with barrier parameter
 // mu (0 for the predictor) and the Hessian eq. (26) (exact = false) or eq.
@@ -1303,7 +1362,7 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
 // NTRIAL barrier trials from the deferred direction's step limit, then reads
 // the direction's scalars, its factorisation flag, the quartic and the trials
 // in one host round trip.
-nmf_status probe(Ctx &c, Dir &d, double *q, double *bar) {
+nmf_status probe_enqueue(Ctx &c) {
     const AnlsParams &p = c.p;
     double *lspart = c.s.fpart;   // reused: Tn*Sx records of 8
     IPM_KS(c.K, hipLaunchKernelGGL(k_ls_quartic<KK>, dim3(p.Tn, p.Sx), dim3(STHR), 0, c.st, p, c.ia, lspart));
@@ -1312,21 +1371,34 @@ nmf_status probe(Ctx &c, Dir &d, double *q, double *bar) {
                                    (const double *)(c.s.sc->out + OUT_DIR + 1), 0.0,
                                    fin(c, c.s.part, PRS, p.Bx + p.By, NTRIAL, 0u, c.s.sc->out + OUT_BAR)));
     HCK(hipGetLastError());
-    IpmScal hs;
-    nmf_status st = read_tail(c, hs);
-    if (st != NMF_OK) return st;
+    return NMF_OK;
+}
+
+// The direction's scalars, the quartic and the first barrier batch from the
+// scalar block read back in hs.
+void probe_parse(Ctx &c, Dir &d, const IpmScal &hs, double *q, double *bar) {
     const double *h = hs.out;
     for (int t = 0; t < 6; ++t) q[t] = h[OUT_QUART + t];
     for (int t = 0; t < NTRIAL; ++t) bar[t] = h[OUT_BAR + t];
     if (d.formed && hs.chol_fail) {
         c.s.S_gn_valid = false;
         d.ok = false;
-        return NMF_OK;
+        return;
     }
     d.ok = true;
     d.slope = h[OUT_DIR];
     d.a1 = h[OUT_DIR + 1] < 1.0 ? h[OUT_DIR + 1] : 1.0;
     d.a2 = h[OUT_DIR + 2] < 1.0 ? h[OUT_DIR + 2] : 1.0;
+}
+
+// The line-search inputs in one host round trip.
+nmf_status probe(Ctx &c, Dir &d, double *q, double *bar) {
+    nmf_status st = probe_enqueue(c);
+    if (st != NMF_OK) return st;
+    IpmScal hs;
+    st = read_tail(c, hs);
+    if (st != NMF_OK) return st;
+    probe_parse(c, d, hs, q, bar);
     return NMF_OK;
 }
 
@@ -1334,6 +1406,7 @@ nmf_status probe(Ctx &c, Dir &d, double *q, double *bar) {
 // barrier sums; the first batch (bar) comes from probe().  Returns the
 // accepted step in *al.
 nmf_status line_search(Ctx &c, const Dir &d, double mu, const double *q, const double *bar0, double *al) {
+#pragma clang fp contract(off)
     const AnlsParams &p = c.p;
     const int maxb = c.o.max_backtracks;
     for (int t0 = 0; t0 <= maxb; t0 += NTRIAL) {
@@ -1367,13 +1440,24 @@ nmf_status line_search(Ctx &c, const Dir &d, double mu, const double *q, const d
     return NMF_OK;
 }
 
-nmf_status update_point(Ctx &c, double a1, double a2) {
+// The update (step a1, a2, or the device's choice in sel), the products at
+// the new point and its KKT sums into slot `slot`, without synchronising.
+nmf_status update_enqueue(Ctx &c, double a1, double a2, const double *sel, int slot) {
     const AnlsParams &p = c.p;
     const int64_t e = p.n > p.m ? p.n : p.m;
-    IPM_KS(c.K, hipLaunchKernelGGL(k_update<KK>, g1(e), dim3(NTHR), 0, c.st, p, c.ia, a1, a2));
-    c.s.S_gn_valid = false;
+    IPM_KS(c.K, hipLaunchKernelGGL(k_update<KK>, g1(e), dim3(NTHR), 0, c.st, p, c.ia, a1, a2, sel));
     HCK(point_products(c));
-    return kkt(c, c.s.mu);
+    return kkt_enqueue(c, c.s.mu, slot);
+}
+
+nmf_status update_point(Ctx &c, double a1, double a2) {
+    nmf_status st = update_enqueue(c, a1, a2, nullptr, 0);
+    if (st != NMF_OK) return st;
+    c.s.S_gn_valid = false;
+    IpmScal hs;
+    st = read_tail(c, hs);
+    if (st != NMF_OK) return st;
+    return kkt_parse(c, hs, 0);
 }
 
 // One inner iteration of Alg. 3 (direction with the flag rule, step rules,
@@ -1404,11 +1488,36 @@ nmf_status inner_iteration(Ctx &c) {
         d.ok = false;
         st = direction(c, mu, false, c.o.tau, d, true);
         if (st != NMF_OK) return st;
-        st = probe(c, d, q, bar);
+        // The line-search inputs, the first Armijo batch, the update and the
+        // KKT sums of the new point are enqueued together and read back in
+        // one round trip; when no trial of the first batch is accepted the
+        // device leaves the point as it is and the host continues the search.
+        st = probe_enqueue(c);
         if (st != NMF_OK) return st;
+        hipLaunchKernelGGL(k_armijo, dim3(1), dim3(64), 0, c.st, s.sc, mu, c.o.eta, c.o.max_backtracks,
+                           d.formed ? 1 : 0);
+        HCK(hipGetLastError());
+        st = update_enqueue(c, 0.0, 0.0, s.sc->out + OUT_SEL, OUT_KKT);
+        if (st != NMF_OK) return st;
+        IpmScal hs;
+        st = read_tail(c, hs);
+        if (st != NMF_OK) return st;
+        probe_parse(c, d, hs, q, bar);
         if (!d.ok) {
             s.err = "Cholesky factorisation of the Gauss-Newton Schur matrix failed";
             return NMF_ESINGULAR;
+        }
+        const double *sel = hs.out + OUT_SEL;
+        if (sel[0] != 0.0) {
+            s.backtracks += (int)sel[3];
+            s.iters += 1;
+            s.at_mu += 1;
+            s.S_gn_valid = false;
+            return kkt_parse(c, hs, OUT_KKT);
+        }
+        if (hs.solve_fail) {
+            s.err = "a block of a triangular solve waited too long for the tile before it";
+            return NMF_EDEVICE;
         }
     }
     double al = 0.0;
