@@ -904,15 +904,18 @@ struct IpmLayout {
     int P;
 };
 
-// Row splits of the Schur formation.  Blocks are dealt to the 8 XCDs in
-// turn and split p of block b is b mod P, so with P = 8 each XCD streams the
-// Z rows of one split only (its L2 holds them for every tile pair).  Large
+// Row splits of the Schur formation (split p of block b is b mod P).  Large
 // problems (enough tile pairs to fill the chip many times) use one split.
+// Otherwise 7: at 3000x500x5 the formation and split reduction took 544 us
+// with 7 splits against 565 us with 8 (where each of the 8 XCDs would stream
+// the Z rows of one split only), 578 with 6 and 569-582 with 12-16; the split
+// count sets how evenly the blocks fill the chip's rounds of resident blocks,
+// and that outweighs the L2 locality.
 static int schur_splits(int64_t n, int64_t m, int K) {
     const int64_t T = (m + 15) / 16;
     const int64_t units = T * (T + 1) / 2 * schur_chunks(K);
     if (units >= 8192 || n < 8 * 32) return 1;
-    return 8;
+    return 7;
 }
 
 constexpr int OPS = 16;   // row splits of the operator's column pass
