@@ -316,6 +316,9 @@ template <> struct MfmaT<true> {
 // V[k - k0][(a, j)] = X_ia Z_i[p][j] + (L_i^-1)[p][a] R_ij for k = i*K + p,
 // columns in component-major order (a*m + j), zero from N = m K to ldV;
 // rounded to FP32 for the mixed-precision form.
+// Block x < K * cbm covers columns j of component a = x / cbm (256 per
+// block, cbm = ceil(m / 256)); the blocks after them zero the padding
+// columns [N, ldV).
 template <int K, typename E>
 __global__ __launch_bounds__(256) void k_vgen(SchurExArgs g, int64_t k0, int64_t k1, E *V, int64_t ldV) {
     const int64_t k = k0 + blockIdx.y;
@@ -323,17 +326,21 @@ __global__ __launch_bounds__(256) void k_vgen(SchurExArgs g, int64_t k0, int64_t
     const int64_t i = k / K;
     const int p = (int)(k - i * K);
     const int64_t N = g.m * K;
-    const double *zr = g.Z + (i * zpad(K) + p) * g.ldY;
-    const double *rr = g.R + i * g.ldY;
-    const double *li = g.Linv + (i * K + p) * K;
-    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < ldV; c += (int64_t)gridDim.x * 256) {
-        double v = 0.0;
-        if (c < N) {
-            const int a = (int)(c / g.m);
-            const int64_t j = c - (int64_t)a * g.m;
-            v = fma(g.X[(int64_t)a * g.ldX + i], zr[j], li[a] * rr[j]);
+    const int cbm = (int)((g.m + 255) / 256);
+    const int bx = (int)blockIdx.x;
+    E *vr = V + (k - k0) * ldV;
+    if (bx < K * cbm) {
+        const int a = bx / cbm;
+        const int64_t j = (int64_t)(bx - a * cbm) * 256 + threadIdx.x;
+        if (j < g.m) {
+            const double *zr = g.Z + (i * zpad(K) + p) * g.ldY;
+            const double *rr = g.R + i * g.ldY;
+            const double *li = g.Linv + (i * K + p) * K;
+            vr[(int64_t)a * g.m + j] = (E)fma(g.X[(int64_t)a * g.ldX + i], zr[j], li[a] * rr[j]);
         }
-        V[(k - k0) * ldV + c] = (E)v;
+    } else {
+        const int64_t c = N + (int64_t)(bx - K * cbm) * 256 + threadIdx.x;
+        if (c < ldV) vr[c] = (E)0.0;
     }
 }
 
@@ -1122,7 +1129,8 @@ hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t
     const dim3 grid((unsigned)(T2 * (T2 + 1) / 2));
     for (int64_t k0 = 0; k0 < nk; k0 += slab) {
         const int64_t k1 = std::min(nk, k0 + slab);
-        const dim3 gv((unsigned)std::min<int64_t>((ldV + 255) / 256, 64), (unsigned)(k1 - k0));
+        const int64_t cbm = (g.m + 255) / 256;
+        const dim3 gv((unsigned)(K * cbm + (ldV - g.m * K + 255) / 256), (unsigned)(k1 - k0));
         const int first = k0 == 0 ? 1 : 0;
         if (f32) {
             float *Vf = (float *)V;
