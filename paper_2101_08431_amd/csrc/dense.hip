@@ -318,29 +318,34 @@ template <> struct MfmaT<true> {
 // rounded to FP32 for the mixed-precision form.
 // Block x < K * cbm covers columns j of component a = x / cbm (256 per
 // block, cbm = ceil(m / 256)); the blocks after them zero the padding
-// columns [N, ldV).
+// columns [N, ldV).  Each block writes VGEN_ROWS consecutive rows (few,
+// larger blocks: the dispatch rate of tiny blocks, not HBM, bounded the
+// one-row form).
+constexpr int VGEN_ROWS = 8;
 template <int K, typename E>
 __global__ __launch_bounds__(256) void k_vgen(SchurExArgs g, int64_t k0, int64_t k1, E *V, int64_t ldV) {
-    const int64_t k = k0 + blockIdx.y;
-    if (k >= k1) return;
-    const int64_t i = k / K;
-    const int p = (int)(k - i * K);
     const int64_t N = g.m * K;
     const int cbm = (int)((g.m + 255) / 256);
     const int bx = (int)blockIdx.x;
-    E *vr = V + (k - k0) * ldV;
+    const int64_t kb = k0 + (int64_t)blockIdx.y * VGEN_ROWS;
+    const int64_t ke = min(k1, kb + VGEN_ROWS);
     if (bx < K * cbm) {
         const int a = bx / cbm;
         const int64_t j = (int64_t)(bx - a * cbm) * 256 + threadIdx.x;
-        if (j < g.m) {
+        if (j >= g.m) return;
+        for (int64_t k = kb; k < ke; ++k) {
+            const int64_t i = k / K;
+            const int p = (int)(k - i * K);
             const double *zr = g.Z + (i * zpad(K) + p) * g.ldY;
             const double *rr = g.R + i * g.ldY;
             const double *li = g.Linv + (i * K + p) * K;
-            vr[(int64_t)a * g.m + j] = (E)fma(g.X[(int64_t)a * g.ldX + i], zr[j], li[a] * rr[j]);
+            V[(k - k0) * ldV + (int64_t)a * g.m + j] =
+                (E)fma(g.X[(int64_t)a * g.ldX + i], zr[j], li[a] * rr[j]);
         }
     } else {
         const int64_t c = N + (int64_t)(bx - K * cbm) * 256 + threadIdx.x;
-        if (c < ldV) vr[c] = (E)0.0;
+        if (c >= ldV) return;
+        for (int64_t k = kb; k < ke; ++k) V[(k - k0) * ldV + c] = (E)0.0;
     }
 }
 
@@ -1130,7 +1135,8 @@ hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t
     for (int64_t k0 = 0; k0 < nk; k0 += slab) {
         const int64_t k1 = std::min(nk, k0 + slab);
         const int64_t cbm = (g.m + 255) / 256;
-        const dim3 gv((unsigned)(K * cbm + (ldV - g.m * K + 255) / 256), (unsigned)(k1 - k0));
+        const dim3 gv((unsigned)(K * cbm + (ldV - g.m * K + 255) / 256),
+                      (unsigned)((k1 - k0 + VGEN_ROWS - 1) / VGEN_ROWS));
         const int first = k0 == 0 ? 1 : 0;
         if (f32) {
             float *Vf = (float *)V;
