@@ -89,8 +89,11 @@ hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st);
 // The exact-Hessian Schur complement with V written out (k_vgen) in slabs of
 // `slab` rows into V ([slab][ldV] doubles, or floats when f32; ldV >= NT*64, a
 // multiple of 64) and summed by a matrix-core rank update per slab (k_syrk_v).
+// kpart (capacity kpart_cap doubles, may be null): partial tiles when the rows
+// of each slab are split over several blocks per tile, which the launcher does
+// when the 128 x 128 tiles are too few to fill the chip evenly.
 hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t ldV, int64_t slab, bool f32,
-                                   hipStream_t st);
+                                   double *kpart, int64_t kpart_cap, hipStream_t st);
 hipError_t launch_schur_apply(int K, bool exact, const OpArgs &g, hipStream_t st);
 hipError_t launch_axpy(double *y, const double *x, int64_t count, hipStream_t st);
 // Linv[i][p][a] = (L_i^-1)[p][a] from the packed factors Lq ([K(K+1)/2 + K][ldX]:

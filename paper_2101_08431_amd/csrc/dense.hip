@@ -359,9 +359,38 @@ __global__ __launch_bounds__(256) void k_vgen(SchurExArgs g, int64_t k0, int64_t
 // flop/byte in FP64).  On a diagonal tile the waves wholly above the diagonal
 // skip the products (their entries are never read).  first: S = Q2bar - sum;
 // otherwise S -= sum (later slabs of rows).
+// Entry (x, y, v) of the lane's output blocks, summed over the rows: written
+// into S (first: S = Q2bar - sum, else S -= sum).
 template <int K, bool F32>
+__device__ __forceinline__ void syrk_put(const SchurExArgs &g, int64_t It, int64_t Jt, int R0, int C0, int gq, int r,
+                                         int x, int y, int v, double sum, int first) {
+    typedef MfmaT<F32> M;
+    const int64_t N = g.m * K;
+    const int64_t row = It * 128 + R0 + 16 * x + r, cl = Jt * 128 + C0 + 16 * y + M::drow(gq, v);
+    if (row < N && cl < N) {
+        double *dst = g.S + cl * g.ldS + row;
+        if (first) {
+            const int a = (int)(row / g.m), b = (int)(cl / g.m);
+            const int64_t j = row - a * g.m, l = cl - b * g.m;
+            double val = -sum;
+            if (j == l) {
+                val += g.GX[a * K + b];
+                if (a == b) val += g.rho + g.s[(int64_t)a * g.ldY + j] / g.Y[(int64_t)a * g.ldY + j];
+            }
+            *dst = val;
+        } else {
+            *dst -= sum;
+        }
+    }
+}
+
+// SPLIT: the rows of the slab are split over blockIdx.y (nsplit ranges of whole
+// 16-row chunks) and each block writes its partial tile to kpart (entry q =
+// (x*4 + y)*4 + v of thread t at ((s * tiles + tile) * 32 + q) * 512 + t);
+// k_syrk_reduce then sums the splits in order and writes S.
+template <int K, bool F32, bool SPLIT>
 __global__ __launch_bounds__(512) void k_syrk_v(SchurExArgs g, const typename MfmaT<F32>::E *V, int64_t ldV,
-                                                int64_t rows, int first) {
+                                                int64_t rows, int first, int nsplit, double *kpart) {
     typedef MfmaT<F32> M;
     typedef typename M::E E;
     constexpr int TW = 128;                           // tile width
@@ -378,14 +407,19 @@ __global__ __launch_bounds__(512) void k_syrk_v(SchurExArgs g, const typename Mf
     const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
     const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 64;
     const bool work = !(It == Jt && R0 + 32 <= C0);   // wave-uniform
-    const int64_t N = g.m * K;
+    int64_t kbeg = 0, kend = rows;
+    if (SPLIT) {
+        const int64_t per = ((rows + nsplit - 1) / nsplit + KC - 1) / KC * KC;
+        kbeg = min(rows, (int64_t)blockIdx.y * per);
+        kend = min(rows, kbeg + per);
+    }
     uint4 ld[NLD];
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int h = 0; h < NLD; ++h) {
             const int idx = h * 512 + threadIdx.x, tile = idx / TSH, rem = idx % TSH, kk = rem / RSH, cq = rem % RSH;
             const int64_t kr = k0 + kk, col = (tile ? Jt : It) * TW + PER * cq;
-            ld[h] = (kr < rows && col < ldV) ? *reinterpret_cast<const uint4 *>(V + kr * ldV + col)
+            ld[h] = (kr < kend && col < ldV) ? *reinterpret_cast<const uint4 *>(V + kr * ldV + col)
                                              : make_uint4(0u, 0u, 0u, 0u);
         }
     };
@@ -403,12 +437,12 @@ __global__ __launch_bounds__(512) void k_syrk_v(SchurExArgs g, const typename Mf
         for (int y = 0; y < 4; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[x][y][v] = (E)0;
-    load(0);
+    load(kbeg);
     store(0);
     __syncthreads();
     int buf = 0;
-    for (int64_t k0 = 0; k0 < rows; k0 += KC) {
-        const bool more = k0 + KC < rows;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+        const bool more = k0 + KC < kend;
         if (more) load(k0 + KC);
         if (work) {
 #pragma unroll
@@ -430,29 +464,46 @@ __global__ __launch_bounds__(512) void k_syrk_v(SchurExArgs g, const typename Mf
         buf ^= 1;
     }
     if (!work) return;
+    if (SPLIT) {
+        double *dst = kpart + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 32 * 512 + threadIdx.x;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dst[((x * 4 + y) * 4 + v) * 512] = (double)acc[x][y][v];
+        return;
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) syrk_put<K, F32>(g, It, Jt, R0, C0, gq, r, x, y, v, (double)acc[x][y][v], first);
+}
+
+// Sums the nsplit partial tiles of k_syrk_v in split order and writes S;
+// the same thread layout (and output positions) as k_syrk_v.
+template <int K, bool F32>
+__global__ __launch_bounds__(512) void k_syrk_reduce(SchurExArgs g, const double *kpart, int nsplit, int first) {
+    int64_t It, Jt;
+    tri_pair(blockIdx.x, It, Jt);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63, gq = lane >> 4, r = lane & 15;
+    const int R0 = (wave >> 1) * 32, C0 = (wave & 1) * 64;
+    if (It == Jt && R0 + 32 <= C0) return;
+    const double *src = kpart + (int64_t)blockIdx.x * 32 * 512 + threadIdx.x;
+    const int64_t sstride = (int64_t)gridDim.x * 32 * 512;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = It * TW + R0 + 16 * x + r, cl = Jt * TW + C0 + 16 * y + M::drow(gq, v);
-                if (row < N && cl < N) {
-                    double *dst = g.S + cl * g.ldS + row;
-                    const double sum = (double)acc[x][y][v];
-                    if (first) {
-                        const int a = (int)(row / g.m), b = (int)(cl / g.m);
-                        const int64_t j = row - a * g.m, l = cl - b * g.m;
-                        double val = -sum;
-                        if (j == l) {
-                            val += g.GX[a * K + b];
-                            if (a == b) val += g.rho + g.s[(int64_t)a * g.ldY + j] / g.Y[(int64_t)a * g.ldY + j];
-                        }
-                        *dst = val;
-                    } else {
-                        *dst -= sum;
-                    }
-                }
+                const int q = (x * 4 + y) * 4 + v;
+                double sum = src[q * 512];
+                for (int s = 1; s < nsplit; ++s) sum += src[s * sstride + q * 512];
+                syrk_put<K, F32>(g, It, Jt, R0, C0, gq, r, x, y, v, sum, first);
             }
 }
 
@@ -1126,12 +1177,31 @@ hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Row splits per tile for the exact-Hessian rank update: the count s <= 12
+// that minimises the per-CU share ceil(tiles s / 256) / s of whole tiles (plus
+// a small charge per split for the partial tiles), within the capacity.
+static int syrk_splits(int64_t tiles, int64_t cap) {
+    int best = 1;
+    double bc = 1e300;
+    for (int s = 1; s <= 12; ++s) {
+        if (s > 1 && (double)s * (double)tiles * 32.0 * 512.0 > (double)cap) break;
+        const double c = (double)((tiles * s + 255) / 256) / s + 0.004 * s;
+        if (c < bc - 1e-12) {
+            bc = c;
+            best = s;
+        }
+    }
+    return best;
+}
+
 hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t ldV, int64_t slab, bool f32,
-                                   hipStream_t st) {
+                                   double *kpart, int64_t kpart_cap, hipStream_t st) {
     const int64_t nk = g.n * K;
     if (slab < 32 || slab > 65535 || ldV < (int64_t)g.NT * 64 || ldV % 64 != 0) return hipErrorInvalidValue;
     const int64_t T2 = (g.NT + 1) / 2;   // 128-wide tiles
-    const dim3 grid((unsigned)(T2 * (T2 + 1) / 2));
+    const int64_t tiles = T2 * (T2 + 1) / 2;
+    const int ns = kpart ? syrk_splits(tiles, kpart_cap) : 1;
+    const dim3 grid((unsigned)tiles, (unsigned)ns);
     for (int64_t k0 = 0; k0 < nk; k0 += slab) {
         const int64_t k1 = std::min(nk, k0 + slab);
         const int64_t cbm = (g.m + 255) / 256;
@@ -1141,13 +1211,27 @@ hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t
         if (f32) {
             float *Vf = (float *)V;
             DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_vgen<KK, float>), gv, dim3(256), 0, st, g, k0, k1, Vf, ldV));
-            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, true>), grid, dim3(512), 0, st, g, (const float *)Vf, ldV,
-                                                 k1 - k0, first));
+            if (ns > 1) {
+                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, true, true>), grid, dim3(512), 0, st, g,
+                                                     (const float *)Vf, ldV, k1 - k0, first, ns, kpart));
+                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_reduce<KK, true>), dim3((unsigned)tiles), dim3(512), 0, st,
+                                                     g, (const double *)kpart, ns, first));
+            } else {
+                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, true, false>), grid, dim3(512), 0, st, g,
+                                                     (const float *)Vf, ldV, k1 - k0, first, 1, (double *)nullptr));
+            }
         } else {
             double *Vd = (double *)V;
             DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_vgen<KK, double>), gv, dim3(256), 0, st, g, k0, k1, Vd, ldV));
-            DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, false>), grid, dim3(512), 0, st, g, (const double *)Vd,
-                                                 ldV, k1 - k0, first));
+            if (ns > 1) {
+                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, false, true>), grid, dim3(512), 0, st, g,
+                                                     (const double *)Vd, ldV, k1 - k0, first, ns, kpart));
+                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_reduce<KK, false>), dim3((unsigned)tiles), dim3(512), 0, st,
+                                                     g, (const double *)kpart, ns, first));
+            } else {
+                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, false, false>), grid, dim3(512), 0, st, g,
+                                                     (const double *)Vd, ldV, k1 - k0, first, 1, (double *)nullptr));
+            }
         }
     }
     return hipGetLastError();

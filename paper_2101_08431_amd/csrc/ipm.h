@@ -56,6 +56,8 @@ struct IpmState {
     double *Vex = nullptr;                     // [vrows][ldS] rows of the exact-Hessian factor V
     int64_t vrows = 0;
     IpmScal *hsc = nullptr;                    // pinned host copy of the scalar block (owner: the context)
+    double *kpart = nullptr;                   // partial tiles of the split exact-Hessian rank update
+    int64_t kpart_cap = 0;                     // its capacity in doubles
     unsigned *flags = nullptr;                 // [3][ldS/64] hand-over flags: factor, forward, backward solve
     unsigned epoch = 0;                        // last flag value used
     bool flags_ready = false;

@@ -898,8 +898,8 @@ static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct IpmLayout {
     size_t r, s, dx, dy, dr, ds, gx, gy, V, tX, tY, Lq, Linv, Rrow, Z, S, vec, vec2, XX, Dinv, spart, flags, part, fpart,
-        sc, rhs0, dacc, Top, Hop, opart, Vex, total;
-    int64_t vrows;
+        sc, rhs0, dacc, Top, Hop, opart, Vex, kpart, total;
+    int64_t vrows, kpart_cap;
     int64_t ldX, ldY, ldS;
     int P;
 };
@@ -967,6 +967,11 @@ static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     L.opart = take((size_t)OPS * K * L.ldY * 8);
     L.vrows = vex_rows(n, K, L.ldS);
     L.Vex = take((size_t)L.vrows * L.ldS * 8);
+    // partial tiles of the exact-Hessian rank update split over rows (up to
+    // 12 splits when its 128 x 128 tiles are fewer than the 256 CUs)
+    const int64_t T2 = (NT + 1) / 2, tiles = T2 * (T2 + 1) / 2;
+    L.kpart_cap = tiles < 256 ? 12 * tiles * 32 * 512 : 0;
+    L.kpart = take(L.kpart_cap > 0 ? (size_t)L.kpart_cap * 8 : 256);
     L.total = off;
     return L;
 }
@@ -1000,6 +1005,8 @@ nmf_status ipm_bind(IpmState &s, uint8_t *base, int64_t n, int64_t m_cap, int K)
     s.opart = (double *)(base + L.opart);
     s.Vex = (double *)(base + L.Vex);
     s.vrows = L.vrows;
+    s.kpart = L.kpart_cap > 0 ? (double *)(base + L.kpart) : nullptr;
+    s.kpart_cap = L.kpart_cap;
     s.bound = true;
     return NMF_OK;
 }
@@ -1243,7 +1250,8 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
             g.s = c.s.s;
             g.Y = p.Y;
             g.rho = rho;
-            HCK(launch_schur_exact_rows(K, g, c.s.Vex, c.s.ldS, c.s.vrows, c.s.mixed != 0, c.st));
+            HCK(launch_schur_exact_rows(K, g, c.s.Vex, c.s.ldS, c.s.vrows, c.s.mixed != 0, c.s.kpart, c.s.kpart_cap,
+                                        c.st));
         } else {
             HCK(launch_xx(K, p.X, p.ldX, p.n, c.s.XX, c.st));
             SchurArgs g;
