@@ -257,7 +257,7 @@ def ipm_section(name="pdf_3000x500_k5", seed=1, iters=10, sweeps=300, mixed=0):
     if cnt[1]:
         # the FP32 form runs on FP32 matrix cores (157.3 TFLOP/s dense)
         pk = 157.3 if mixed else FP64_PEAK_TFS
-        out["roofline"]["exact_schur"] = {"kernel": "k_vgen + k_syrk_v (+ k_linv, k_residual_rows)", "bound": "mfma",
+        out["roofline"]["exact_schur"] = {"kernel": "k_vgen + k_syrk_v (+ k_syrk_reduce, k_linv, k_residual_rows)", "bound": "mfma",
                                           "dtype": "f32" if mixed else "f64",
                                           "achieved": tfs(ex_flop, ms[1]), "peak": pk,
                                           "unit": "TFLOP/s", "frac": (tfs(ex_flop, ms[1]) or 0.0) / pk}

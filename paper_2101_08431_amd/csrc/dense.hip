@@ -483,7 +483,9 @@ __global__ __launch_bounds__(512) void k_syrk_v(SchurExArgs g, const typename Mf
 }
 
 // Sums the nsplit partial tiles of k_syrk_v in split order and writes S;
-// the same thread layout (and output positions) as k_syrk_v.
+// the same thread layout (and output positions) as k_syrk_v.  Block
+// (tile, qg) handles the entries q = 4 qg .. 4 qg + 3 of its threads, so the
+// partials are read by many blocks at once.
 template <int K, bool F32>
 __global__ __launch_bounds__(512) void k_syrk_reduce(SchurExArgs g, const double *kpart, int nsplit, int first) {
     int64_t It, Jt;
@@ -494,17 +496,22 @@ __global__ __launch_bounds__(512) void k_syrk_reduce(SchurExArgs g, const double
     if (It == Jt && R0 + 32 <= C0) return;
     const double *src = kpart + (int64_t)blockIdx.x * 32 * 512 + threadIdx.x;
     const int64_t sstride = (int64_t)gridDim.x * 32 * 512;
+    const int q0 = (int)blockIdx.y * 4;
+    double sum[4];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int u = 0; u < 4; ++u) sum[u] = src[(q0 + u) * 512];
+    for (int s = 1; s < nsplit; ++s) {
+        double t[4];
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int u = 0; u < 4; ++u) t[u] = src[s * sstride + (q0 + u) * 512];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int q = (x * 4 + y) * 4 + v;
-                double sum = src[q * 512];
-                for (int s = 1; s < nsplit; ++s) sum += src[s * sstride + q * 512];
-                syrk_put<K, F32>(g, It, Jt, R0, C0, gq, r, x, y, v, sum, first);
-            }
+        for (int u = 0; u < 4; ++u) sum[u] += t[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u, x = q >> 4, y = (q >> 2) & 3, v = q & 3;
+        syrk_put<K, F32>(g, It, Jt, R0, C0, gq, r, x, y, v, sum[u], first);
+    }
 }
 
 // Linv[i][p][a] = (L_i^-1)[p][a], one row i per thread.
@@ -1214,7 +1221,7 @@ hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t
             if (ns > 1) {
                 DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, true, true>), grid, dim3(512), 0, st, g,
                                                      (const float *)Vf, ldV, k1 - k0, first, ns, kpart));
-                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_reduce<KK, true>), dim3((unsigned)tiles), dim3(512), 0, st,
+                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_reduce<KK, true>), dim3((unsigned)tiles, 8), dim3(512), 0, st,
                                                      g, (const double *)kpart, ns, first));
             } else {
                 DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, true, false>), grid, dim3(512), 0, st, g,
@@ -1226,7 +1233,7 @@ hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t
             if (ns > 1) {
                 DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, false, true>), grid, dim3(512), 0, st, g,
                                                      (const double *)Vd, ldV, k1 - k0, first, ns, kpart));
-                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_reduce<KK, false>), dim3((unsigned)tiles), dim3(512), 0, st,
+                DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_reduce<KK, false>), dim3((unsigned)tiles, 8), dim3(512), 0, st,
                                                      g, (const double *)kpart, ns, first));
             } else {
                 DENSE_K_SWITCH(K, hipLaunchKernelGGL((k_syrk_v<KK, false, false>), grid, dim3(512), 0, st, g,
