@@ -316,10 +316,10 @@ template <> struct MfmaT<true> {
 // V[k - k0][(a, j)] = X_ia Z_i[p][j] + (L_i^-1)[p][a] R_ij for k = i*K + p,
 // columns in component-major order (a*m + j), zero from N = m K to ldV;
 // rounded to FP32 for the mixed-precision form.
-// Block x < K * cbm covers columns j of component a = x / cbm (256 per
-// block, cbm = ceil(m / 256)); the blocks after them zero the padding
-// columns [N, ldV).  Each block writes VGEN_ROWS consecutive rows (few,
-// larger blocks: the dispatch rate of tiny blocks, not HBM, bounded the
+// Block x < cbm covers columns j = 256 x + t of every component a (Z_i[p][j]
+// and R_ij loaded once for the K entries); the blocks after them zero the
+// padding columns [N, ldV).  Each block writes VGEN_ROWS consecutive rows
+// (few, larger blocks: the dispatch rate of tiny blocks, not HBM, bounded a
 // one-row form).
 constexpr int VGEN_ROWS = 8;
 template <int K, typename E>
@@ -329,36 +329,26 @@ __global__ __launch_bounds__(256) void k_vgen(SchurExArgs g, int64_t k0, int64_t
     const int bx = (int)blockIdx.x;
     const int64_t kb = k0 + (int64_t)blockIdx.y * VGEN_ROWS;
     const int64_t ke = min(k1, kb + VGEN_ROWS);
-    if (bx < K * cbm) {
-        const int a = bx / cbm;
-        const int64_t j = (int64_t)(bx - a * cbm) * 256 + threadIdx.x;
+    if (bx < cbm) {
+        const int64_t j = (int64_t)bx * 256 + threadIdx.x;
         if (j >= g.m) return;
         for (int64_t k = kb; k < ke; ++k) {
             const int64_t i = k / K;
             const int p = (int)(k - i * K);
-            const double *zr = g.Z + (i * zpad(K) + p) * g.ldY;
-            const double *rr = g.R + i * g.ldY;
+            const double z = g.Z[(i * zpad(K) + p) * g.ldY + j];
+            const double rv = g.R[i * g.ldY + j];
             const double *li = g.Linv + (i * K + p) * K;
-            V[(k - k0) * ldV + (int64_t)a * g.m + j] =
-                (E)fma(g.X[(int64_t)a * g.ldX + i], zr[j], li[a] * rr[j]);
+            E *vr = V + (k - k0) * ldV + j;
+#pragma unroll
+            for (int a = 0; a < K; ++a) vr[(int64_t)a * g.m] = (E)fma(g.X[(int64_t)a * g.ldX + i], z, li[a] * rv);
         }
     } else {
-        const int64_t c = N + (int64_t)(bx - K * cbm) * 256 + threadIdx.x;
+        const int64_t c = N + (int64_t)(bx - cbm) * 256 + threadIdx.x;
         if (c >= ldV) return;
         for (int64_t k = kb; k < ke; ++k) V[(k - k0) * ldV + c] = (E)0.0;
     }
 }
 
-// S (tile (I, J) of 128 x 128, I >= J) minus the sum over `rows` rows k of
-// V of V[k][rows I] V[k][cols J] on matrix cores (FP64, or FP32 for the
-// mixed-precision form), V read from memory (written once by k_vgen).  512
-// threads: wave w owns rows 32 (w / 2) and columns 64 (w % 2) of the tile
-// (2 x 4 blocks of 16 x 16).  Chunks of 16 rows of V are staged in LDS with
-// 16-byte loads, the next chunk loaded while the current one is multiplied.
-// 128-wide tiles read each V element half as often as 64-wide ones (16
-// flop/byte in FP64).  On a diagonal tile the waves wholly above the diagonal
-// skip the products (their entries are never read).  first: S = Q2bar - sum;
-// otherwise S -= sum (later slabs of rows).
 // Entry (x, y, v) of the lane's output blocks, summed over the rows: written
 // into S (first: S = Q2bar - sum, else S -= sum).
 template <int K, bool F32>
@@ -1212,7 +1202,7 @@ hipError_t launch_schur_exact_rows(int K, const SchurExArgs &g, void *V, int64_t
     for (int64_t k0 = 0; k0 < nk; k0 += slab) {
         const int64_t k1 = std::min(nk, k0 + slab);
         const int64_t cbm = (g.m + 255) / 256;
-        const dim3 gv((unsigned)(K * cbm + (ldV - g.m * K + 255) / 256),
+        const dim3 gv((unsigned)(cbm + (ldV - g.m * K + 255) / 256),
                       (unsigned)((k1 - k0 + VGEN_ROWS - 1) / VGEN_ROWS));
         const int first = k0 == 0 ? 1 : 0;
         if (f32) {
