@@ -100,6 +100,29 @@ def test_first_iteration_across_ranks_matches_oracle(orc, k):
     assert rel(Rg, res.r) <= 1e-8 and rel(Sg.T, res.s) <= 1e-8
 
 
+def test_exact_hessian_slabs_and_split_rank_update_match_oracle(orc):
+    # n k = 70000 rows of V: two slabs of at most 65535 rows; mk = 300: six
+    # 128 x 128 tiles, so the rank update splits the rows of each slab over
+    # several blocks per tile.  sigma_c = 1 turns the exact Hessian (eq. (27))
+    # on at the first mu update, so iterations 4-6 take exact steps.
+    spec = dict(kind="pdf", n=14000, m=60, k=5, sigma=1e-3, sigma_relative=True)
+    M, X, Yt = start_point(orc, spec, 2, sweeps=30)
+    print("case exact-Hessian slabs + split rank update 14000x60x5", flush=True)
+    ctx = gpu_ctx(M, X, Yt, eps_tol=1e-10, sigma_c=1.0)
+    _, rep = ctx.ipm_step(6)
+    Xg, Yg = ctx.factors()
+    Rg, Sg = ctx.duals()
+    ctx.close()
+    X1, Y1, r1, s1, mu1, rho1 = orc.transition(M, X, Yt, 1e-10)
+    res = orc.ipm(M, X1, Y1, r1, s1, mu1, rho1, orc.IPMOptions(eps_tol=1e-10, max_inner=6, sigma_c=1.0))
+    assert res.inner == 6 and res.exact_steps == 3
+    print(f"exact steps gpu {rep['exact_steps']} oracle {res.exact_steps}; agreement: X {rel(Xg, res.X):.2e} "
+          f"Y {rel(Yg.T, res.Yt):.2e} R {rel(Rg, res.r):.2e} S {rel(Sg.T, res.s):.2e}", flush=True)
+    assert rep["exact_steps"] == res.exact_steps
+    assert rel(Xg, res.X) <= 1e-8 and rel(Yg.T, res.Yt) <= 1e-8
+    assert rel(Rg, res.r) <= 1e-8 and rel(Sg.T, res.s) <= 1e-8
+
+
 @pytest.mark.parametrize("seed", [0, 1, 4])
 def test_full_solve_200x50x3_matches_oracle(orc, seed):
     M, X, Yt = start_point(orc, "pdf_200x50_k3", seed)
