@@ -42,11 +42,11 @@ namespace nmfk {
 constexpr int PRS = KMAX * KMAX;   // stride of block records in `part`
 // Slots of the scalar block's `out`: the direction's slope and step limits,
 // the line-search quartic and first barrier batch, the Armijo choice made on
-// the device ([0] accepted, [1] a1, [2] a2, [3] backtracks) and the KKT sums
-// of the point it leads to.
+// the device ([0] accepted, [1] a1, [2] a2, [3] backtracks), the KKT sums
+// of the point it leads to, and the predictor's complementarity sum.
 constexpr int OUT_DIR = 0, OUT_QUART = 8, OUT_BAR = 16;
-constexpr int OUT_SEL = OUT_BAR + NTRIAL, OUT_KKT = OUT_SEL + 4;
-static_assert(OUT_KKT + 4 <= 4 * PARTW, "the finish outputs fit the scalar block");
+constexpr int OUT_SEL = OUT_BAR + NTRIAL, OUT_KKT = OUT_SEL + 4, OUT_AFF = OUT_KKT + 4;
+static_assert(OUT_AFF + 1 <= 4 * PARTW, "the finish outputs fit the scalar block");
 constexpr int CB = 64;             // dense Cholesky / triangular-solve tile
 constexpr int TJ = 16;             // Schur tile: 16 x 16 (j, l) pairs
 constexpr int ZRB = 8;             // rows per block of the Z kernel
@@ -800,8 +800,15 @@ __global__ void k_armijo(IpmScal *sc, double mu, double eta, int maxb, int forme
 
 // Predictor probe, eq. (8): [0] sum (v + a1 d)(dual + a2 ddual).
 template <int K>
-__global__ __launch_bounds__(NTHR) void k_muaff(AnlsParams p, IpmArgs ia, double a1, double a2, FinArgs fa) {
+// adev != nullptr: the step limits are read from the device (adev[0], adev[1]
+// capped at 1, as the host caps them).
+__global__ __launch_bounds__(NTHR) void k_muaff(AnlsParams p, IpmArgs ia, double a1, double a2, const double *adev,
+                                                FinArgs fa) {
     __shared__ double lds[NTHR];
+    if (adev) {
+        a1 = adev[0] < 1.0 ? adev[0] : 1.0;
+        a2 = adev[1] < 1.0 ? adev[1] : 1.0;
+    }
     const Side sd = side_of<K>(p, ia, true);
     const double *dd = (int)blockIdx.x < p.Bx ? ia.dr : ia.ds;
     double acc = 0.0;
@@ -1544,21 +1551,25 @@ nmf_status mu_update(Ctx &c) {
     IpmState &s = c.s;
     const AnlsParams &p = c.p;
     Dir d;
-    nmf_status st = direction(c, 0.0, false, 1.0, d);
+    d.ok = false;
+    // the predictor direction and its complementarity sum, read back together
+    nmf_status st = direction(c, 0.0, false, 1.0, d, true);
     if (st != NMF_OK) return st;
-    if (!d.ok) {
+    IPM_KS(c.K, hipLaunchKernelGGL(k_muaff<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, 0.0, 0.0,
+                                   (const double *)(s.sc->out + OUT_DIR + 1),
+                                   fin(c, s.part, PRS, p.Bx + p.By, 1, 0u, s.sc->out + OUT_AFF)));
+    HCK(hipGetLastError());
+    IpmScal hs;
+    st = read_tail(c, hs);
+    if (st != NMF_OK) return st;
+    if (d.formed && hs.chol_fail) {
+        s.S_gn_valid = false;
         s.err = "Cholesky factorisation of the predictor Schur matrix failed";
         return NMF_ESINGULAR;
     }
-    IPM_KS(c.K, hipLaunchKernelGGL(k_muaff<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, d.a1, d.a2,
-                                   fin(c, s.part, PRS, p.Bx + p.By, 1, 0u, s.sc->out)));
-    HCK(hipGetLastError());
-    double h[1];
-    st = read_out(c, h, 1);
-    if (st != NMF_OK) return st;
     const double Nn = (double)(p.n + p.m) * c.K;
     const double avg = s.SR / Nn;   // current average complementarity
-    const double mu_aff = h[0] / Nn;
+    const double mu_aff = hs.out[OUT_AFF] / Nn;
     // mu_aff is a complementarity of points in the closed orthant, so it is
     // >= 0; the step to the boundary (tau = 1) can leave a rounding residue
     // below 0, which must not turn sigma (and mu) negative.
