@@ -1214,14 +1214,13 @@ struct Dir {
     bool formed = false;   // S was formed and factored for this direction (its failure flag is pending)
 };
 
-// Slots of IpmScal::out for the scalars of one inner iteration, read in one
-// copy: the direction's (slope, step limits), the line search's quartic
-// coefficients and the first batch of barrier trials.
-
 // Newton direction of eq. (12) at the current point with barrier parameter
 // mu (0 for the predictor) and the Hessian eq. (26) (exact = false) or eq.
-// (27) (exact = true).  Leaves dx, dy, dr, ds and the step-rule quantities.
-nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool defer = false) {
+// (27) (exact = true), enqueued without synchronising.  Leaves dx, dy, dr, ds,
+// the slope and step limits in out[OUT_DIR..] and, when S was factored, the
+// factorisation flag; d.formed says whether it was.  The caller reads them in
+// its own round trip.
+nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d) {
     const AnlsParams &p = c.p;
     const int K = c.K;
     const int64_t N = p.m * K;
@@ -1352,34 +1351,12 @@ nmf_status direction(Ctx &c, double mu, bool exact, double tau, Dir &d, bool def
                                      p.By, fin(c, c.s.part, PRS, p.By + p.Bx, 3, 0x6u, c.s.sc->out + OUT_DIR)));
     }
     HCK(hipGetLastError());
-    if (defer) {
-        // the caller reads the scalars and the failure flag with the line
-        // search's (probe())
-        d.formed = formed;
-        return NMF_OK;
-    }
-    IpmScal hs;
-    st = read_tail(c, hs);
-    if (st != NMF_OK) return st;
-    const double *h = hs.out + OUT_DIR;
-    if (formed && hs.chol_fail) {
-        c.s.S_gn_valid = false;
-        d.ok = false;
-        return NMF_OK;
-    }
-    d.ok = true;
-    d.slope = h[0];
-    d.a1 = h[1] < 1.0 ? h[1] : 1.0;
-    d.a2 = h[2] < 1.0 ? h[2] : 1.0;
+    d.formed = formed;
     return NMF_OK;
 }
 
-// Armijo backtracking (eq. (13)) on the closed-form quartic plus barrier sums.
-// Returns the accepted step in *al.
 // Enqueues the line search's quartic (k_ls_quartic) and its first batch of
-// NTRIAL barrier trials from the deferred direction's step limit, then reads
-// the direction's scalars, its factorisation flag, the quartic and the trials
-// in one host round trip.
+// NTRIAL barrier trials from the direction's step limit (read on the device).
 nmf_status probe_enqueue(Ctx &c) {
     const AnlsParams &p = c.p;
     double *lspart = c.s.fpart;   // reused: Tn*Sx records of 8
@@ -1489,7 +1466,7 @@ nmf_status inner_iteration(Ctx &c) {
     nmf_status st;
     double q[6], bar[NTRIAL];
     if (s.flag == 1 && c.o.exact_hessian_switch) {
-        st = direction(c, mu, true, c.o.tau, d, true);
+        st = direction(c, mu, true, c.o.tau, d);
         if (st != NMF_OK) return st;
         st = probe(c, d, q, bar);
         if (st != NMF_OK) return st;
@@ -1504,7 +1481,7 @@ nmf_status inner_iteration(Ctx &c) {
     if (!have) {
         d = Dir();
         d.ok = false;
-        st = direction(c, mu, false, c.o.tau, d, true);
+        st = direction(c, mu, false, c.o.tau, d);
         if (st != NMF_OK) return st;
         // The line-search inputs, the first Armijo batch, the update and the
         // KKT sums of the new point are enqueued together and read back in
@@ -1553,7 +1530,7 @@ nmf_status mu_update(Ctx &c) {
     Dir d;
     d.ok = false;
     // the predictor direction and its complementarity sum, read back together
-    nmf_status st = direction(c, 0.0, false, 1.0, d, true);
+    nmf_status st = direction(c, 0.0, false, 1.0, d);
     if (st != NMF_OK) return st;
     IPM_KS(c.K, hipLaunchKernelGGL(k_muaff<KK>, dim3(p.Bx + p.By), dim3(NTHR), 0, c.st, p, c.ia, 0.0, 0.0,
                                    (const double *)(s.sc->out + OUT_DIR + 1),
