@@ -89,6 +89,9 @@ hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st);
 // The exact-Hessian Schur complement with V written out (k_vgen) in slabs of
 // `slab` rows into V ([slab][ldV] doubles, or floats when f32; ldV >= NT*64, a
 // multiple of 64) and summed by a matrix-core rank update per slab (k_syrk_v).
+// Row splits per 128 x 128 tile of the exact-Hessian rank update for `tiles`
+// tiles, within a partial-tile capacity of `cap` doubles (1: no split).
+int syrk_splits(int64_t tiles, int64_t cap);
 // kpart (capacity kpart_cap doubles, may be null): partial tiles when the rows
 // of each slab are split over several blocks per tile, which the launcher does
 // when the 128 x 128 tiles are too few to fill the chip evenly.

@@ -1177,7 +1177,7 @@ hipError_t launch_schur_gn(int K, const SchurArgs &g, hipStream_t st) {
 // Row splits per tile for the exact-Hessian rank update: the count s <= 12
 // that minimises the per-CU share ceil(tiles s / 256) / s of whole tiles (plus
 // a small charge per split for the partial tiles), within the capacity.
-static int syrk_splits(int64_t tiles, int64_t cap) {
+int syrk_splits(int64_t tiles, int64_t cap) {
     int best = 1;
     double bc = 1e300;
     for (int s = 1; s <= 12; ++s) {

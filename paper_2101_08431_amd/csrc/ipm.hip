@@ -974,10 +974,12 @@ static IpmLayout ipm_layout(int64_t n, int64_t m_cap, int K) {
     L.opart = take((size_t)OPS * K * L.ldY * 8);
     L.vrows = vex_rows(n, K, L.ldS);
     L.Vex = take((size_t)L.vrows * L.ldS * 8);
-    // partial tiles of the exact-Hessian rank update split over rows (up to
-    // 12 splits when its 128 x 128 tiles are fewer than the 256 CUs)
+    // partial tiles of the exact-Hessian rank update split over rows, sized
+    // for the split count chosen at this capacity (fewer columns give fewer
+    // tiles, whose chosen splits fit the same space)
     const int64_t T2 = (NT + 1) / 2, tiles = T2 * (T2 + 1) / 2;
-    L.kpart_cap = tiles < 256 ? 12 * tiles * 32 * 512 : 0;
+    const int ns = tiles < 256 ? syrk_splits(tiles, INT64_MAX) : 1;
+    L.kpart_cap = ns > 1 ? (int64_t)ns * tiles * 32 * 512 : 0;
     L.kpart = take(L.kpart_cap > 0 ? (size_t)L.kpart_cap * 8 : 256);
     L.total = off;
     return L;
